@@ -1,0 +1,201 @@
+"""ctypes wrapper of the FP64 CPU oracle (fvlbm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+benchmark's CPU-baseline leg.  The product path never imports this module.
+The wrapper only marshals arrays; every step of the method is in the C file.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fvlbm_oracle.c")
+_LIB = os.path.join(_HERE, "libfvlbm_oracle.so")
+MAXF = 8
+Q = 9
+SCHEMES = {"euler": 0, "rk4": 1, "ab2": 2}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+        ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+        L.orc_create.restype = C.c_void_p
+        L.orc_create.argtypes = [C.c_int, dp, C.c_int, ip, ip, C.c_int, ip, ip, C.c_int, ip, ip, dp, dp,
+                                 C.c_int, ip, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                 C.c_int, C.c_char_p, C.c_int]
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_n_cells.argtypes = [C.c_void_p]; L.orc_n_cells.restype = C.c_int
+        L.orc_dt.argtypes = [C.c_void_p]; L.orc_dt.restype = C.c_double
+        L.orc_steps.argtypes = [C.c_void_p]; L.orc_steps.restype = C.c_long
+        L.orc_feq.argtypes = [C.c_double, C.c_double, C.c_double, dp]
+        L.orc_moments.argtypes = [dp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_lattice.argtypes = [dp, dp, dp]
+        L.orc_geometry.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, ip]
+        L.orc_faces.argtypes = [C.c_void_p, ip, ip, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_lsq_gradient.argtypes = [C.c_void_p, dp, dp, dp]
+        L.orc_rhs.argtypes = [C.c_void_p, dp, dp]
+        L.orc_face_values.argtypes = [C.c_void_p, dp, dp]
+        L.orc_init.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double]
+        L.orc_set_f.argtypes = [C.c_void_p, dp]
+        L.orc_get_f.argtypes = [C.c_void_p, dp]
+        L.orc_step.argtypes = [C.c_void_p, C.c_long]
+        L.orc_macros.argtypes = [C.c_void_p, dp, dp]
+        L.orc_mass.argtypes = [C.c_void_p]; L.orc_mass.restype = C.c_double
+        L.orc_residual.argtypes = [C.c_int, dp, dp]; L.orc_residual.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def feq(rho: float, ux: float, uy: float) -> np.ndarray:
+    out = np.zeros(Q)
+    lib().orc_feq(float(rho), float(ux), float(uy), out)
+    return out
+
+
+def moments(f) -> tuple:
+    r, x, y = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_moments(np.ascontiguousarray(f, dtype=np.float64), C.byref(r), C.byref(x), C.byref(y))
+    return r.value, x.value, y.value
+
+
+def lattice():
+    ex, ey, w = np.zeros(Q), np.zeros(Q), np.zeros(Q)
+    lib().orc_lattice(ex, ey, w)
+    return ex, ey, w
+
+
+def residual(u, u_old) -> float:
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    u_old = np.ascontiguousarray(u_old, dtype=np.float64).reshape(-1)
+    return lib().orc_residual(u.size // 2, u, u_old)
+
+
+class Oracle:
+    """One FP64 solve on one raw mesh (see paper_1812_00390_amd.meshgen.RawMesh)."""
+
+    def __init__(self, mesh, tau: float, dt: float = 0.0, cfl: float = 0.5, u_ref: float = 0.1,
+                 scheme: str = "euler"):
+        L = lib()
+        g = mesh.groups
+        kinds = np.asarray([x.kind for x in g] or [0], dtype=np.int32)
+        internal = np.asarray([x.internal for x in g] or [0], dtype=np.int32)
+        gu = np.asarray([c for x in g for c in x.u] or [0.0, 0.0], dtype=np.float64)
+        grho = np.asarray([x.rho for x in g] or [0.0], dtype=np.float64)
+        per = np.ascontiguousarray(mesh.periodic, dtype=np.int32).reshape(-1)
+        if per.size == 0:
+            per = np.zeros(2, np.int32)
+        sh = np.ascontiguousarray(mesh.periodic_shift, dtype=np.float64).reshape(-1)
+        if sh.size == 0:
+            sh = np.zeros(2)
+        bfn = np.ascontiguousarray(mesh.bface_nodes, dtype=np.int32).reshape(-1)
+        if bfn.size == 0:
+            bfn = np.zeros(2, np.int32)
+        bfg = np.ascontiguousarray(mesh.bface_group, dtype=np.int32).reshape(-1)
+        if bfg.size == 0:
+            bfg = np.zeros(1, np.int32)
+        err = C.create_string_buffer(256)
+        self._keep = (kinds, internal, gu, grho, per, sh, bfn, bfg)
+        self.h = L.orc_create(mesh.n_nodes, np.ascontiguousarray(mesh.nodes, dtype=np.float64).reshape(-1),
+                              mesh.n_cells, np.ascontiguousarray(mesh.cell_ptr, dtype=np.int32),
+                              np.ascontiguousarray(mesh.cell_nodes, dtype=np.int32),
+                              int(mesh.bface_nodes.shape[0]), bfn, bfg, len(g), kinds, internal, gu, grho,
+                              int(mesh.periodic.shape[0]), per, sh, float(tau), float(dt), float(cfl),
+                              float(u_ref), SCHEMES[scheme], err, 256)
+        if not self.h:
+            raise ValueError("oracle: " + err.value.decode())
+        self.n = L.orc_n_cells(self.h)
+        self.tau = tau
+        self.scheme = scheme
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    @property
+    def dt(self) -> float:
+        return lib().orc_dt(self.h)
+
+    @property
+    def steps(self) -> int:
+        return lib().orc_steps(self.h)
+
+    def init(self, rho0=1.0, u0=(0.0, 0.0), rho=None, u=None):
+        r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+        v = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+        self._init_keep = (r, v)
+        lib().orc_init(self.h, None if r is None else r.ctypes.data, None if v is None else v.ctypes.data,
+                       float(rho0), float(u0[0]), float(u0[1]))
+
+    @property
+    def f(self) -> np.ndarray:
+        out = np.zeros((self.n, Q))
+        lib().orc_get_f(self.h, out)
+        return out
+
+    @f.setter
+    def f(self, value):
+        lib().orc_set_f(self.h, np.ascontiguousarray(value, dtype=np.float64).reshape(self.n, Q))
+
+    def rhs(self, f) -> np.ndarray:
+        out = np.zeros((self.n, Q))
+        lib().orc_rhs(self.h, np.ascontiguousarray(f, dtype=np.float64).reshape(self.n, Q), out)
+        return out
+
+    def face_values(self, f) -> np.ndarray:
+        out = np.zeros((self.n, MAXF, Q))
+        lib().orc_face_values(self.h, np.ascontiguousarray(f, dtype=np.float64).reshape(self.n, Q), out)
+        return out
+
+    def step(self, n: int = 1):
+        lib().orc_step(self.h, int(n))
+
+    def macros(self):
+        rho = np.zeros(self.n); u = np.zeros((self.n, 2))
+        lib().orc_macros(self.h, rho, u)
+        return rho, u
+
+    def mass(self) -> float:
+        return lib().orc_mass(self.h)
+
+    def geometry(self) -> dict:
+        n = self.n
+        a, cx, cy, lx, ly = (np.zeros(n) for _ in range(5))
+        nf = np.zeros(n, np.int32)
+        lib().orc_geometry(self.h, a, cx, cy, lx, ly, nf)
+        return dict(area=a, cx=cx, cy=cy, lx=lx, ly=ly, nf=nf)
+
+    def faces(self) -> dict:
+        s = (self.n, MAXF)
+        nbr, grp = np.zeros(s, np.int32), np.zeros(s, np.int32)
+        fx, fy, nx, ny, ln, stx, sty = (np.zeros(s) for _ in range(7))
+        lib().orc_faces(self.h, nbr, grp, fx, fy, nx, ny, ln, stx, sty)
+        return dict(nbr=nbr, grp=grp, fx=fx, fy=fy, nx=nx, ny=ny, len=ln, stx=stx, sty=sty)
+
+    def lsq_gradient(self, phi, phi_bnd) -> np.ndarray:
+        out = np.zeros((self.n, 2))
+        lib().orc_lsq_gradient(self.h, np.ascontiguousarray(phi, dtype=np.float64),
+                               np.ascontiguousarray(phi_bnd, dtype=np.float64).reshape(self.n, MAXF), out)
+        return out
