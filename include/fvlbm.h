@@ -1,0 +1,185 @@
+/*
+ * fvlbm.h - C ABI of the MI355X (gfx950) cell-centred finite-volume lattice
+ * Boltzmann library (D2Q9, BGK) on 2D unstructured meshes.
+ *
+ * The method is that of Wang, Zhong, Cao and Zhuo, "A simplified finite
+ * volume lattice Boltzmann method ... Part I" (arXiv 1812.00390), Section 2:
+ * per-cell weighted least-squares gradients of the nine distributions
+ * (Eq. 12), second-order upwind face values (Eq. 11), face-flux
+ * accumulation and the BGK source (Eq. 10), forward Euler (Eq. 13), AB2
+ * (Eq. 16) or the four-stage Runge-Kutta scheme (Eq. 17), with the wall,
+ * inlet, outlet and symmetry treatments of Section 2.4 (Eqs. 18-26).
+ *
+ * Conventions
+ *  - Every call returns fvlbm_status (0 = OK, < 0 = error) unless stated.
+ *    No C++ exception crosses this boundary.  fvlbm_last_error() gives a
+ *    thread-local text for the last failing call of the calling thread.
+ *  - Host arrays passed in are read during the call only (copied).
+ *  - hip_stream arguments are hipStream_t values (NULL = the null stream).
+ *    Work is enqueued on that stream; only calls documented as syncing wait.
+ *  - Cell indices are the caller's (input) order everywhere in this API; an
+ *    internal reordering is undone on output.
+ *  - Distributions are exchanged in FP64, [cell][alpha], alpha in the order
+ *    of Eq. 2: e0=(0,0), e1..e4=(1,0),(0,1),(-1,0),(0,-1),
+ *    e5..e8=(1,1),(-1,1),(-1,-1),(1,-1).
+ */
+#ifndef FVLBM_H
+#define FVLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FVLBM_OK = 0,
+    FVLBM_E_ARG = -1,      /* null pointer, size out of range, bad enum value */
+    FVLBM_E_MESH = -2,     /* invalid mesh: non-CCW/inverted cell, open or non-manifold edge, bad periodic pair, singular stencil */
+    FVLBM_E_PARAM = -3,    /* tau <= 0, dt > 2 tau without FVLBM_FLAG_FORCE_DT, bad scheme/storage, buffer too small */
+    FVLBM_E_NOMEM = -4,    /* device allocation failed */
+    FVLBM_E_DEVICE = -5,   /* a HIP runtime call or kernel failed */
+    FVLBM_E_DIVERGED = -6, /* a non-finite density or velocity was found (fvlbm_macros) */
+    FVLBM_E_STATE = -7     /* the solver is in an error state; destroy it */
+} fvlbm_status;
+
+/* Boundary-condition kinds, Section 2.4 (Eqs. 18-26). */
+typedef enum {
+    FVLBM_BC_WALL = 1,     /* Eq. 18: f_P = f_eq(rho_k, u_w) + f_k - f_eq,k; face value f_P for all alpha */
+    FVLBM_BC_INLET = 2,    /* Eq. 19 ghost, Eq. 23 face; rho* = rho_inf (external) or rho_k (internal) */
+    FVLBM_BC_OUTLET = 3,   /* external: Eq. 20 ghost, Eq. 25 face; internal: Eq. 21 ghost, Eq. 24 face */
+    FVLBM_BC_SYMMETRY = 4  /* Eq. 22 ghost (mirrored normal velocity), Eq. 26 face */
+} fvlbm_bc_kind;
+
+typedef struct {
+    int32_t kind;          /* fvlbm_bc_kind */
+    int32_t internal;      /* 0 external flow, 1 internal flow (inlet/outlet only) */
+    double u[2];           /* wall velocity u_w (wall) or free-stream velocity u_inf (inlet/outlet) */
+    double rho;            /* rho_inf (inlet/outlet); ignored for wall/symmetry */
+} fvlbm_bc;
+
+enum { FVLBM_SCHEME_EULER = 0, FVLBM_SCHEME_RK4 = 1, FVLBM_SCHEME_AB2 = 2 };
+enum { FVLBM_STORE_FP32 = 0, FVLBM_STORE_FP32_DEV = 1, FVLBM_STORE_FP16_DEV = 2 };
+enum { FVLBM_REORDER_NONE = 0, FVLBM_REORDER_RCM = 1, FVLBM_REORDER_HILBERT = 2 };
+enum { FVLBM_FLAG_FORCE_DT = 1 };
+
+typedef struct {
+    double tau;            /* relaxation time, tau = nu / cs^2 = 3 nu (Eq. 6); > 0 */
+    double dt;             /* time step; 0 = min(CFL limit of Eq. 14, 2 tau of Eq. 15) */
+    double cfl;            /* CFL number used when dt == 0 */
+    double u_ref;          /* |U|max of Eq. 14, used when dt == 0 */
+    int32_t scheme;        /* FVLBM_SCHEME_* */
+    int32_t storage;       /* FVLBM_STORE_*: f as FP32, h = f - f_eq(rho0, u_dev) as FP32, or h/(w S) as FP16 */
+    double rho0;           /* reference density of the deviation storage (and of Step 0 when no field is given) */
+    double fp16_scale;     /* S of the FP16 deviation storage; 0 = 3 |u_ref| (or 0.3 if u_ref = 0) */
+    int32_t residual_lag;  /* steps between velocity snapshots for the residual (Eq. 32); 0 = 1000 */
+    int32_t flags;         /* FVLBM_FLAG_* */
+    double u_dev[2];       /* deviations are stored from f_eq(rho0, u_dev) (Eq. 3); (0,0) gives f - w rho0.
+                              A free-stream value keeps far-field deviations small (FP16 storage) */
+} fvlbm_params;
+
+typedef struct fvlbm_mesh fvlbm_mesh;        /* opaque; device arrays owned by the library */
+typedef struct fvlbm_solver fvlbm_solver;    /* opaque; state lives in a caller-owned device buffer */
+typedef struct fvlbm_batch fvlbm_batch;      /* opaque; a set of solvers advanced by shared launches */
+
+/*
+ * Build a mesh (Section 2.2): convex polygons with 3 or 4 nodes, CCW.
+ *   xy            [2*n_nodes]  node coordinates
+ *   cell_ptr      [n_cells+1]  CSR offsets into cell_nodes; cell_nodes CCW node ids
+ *   bface_nodes   [2*n_bfaces] node pairs of boundary edges (either order)
+ *   bface_group   [n_bfaces]   index into groups, or -1 for an edge listed in periodic_pairs
+ *   groups        [n_groups]   boundary-condition groups
+ *   periodic_pairs[2*n_periodic] boundary-edge indices (a, b) joined by periodicity
+ *   periodic_shift[2*n_periodic] vector added to positions on b's side to bring them next to a
+ *   reorder       FVLBM_REORDER_*; internal cell order for locality (outputs stay in input order)
+ * Geometry and least-squares coefficients are computed on the device in FP64
+ * (Eq. 12 with w = 1/|x_n - x_i|^2; f at the area centroid) and stored as FP32.
+ * Errors: FVLBM_E_ARG, FVLBM_E_MESH, FVLBM_E_NOMEM, FVLBM_E_DEVICE.  Syncs hip_stream.
+ */
+fvlbm_status fvlbm_create_mesh(int32_t n_nodes, const double *xy, int32_t n_cells,
+                               const int32_t *cell_ptr, const int32_t *cell_nodes,
+                               int32_t n_bfaces, const int32_t *bface_nodes,
+                               const int32_t *bface_group, int32_t n_groups,
+                               const fvlbm_bc *groups, int32_t n_periodic,
+                               const int32_t *periodic_pairs, const double *periodic_shift,
+                               int32_t reorder, void *hip_stream, fvlbm_mesh **out);
+
+/* Mesh facts: out[0] n_cells, out[1] faces per cell slot (3 or 4), out[2] device bytes
+ * of the mesh arrays, out[3] number of boundary-adjacent cells.  Returns FVLBM_OK or FVLBM_E_ARG. */
+fvlbm_status fvlbm_mesh_info(const fvlbm_mesh *mesh, int64_t out[4]);
+
+/* min over cells of A/(Lx+Ly) (Eq. 14's length scale, FP64), or -1 on a null mesh. */
+double fvlbm_mesh_cfl_length(const fvlbm_mesh *mesh);
+
+/* Device bytes a solver needs in its caller-owned state buffer for these params
+ * (distribution buffers for the scheme plus per-cell scratch).  0 on bad arguments. */
+size_t fvlbm_state_bytes(const fvlbm_mesh *mesh, const fvlbm_params *params);
+
+/*
+ * Step 0 (Section 2.5): f = f_eq(rho, u) per cell.  rho0_cells [n_cells] and
+ * u0_cells [2*n_cells] may be NULL for the uniform values params->rho0 and (0,0).
+ * device_buf must hold fvlbm_state_bytes() bytes, 256-byte aligned, and outlive
+ * the solver.  The solver keeps a reference to mesh (destroy solvers first).
+ * Errors: FVLBM_E_ARG, FVLBM_E_PARAM, FVLBM_E_DEVICE.
+ */
+fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const double *rho0_cells,
+                        const double *u0_cells, void *device_buf, size_t buf_bytes,
+                        void *hip_stream, fvlbm_solver **out);
+
+/* Time step actually used (after the Eq. 14/15 rule), or -1 on a null solver. */
+double fvlbm_solver_dt(const fvlbm_solver *s);
+
+/* Steps 1-5 repeated n_steps times (Section 2.5), enqueued on the solver's stream;
+ * does not sync.  Errors: FVLBM_E_ARG (n_steps < 0), FVLBM_E_STATE, FVLBM_E_DEVICE. */
+fvlbm_status fvlbm_step(fvlbm_solver *s, int64_t n_steps);
+
+/*
+ * Step 6: rho [n_cells], u [2*n_cells] (either may be NULL) and
+ * stats [4] = {mass = sum A_i rho_i, velocity residual of Eq. 32 against the
+ * snapshot taken residual_lag steps earlier (or -1 if none yet), time, steps}
+ * (may be NULL).  Reductions run in FP64 on the device.  Syncs the stream.
+ * Returns FVLBM_E_DIVERGED if any rho or u is not finite.
+ */
+fvlbm_status fvlbm_macros(fvlbm_solver *s, double *rho, double *u, double *stats);
+
+/* Copy the distributions out / in (FP64, [cell][alpha], input cell order).  Sync. */
+fvlbm_status fvlbm_get_f(fvlbm_solver *s, double *f);
+fvlbm_status fvlbm_set_f(fvlbm_solver *s, const double *f);
+
+/* One evaluation of RHS (Eq. 10) at the current state, FP64 out, [cell][alpha]. Sync. */
+fvlbm_status fvlbm_rhs(fvlbm_solver *s, double *rhs);
+
+/* Raw checkpoint of the solver state (storage precision).  state_bytes() tells the size. */
+size_t fvlbm_checkpoint_bytes(const fvlbm_solver *s);
+fvlbm_status fvlbm_checkpoint(fvlbm_solver *s, void *host_buf, size_t bytes);
+fvlbm_status fvlbm_restore(fvlbm_solver *s, const void *host_buf, size_t bytes);
+
+void fvlbm_solver_destroy(fvlbm_solver *s);
+void fvlbm_mesh_destroy(fvlbm_mesh *mesh);
+
+/*
+ * Batched solves: several solvers (each with its own mesh, parameters and
+ * state) advanced by shared launches, one work unit per (solver, cell tile).
+ * All solvers must use the same scheme and storage and the same stream.
+ * fvlbm_batch_step() advances every member by n_steps; the launches of one
+ * chunk of steps are captured once into a HIP graph and replayed.
+ * The per-cell arithmetic is the same as fvlbm_step(): a member's result does
+ * not depend on the other members.  Errors: FVLBM_E_ARG, FVLBM_E_PARAM, FVLBM_E_DEVICE.
+ */
+fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_batch **out);
+fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps);
+void fvlbm_batch_destroy(fvlbm_batch *b);
+
+/* Launch schedule (block size in cells, and whether block ids are spread so
+ * that neighbouring tiles share an XCD's L2).  set returns FVLBM_E_ARG for an
+ * unsupported block size (64, 128, 256, 512 are supported). */
+fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap);
+fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap);
+
+const char *fvlbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FVLBM_H */

@@ -1,0 +1,690 @@
+// C ABI of the library: mesh and solver objects, step sequencing for the
+// three integrators, graph replay of step chunks, Step 6 and the FP64
+// reductions, checkpoints, and batched multi-instance stepping.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "fvlbm_internal.h"
+
+using namespace fvlbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+fvlbm_status fail(fvlbm_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int storage_bytes(int storage) { return storage == FVLBM_STORE_FP16_DEV ? 2 : 4; }
+int n_fbufs(int scheme) { return scheme == FVLBM_SCHEME_RK4 ? 3 : 2; }
+
+// RK4 coefficients of Eq. 17, read as f(k+1) = f(0) + beta_(k+1) dt RHS(f(k))
+constexpr double BETA[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
+
+struct Layout {
+    size_t fbuf[3], r32, snap[2], partial, scal, flag, out, total;
+};
+
+Layout layout(int n, int np, const fvlbm_params &p) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t o = off; off = align256(off + b); return o; };
+    size_t fb = (size_t)Q * np * storage_bytes(p.storage);
+    for (int k = 0; k < 3; k++) L.fbuf[k] = k < n_fbufs(p.scheme) ? take(fb) : 0;
+    L.r32 = take((size_t)Q * np * sizeof(float));
+    L.snap[0] = take((size_t)2 * n * sizeof(double));
+    L.snap[1] = take((size_t)2 * n * sizeof(double));
+    L.partial = take((size_t)2 * reduce_blocks(n) * sizeof(double));
+    L.scal = take(8 * sizeof(double));
+    L.flag = take(sizeof(int) * 4);
+    L.out = take((size_t)Q * n * sizeof(double));   // FP64 staging for copy-out (rho,u or f or rhs)
+    L.total = off;
+    return L;
+}
+
+enum Kind { E0 = 0, E1, R1, R2, R3, R4, F0, F1, A0, A1, RH0, RH1, RH2, N_KINDS };
+
+}  // namespace
+
+struct fvlbm_mesh {
+    MeshDev dev;
+    int refs = 0;
+};
+
+struct fvlbm_solver {
+    fvlbm_mesh *mesh = nullptr;
+    fvlbm_params p{};
+    hipStream_t stream = nullptr;
+    double dt = 0;
+    RefDev ref{};
+    char *buf = nullptr;
+    Layout L{};
+    int cur = 0;               // which distribution buffer holds the state (Euler / AB2)
+    int64_t steps = 0;
+    int snap_cur = -1;         // buffer of the newest snapshot, -1 none
+    int64_t snap_step = -1;
+    bool have_prev = false;    // AB2 history valid
+    int lag = 1000;
+    bool failed = false;
+    InstDesc *desc_dev = nullptr;   // [N_KINDS]
+    UnitTable ut;
+    Schedule sched;
+    // graph cache: key (start buffer, steps)
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    ~fvlbm_solver();
+};
+
+struct fvlbm_batch {
+    std::vector<fvlbm_solver *> members;
+    InstDesc *desc_dev = nullptr;     // [N_KINDS][n]
+    UnitTable ut[2];                  // by face-slot count (3, 4)
+    int scheme = 0, storage = 0;
+    hipStream_t stream = nullptr;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    Schedule sched;
+};
+
+namespace {
+
+void free_graphs(std::map<std::pair<int, int>, hipGraphExec_t> &g) {
+    for (auto &kv : g) hipGraphExecDestroy(kv.second);
+    g.clear();
+}
+
+// Build the unit table (instance, first cell) for a list of (instance, n_cells).
+fvlbm_status make_units(const std::vector<std::pair<int, int>> &inst, int block, UnitTable &ut) {
+    std::vector<int2> units;
+    for (auto &pr : inst)
+        for (int c = 0; c < pr.second; c += block) units.push_back(make_int2(pr.first, c));
+    if (ut.units) { hipFree(ut.units); ut.units = nullptr; }
+    ut.n_units = (int)units.size();
+    ut.block = block;
+    if (units.empty()) return FVLBM_OK;
+    if (hipMalloc(&ut.units, units.size() * sizeof(int2)) != hipSuccess) return fail(FVLBM_E_NOMEM, "unit table allocation failed");
+    if (hipMemcpy(ut.units, units.data(), units.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FVLBM_E_DEVICE, "unit table copy failed");
+    return FVLBM_OK;
+}
+
+void *fptr(fvlbm_solver *s, int k) { return s->buf + s->L.fbuf[k]; }
+
+InstDesc base_desc(fvlbm_solver *s) {
+    const MeshDev &m = s->mesh->dev;
+    InstDesc d{};
+    d.nbr = m.nbr; d.cg = m.cg; d.rf = m.rf; d.rj = m.rj; d.gn = m.gn;
+    d.n_cells = m.n_cells; d.np = m.np;
+    d.inv_tau = (float)(1.0 / s->p.tau);
+    d.ref = s->ref;
+    d.n_groups = m.n_groups;
+    for (int g = 0; g < m.n_groups; g++) {
+        const fvlbm_bc &b = m.groups_host[g];
+        d.groups[g].kind = b.kind;
+        d.groups[g].internal = b.internal;
+        d.groups[g].ux = (float)b.u[0];
+        d.groups[g].uy = (float)b.u[1];
+        d.groups[g].drho = (float)(b.rho - (double)s->ref.rho0);
+        d.groups[g].rho = (float)b.rho;
+    }
+    d.rhs_prev = reinterpret_cast<float *>(s->buf + s->L.r32);
+    return d;
+}
+
+// Descriptors of every stage kind for one solver.
+void fill_descs(fvlbm_solver *s, InstDesc out[N_KINDS]) {
+    InstDesc b = base_desc(s);
+    auto set = [&](int k, int src, int base, int dst, double coef, int mode) {
+        out[k] = b;
+        out[k].src = fptr(s, src);
+        out[k].base = fptr(s, base);
+        out[k].dst = dst >= 0 ? fptr(s, dst) : (void *)(s->buf + s->L.r32);
+        out[k].coef = (float)coef;
+        out[k].mode = mode;
+    };
+    const double dt = s->dt;
+    set(E0, 0, 0, 1, dt, 0);
+    set(E1, 1, 1, 0, dt, 0);
+    if (s->p.scheme == FVLBM_SCHEME_RK4) {
+        set(R1, 0, 0, 1, BETA[0] * dt, 0);
+        set(R2, 1, 0, 2, BETA[1] * dt, 0);
+        set(R3, 2, 0, 1, BETA[2] * dt, 0);
+        set(R4, 1, 0, 0, BETA[3] * dt, 0);   // in place on f(0): each cell reads only its own base value
+    } else {
+        out[R1] = out[R2] = out[R3] = out[R4] = out[E0];
+    }
+    set(F0, 0, 0, 1, dt, 1);
+    set(F1, 1, 1, 0, dt, 1);
+    set(A0, 0, 0, 1, dt, 2);
+    set(A1, 1, 1, 0, dt, 2);
+    set(RH0, 0, 0, -1, 0, 3);
+    set(RH1, 1, 1, -1, 0, 3);
+    set(RH2, 2, 2, -1, 0, 3);
+}
+
+// The sequence of stage kinds of one step, given the solver's position.
+void step_kinds(int scheme, int cur, bool have_prev, std::vector<int> &ks) {
+    ks.clear();
+    if (scheme == FVLBM_SCHEME_RK4) { ks = {R1, R2, R3, R4}; return; }
+    if (scheme == FVLBM_SCHEME_EULER) { ks.push_back(cur == 0 ? E0 : E1); return; }
+    if (!have_prev) ks.push_back(cur == 0 ? F0 : F1);
+    else ks.push_back(cur == 0 ? A0 : A1);
+}
+
+void advance_position(int scheme, int &cur, bool &have_prev) {
+    if (scheme != FVLBM_SCHEME_RK4) cur ^= 1;
+    if (scheme == FVLBM_SCHEME_AB2) have_prev = true;
+}
+
+hipError_t take_snapshot(fvlbm_solver *s) {
+    const MeshDev &m = s->mesh->dev;
+    int nxt = s->snap_cur < 0 ? 0 : (s->snap_cur ^ 1);
+    double *snap_new = reinterpret_cast<double *>(s->buf + s->L.snap[nxt]);
+    const double *snap_old = s->snap_cur < 0 ? nullptr : reinterpret_cast<double *>(s->buf + s->L.snap[s->snap_cur]);
+    double *partial = reinterpret_cast<double *>(s->buf + s->L.partial);
+    double *scal = reinterpret_cast<double *>(s->buf + s->L.scal);
+    hipError_t e = launch_snapshot(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref,
+                                   snap_new, snap_old, partial, s->stream);
+    if (e == hipSuccess && snap_old) e = launch_finish_sums(partial, reduce_blocks(m.n_cells), scal, 1, s->stream);
+    s->snap_cur = nxt;
+    s->snap_step = s->steps;
+    return e;
+}
+
+// Build (or fetch) a graph replaying `nsteps` steps starting from buffer `cur`.
+hipGraphExec_t solver_graph(fvlbm_solver *s, int cur, int nsteps) {
+    auto key = std::make_pair(cur, nsteps);
+    auto it = s->graphs.find(key);
+    if (it != s->graphs.end()) return it->second;
+    hipGraph_t g;
+    if (hipGraphCreate(&g, 0) != hipSuccess) return nullptr;
+    std::vector<int> ks;
+    std::vector<std::unique_ptr<void *[]>> argstore;
+    hipGraphNode_t prev = nullptr;
+    int c = cur;
+    bool hp = true;
+    bool ok = true;
+    for (int it2 = 0; it2 < nsteps && ok; it2++) {
+        step_kinds(s->p.scheme, c, hp, ks);
+        for (int k : ks) {
+            argstore.emplace_back(new void *[8]);
+            void **ab = argstore.back().get();
+            ab[0] = new char[64];
+            hipGraphNode_t node;
+            ok = add_stage_node(g, &node, prev ? &prev : nullptr, prev ? 1 : 0, s->desc_dev + k, s->ut,
+                                s->mesh->dev.nf, s->p.storage, s->sched.xcd_remap, ab) == hipSuccess;
+            prev = node;
+            if (!ok) break;
+        }
+        advance_position(s->p.scheme, c, hp);
+    }
+    hipGraphExec_t ex = nullptr;
+    if (ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+    for (auto &a : argstore) delete[] static_cast<char *>(a[0]);
+    hipGraphDestroy(g);
+    if (ex) s->graphs[key] = ex;
+    return ex;
+}
+
+constexpr int GRAPH_CHUNK = 32;
+
+// Enqueue n steps without snapshots.
+fvlbm_status enqueue_steps(fvlbm_solver *s, int64_t n) {
+    std::vector<int> ks;
+    int64_t done = 0;
+    const int nf = s->mesh->dev.nf;
+    while (done < n) {
+        int64_t left = n - done;
+        bool graphable = left >= GRAPH_CHUNK && (s->p.scheme != FVLBM_SCHEME_AB2 || s->have_prev);
+        if (graphable) {
+            hipGraphExec_t ex = solver_graph(s, s->cur, GRAPH_CHUNK);
+            if (!ex) return fail(FVLBM_E_DEVICE, "graph build failed");
+            if (hipGraphLaunch(ex, s->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "graph launch failed");
+            for (int k = 0; k < GRAPH_CHUNK; k++) advance_position(s->p.scheme, s->cur, s->have_prev);
+            done += GRAPH_CHUNK;
+            s->steps += GRAPH_CHUNK;
+            continue;
+        }
+        step_kinds(s->p.scheme, s->cur, s->have_prev, ks);
+        for (int k : ks) {
+            hipError_t e = launch_stage(s->desc_dev + k, s->ut, nf, s->p.storage, s->sched.xcd_remap, s->stream);
+            if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("stage launch failed: ") + hipGetErrorString(e));
+        }
+        advance_position(s->p.scheme, s->cur, s->have_prev);
+        done++;
+        s->steps++;
+    }
+    return FVLBM_OK;
+}
+
+fvlbm_status upload_descs(fvlbm_solver *s) {
+    InstDesc d[N_KINDS];
+    fill_descs(s, d);
+    if (hipMemcpy(s->desc_dev, d, sizeof(d), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FVLBM_E_DEVICE, "descriptor upload failed");
+    return FVLBM_OK;
+}
+
+}  // namespace
+
+fvlbm_solver::~fvlbm_solver() {
+    free_graphs(graphs);
+    if (desc_dev) hipFree(desc_dev);
+    if (ut.units) hipFree(ut.units);
+}
+
+extern "C" {
+
+const char *fvlbm_last_error(void) { return g_err.c_str(); }
+
+fvlbm_status fvlbm_create_mesh(int32_t n_nodes, const double *xy, int32_t n_cells,
+                               const int32_t *cell_ptr, const int32_t *cell_nodes,
+                               int32_t n_bfaces, const int32_t *bface_nodes,
+                               const int32_t *bface_group, int32_t n_groups,
+                               const fvlbm_bc *groups, int32_t n_periodic,
+                               const int32_t *periodic_pairs, const double *periodic_shift,
+                               int32_t reorder, void *hip_stream, fvlbm_mesh **out) {
+    if (!out) return fail(FVLBM_E_ARG, "out is null");
+    *out = nullptr;
+    try {
+        HostTopology topo;
+        std::string err;
+        fvlbm_status st = build_topology(n_nodes, xy, n_cells, cell_ptr, cell_nodes, n_bfaces, bface_nodes,
+                                         bface_group, n_groups, groups, n_periodic, periodic_pairs,
+                                         periodic_shift, reorder, topo, err);
+        if (st != FVLBM_OK) return fail(st, err);
+        auto *m = new fvlbm_mesh();
+        st = build_device_mesh(topo, groups, n_groups, (hipStream_t)hip_stream, m->dev, err);
+        if (st != FVLBM_OK) {
+            if (m->dev.block) hipFree(m->dev.block);
+            delete m;
+            return fail(st, err);
+        }
+        *out = m;
+        return FVLBM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FVLBM_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(FVLBM_E_ARG, "unexpected exception in fvlbm_create_mesh");
+    }
+}
+
+fvlbm_status fvlbm_mesh_info(const fvlbm_mesh *mesh, int64_t out[4]) {
+    if (!mesh || !out) return fail(FVLBM_E_ARG, "null argument");
+    out[0] = mesh->dev.n_cells;
+    out[1] = mesh->dev.nf;
+    out[2] = (int64_t)mesh->dev.bytes;
+    out[3] = mesh->dev.n_boundary_cells;
+    return FVLBM_OK;
+}
+
+double fvlbm_mesh_cfl_length(const fvlbm_mesh *mesh) { return mesh ? mesh->dev.cfl_length : -1.0; }
+
+void fvlbm_mesh_destroy(fvlbm_mesh *mesh) {
+    if (!mesh) return;
+    if (mesh->dev.block) hipFree(mesh->dev.block);
+    delete mesh;
+}
+
+size_t fvlbm_state_bytes(const fvlbm_mesh *mesh, const fvlbm_params *p) {
+    if (!mesh || !p || p->scheme < 0 || p->scheme > 2 || p->storage < 0 || p->storage > 2) return 0;
+    return layout(mesh->dev.n_cells, mesh->dev.np, *p).total;
+}
+
+fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const double *rho0_cells,
+                        const double *u0_cells, void *device_buf, size_t buf_bytes, void *hip_stream,
+                        fvlbm_solver **out) {
+    if (!mesh || !params || !device_buf || !out) return fail(FVLBM_E_ARG, "null argument");
+    *out = nullptr;
+    const fvlbm_params &p = *params;
+    if (!(p.tau > 0)) return fail(FVLBM_E_PARAM, "tau must be positive");
+    if (p.scheme < 0 || p.scheme > 2) return fail(FVLBM_E_PARAM, "unknown scheme");
+    if (p.storage < 0 || p.storage > 2) return fail(FVLBM_E_PARAM, "unknown storage");
+    if (!(p.rho0 > 0)) return fail(FVLBM_E_PARAM, "rho0 must be positive");
+    if (((uintptr_t)device_buf & 255) != 0) return fail(FVLBM_E_ARG, "device buffer must be 256-byte aligned");
+    const MeshDev &m = mesh->dev;
+    Layout L = layout(m.n_cells, m.np, p);
+    if (buf_bytes < L.total) return fail(FVLBM_E_PARAM, "state buffer too small (see fvlbm_state_bytes)");
+    double dt = p.dt;
+    if (dt < 0) return fail(FVLBM_E_PARAM, "dt must be >= 0");
+    if (dt == 0) {
+        if (!(p.cfl > 0)) return fail(FVLBM_E_PARAM, "dt == 0 needs cfl > 0");
+        // Eq. 14 with |e|max = sqrt(2), |U|max = u_ref; Eq. 15 caps at 2 tau
+        dt = p.cfl * m.cfl_length / (std::sqrt(2.0) + std::fabs(p.u_ref));
+        dt = std::min(dt, 2.0 * p.tau);
+    } else if (dt > 2.0 * p.tau && !(p.flags & FVLBM_FLAG_FORCE_DT)) {
+        return fail(FVLBM_E_PARAM, "dt > 2 tau violates the collision limit (Eq. 15)");
+    }
+    auto s = std::make_unique<fvlbm_solver>();
+    s->mesh = mesh;
+    s->p = p;
+    s->stream = (hipStream_t)hip_stream;
+    s->dt = dt;
+    double S = p.fp16_scale > 0 ? p.fp16_scale : (p.u_ref != 0 ? 3.0 * std::fabs(p.u_ref) : 0.3);
+    s->ref = make_ref(p.rho0, p.u_dev[0], p.u_dev[1], S);
+    s->buf = (char *)device_buf;
+    s->L = L;
+    s->lag = p.residual_lag > 0 ? p.residual_lag : 1000;
+    if (hipMalloc(&s->desc_dev, sizeof(InstDesc) * N_KINDS) != hipSuccess) return fail(FVLBM_E_NOMEM, "descriptor allocation failed");
+    fvlbm_status st = make_units({{0, m.n_cells}}, s->sched.block, s->ut);
+    if (st != FVLBM_OK) return st;
+    st = upload_descs(s.get());
+    if (st != FVLBM_OK) return st;
+    // Step 0 from the caller's fields (staged through the copy-out area)
+    double *stage = reinterpret_cast<double *>(s->buf + L.out);
+    const double *rho_dev = nullptr, *u_dev = nullptr;
+    hipError_t e = hipSuccess;
+    if (rho0_cells) {
+        e = hipMemcpyAsync(stage, rho0_cells, (size_t)m.n_cells * sizeof(double), hipMemcpyHostToDevice, s->stream);
+        rho_dev = stage;
+    }
+    if (e == hipSuccess && u0_cells) {
+        e = hipMemcpyAsync(stage + m.n_cells, u0_cells, (size_t)2 * m.n_cells * sizeof(double), hipMemcpyHostToDevice, s->stream);
+        u_dev = stage + m.n_cells;
+    }
+    if (e == hipSuccess)
+        e = launch_init_eq(fptr(s.get(), 0), p.storage, m.n_cells, m.np, s->ref, rho_dev, u_dev,
+                           m.perm_dev, p.rho0, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("init failed: ") + hipGetErrorString(e));
+    mesh->refs++;
+    *out = s.release();
+    return FVLBM_OK;
+}
+
+double fvlbm_solver_dt(const fvlbm_solver *s) { return s ? s->dt : -1.0; }
+
+void fvlbm_solver_destroy(fvlbm_solver *s) {
+    if (!s) return;
+    if (s->mesh) s->mesh->refs--;
+    delete s;
+}
+
+fvlbm_status fvlbm_step(fvlbm_solver *s, int64_t n_steps) {
+    if (!s || n_steps < 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_step");
+    if (s->failed) return fail(FVLBM_E_STATE, "solver is in an error state");
+    if (s->snap_cur < 0 && s->steps % s->lag == 0) {
+        if (take_snapshot(s) != hipSuccess) { s->failed = true; return fail(FVLBM_E_DEVICE, "snapshot failed"); }
+    }
+    int64_t left = n_steps;
+    while (left > 0) {
+        int64_t to_snap = s->lag - (s->steps % s->lag);
+        int64_t chunk = std::min(left, to_snap);
+        fvlbm_status st = enqueue_steps(s, chunk);
+        if (st != FVLBM_OK) { s->failed = true; return st; }
+        left -= chunk;
+        if (s->steps % s->lag == 0) {
+            if (take_snapshot(s) != hipSuccess) { s->failed = true; return fail(FVLBM_E_DEVICE, "snapshot failed"); }
+        }
+    }
+    return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_macros(fvlbm_solver *s, double *rho, double *u, double *stats) {
+    if (!s) return fail(FVLBM_E_ARG, "null solver");
+    if (s->failed) return fail(FVLBM_E_STATE, "solver is in an error state");
+    const MeshDev &m = s->mesh->dev;
+    double *out = reinterpret_cast<double *>(s->buf + s->L.out);
+    double *scal = reinterpret_cast<double *>(s->buf + s->L.scal);
+    int *flag = reinterpret_cast<int *>(s->buf + s->L.flag);
+    double *partial = reinterpret_cast<double *>(s->buf + s->L.partial);
+    int zero = 0;
+    hipError_t e = hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = launch_macros(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref, m.area, m.perm_dev,
+                          out, out + m.n_cells, partial, flag, s->stream);
+    if (e == hipSuccess) e = launch_finish_sums(partial, reduce_blocks(m.n_cells), scal, 0, s->stream);
+    double sc[2] = {0, -1};
+    int fl = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(sc, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&fl, flag, sizeof(int), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, out, (size_t)m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(u, out + m.n_cells, (size_t)2 * m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) { s->failed = true; return fail(FVLBM_E_DEVICE, std::string("macros failed: ") + hipGetErrorString(e)); }
+    bool have_res = s->snap_cur >= 0 && s->snap_step >= s->lag;
+    if (stats) {
+        stats[0] = sc[0];
+        stats[1] = have_res ? sc[1] : -1.0;
+        stats[2] = (double)s->steps * s->dt;
+        stats[3] = (double)s->steps;
+    }
+    if (fl) return fail(FVLBM_E_DIVERGED, "non-finite density or velocity");
+    return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_get_f(fvlbm_solver *s, double *f) {
+    if (!s || !f) return fail(FVLBM_E_ARG, "null argument");
+    const MeshDev &m = s->mesh->dev;
+    double *out = reinterpret_cast<double *>(s->buf + s->L.out);
+    hipError_t e = launch_get_f(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref, m.perm_dev, out, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, out, (size_t)Q * m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
+    return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_set_f(fvlbm_solver *s, const double *f) {
+    if (!s || !f) return fail(FVLBM_E_ARG, "null argument");
+    const MeshDev &m = s->mesh->dev;
+    double *stage = reinterpret_cast<double *>(s->buf + s->L.out);
+    hipError_t e = hipMemcpyAsync(stage, f, (size_t)Q * m.n_cells * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = launch_set_f(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref, m.perm_dev, stage, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
+    s->have_prev = false;
+    s->snap_cur = -1;
+    s->snap_step = -1;
+    return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_rhs(fvlbm_solver *s, double *rhs) {
+    if (!s || !rhs) return fail(FVLBM_E_ARG, "null argument");
+    if (s->p.scheme == FVLBM_SCHEME_AB2 && s->have_prev)
+        return fail(FVLBM_E_STATE, "fvlbm_rhs would overwrite the AB2 history; call it before stepping");
+    const MeshDev &m = s->mesh->dev;
+    double *out = reinterpret_cast<double *>(s->buf + s->L.out);
+    int k = s->cur == 0 ? RH0 : (s->cur == 1 ? RH1 : RH2);
+    hipError_t e = launch_stage(s->desc_dev + k, s->ut, m.nf, s->p.storage, s->sched.xcd_remap, s->stream);
+    if (e == hipSuccess) e = launch_rhs_out(reinterpret_cast<float *>(s->buf + s->L.r32), m.n_cells, m.np, m.perm_dev, out, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(rhs, out, (size_t)Q * m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
+    return FVLBM_OK;
+}
+
+size_t fvlbm_checkpoint_bytes(const fvlbm_solver *s) {
+    if (!s) return 0;
+    const MeshDev &m = s->mesh->dev;
+    size_t fb = (size_t)Q * m.np * storage_bytes(s->p.storage);
+    size_t extra = s->p.scheme == FVLBM_SCHEME_AB2 ? (size_t)Q * m.np * sizeof(float) : 0;
+    return 64 + fb + extra;
+}
+
+fvlbm_status fvlbm_checkpoint(fvlbm_solver *s, void *host_buf, size_t bytes) {
+    if (!s || !host_buf || bytes < fvlbm_checkpoint_bytes(s)) return fail(FVLBM_E_ARG, "bad checkpoint buffer");
+    const MeshDev &m = s->mesh->dev;
+    size_t fb = (size_t)Q * m.np * storage_bytes(s->p.storage);
+    int64_t hdr[8] = {0x46564c424d31LL, s->steps, s->p.storage, s->p.scheme, m.n_cells, s->have_prev, 0, 0};
+    std::memcpy(host_buf, hdr, 64);
+    hipError_t e = hipMemcpyAsync((char *)host_buf + 64, fptr(s, s->cur), fb, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && s->p.scheme == FVLBM_SCHEME_AB2)
+        e = hipMemcpyAsync((char *)host_buf + 64 + fb, s->buf + s->L.r32, (size_t)Q * m.np * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
+    return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_restore(fvlbm_solver *s, const void *host_buf, size_t bytes) {
+    if (!s || !host_buf || bytes < fvlbm_checkpoint_bytes(s)) return fail(FVLBM_E_ARG, "bad checkpoint buffer");
+    const MeshDev &m = s->mesh->dev;
+    int64_t hdr[8];
+    std::memcpy(hdr, host_buf, 64);
+    if (hdr[0] != 0x46564c424d31LL || hdr[2] != s->p.storage || hdr[3] != s->p.scheme || hdr[4] != m.n_cells)
+        return fail(FVLBM_E_ARG, "checkpoint does not match this solver");
+    size_t fb = (size_t)Q * m.np * storage_bytes(s->p.storage);
+    s->cur = 0;
+    hipError_t e = hipMemcpyAsync(fptr(s, 0), (const char *)host_buf + 64, fb, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess && s->p.scheme == FVLBM_SCHEME_AB2)
+        e = hipMemcpyAsync(s->buf + s->L.r32, (const char *)host_buf + 64 + fb, (size_t)Q * m.np * sizeof(float), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
+    s->steps = hdr[1];
+    s->have_prev = hdr[5] != 0;
+    s->snap_cur = -1;
+    s->snap_step = -1;
+    s->failed = false;
+    return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap) {
+    if (!s || (block != 64 && block != 128 && block != 256 && block != 512)) return fail(FVLBM_E_ARG, "unsupported block size");
+    s->sched.block = block;
+    s->sched.xcd_remap = xcd_remap ? 1 : 0;
+    free_graphs(s->graphs);
+    return make_units({{0, s->mesh->dev.n_cells}}, block, s->ut);
+}
+
+fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap) {
+    if (!s || !block || !xcd_remap) return fail(FVLBM_E_ARG, "null argument");
+    *block = s->sched.block;
+    *xcd_remap = s->sched.xcd_remap;
+    return FVLBM_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
+fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_batch **out) {
+    if (!solvers || n <= 0 || !out) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_batch_create");
+    *out = nullptr;
+    auto b = std::make_unique<fvlbm_batch>();
+    b->scheme = solvers[0]->p.scheme;
+    b->storage = solvers[0]->p.storage;
+    b->stream = solvers[0]->stream;
+    b->sched = solvers[0]->sched;
+    for (int i = 0; i < n; i++) {
+        fvlbm_solver *s = solvers[i];
+        if (!s || s->failed) return fail(FVLBM_E_ARG, "null or failed solver in batch");
+        if (s->p.scheme != b->scheme || s->p.storage != b->storage) return fail(FVLBM_E_PARAM, "batch members must share scheme and storage");
+        if (s->stream != b->stream) return fail(FVLBM_E_PARAM, "batch members must share a stream");
+        if (s->p.scheme != FVLBM_SCHEME_RK4 && s->cur != solvers[0]->cur) return fail(FVLBM_E_PARAM, "batch members must be at the same buffer parity");
+        if (s->p.scheme == FVLBM_SCHEME_AB2 && !s->have_prev) return fail(FVLBM_E_PARAM, "AB2 members must have taken their first step");
+        b->members.push_back(s);
+    }
+    std::vector<InstDesc> all((size_t)N_KINDS * n);
+    for (int i = 0; i < n; i++) {
+        InstDesc d[N_KINDS];
+        fill_descs(b->members[i], d);
+        for (int k = 0; k < N_KINDS; k++) all[(size_t)k * n + i] = d[k];
+    }
+    if (hipMalloc(&b->desc_dev, all.size() * sizeof(InstDesc)) != hipSuccess) return fail(FVLBM_E_NOMEM, "batch descriptor allocation failed");
+    if (hipMemcpy(b->desc_dev, all.data(), all.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FVLBM_E_DEVICE, "batch descriptor upload failed");
+    for (int t = 0; t < 2; t++) {
+        std::vector<std::pair<int, int>> inst;
+        for (int i = 0; i < n; i++)
+            if (b->members[i]->mesh->dev.nf == 3 + t) inst.push_back({i, b->members[i]->mesh->dev.n_cells});
+        fvlbm_status st = make_units(inst, b->sched.block, b->ut[t]);
+        if (st != FVLBM_OK) return st;
+    }
+    *out = b.release();
+    return FVLBM_OK;
+}
+
+namespace {
+hipGraphExec_t batch_graph(fvlbm_batch *b, int cur, int nsteps) {
+    auto key = std::make_pair(cur, nsteps);
+    auto it = b->graphs.find(key);
+    if (it != b->graphs.end()) return it->second;
+    hipGraph_t g;
+    if (hipGraphCreate(&g, 0) != hipSuccess) return nullptr;
+    std::vector<int> ks;
+    std::vector<std::unique_ptr<void *[]>> argstore;
+    std::vector<hipGraphNode_t> prev;
+    const int n = (int)b->members.size();
+    int c = cur;
+    bool hp = true, ok = true;
+    for (int st = 0; st < nsteps && ok; st++) {
+        step_kinds(b->scheme, c, hp, ks);
+        for (int k : ks) {
+            std::vector<hipGraphNode_t> now;
+            for (int t = 0; t < 2 && ok; t++) {
+                if (b->ut[t].n_units == 0) continue;
+                argstore.emplace_back(new void *[8]);
+                void **ab = argstore.back().get();
+                ab[0] = new char[64];
+                hipGraphNode_t node;
+                ok = add_stage_node(g, &node, prev.empty() ? nullptr : prev.data(), (int)prev.size(),
+                                    b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
+                                    b->sched.xcd_remap, ab) == hipSuccess;
+                now.push_back(node);
+            }
+            prev = now;
+        }
+        advance_position(b->scheme, c, hp);
+    }
+    hipGraphExec_t ex = nullptr;
+    if (ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
+    for (auto &a : argstore) delete[] static_cast<char *>(a[0]);
+    hipGraphDestroy(g);
+    if (ex) b->graphs[key] = ex;
+    return ex;
+}
+}  // namespace
+
+fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps) {
+    if (!b || n_steps < 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_batch_step");
+    const int n = (int)b->members.size();
+    int64_t left = n_steps;
+    std::vector<int> ks;
+    while (left > 0) {
+        fvlbm_solver *s0 = b->members[0];
+        int64_t chunk = std::min<int64_t>(left, GRAPH_CHUNK);
+        if (chunk == GRAPH_CHUNK) {
+            hipGraphExec_t ex = batch_graph(b, s0->cur, GRAPH_CHUNK);
+            if (!ex) return fail(FVLBM_E_DEVICE, "batch graph build failed");
+            if (hipGraphLaunch(ex, b->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "batch graph launch failed");
+        } else {
+            int c = s0->cur;
+            bool hp = true;
+            for (int st = 0; st < chunk; st++) {
+                step_kinds(b->scheme, c, hp, ks);
+                for (int k : ks)
+                    for (int t = 0; t < 2; t++) {
+                        hipError_t e = launch_stage(b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
+                                                    b->sched.xcd_remap, b->stream);
+                        if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
+                    }
+                advance_position(b->scheme, c, hp);
+            }
+        }
+        for (fvlbm_solver *s : b->members) {
+            int64_t before = s->steps;
+            for (int64_t k = 0; k < chunk; k++) advance_position(s->p.scheme, s->cur, s->have_prev);
+            s->steps += chunk;
+            // snapshot when a lag boundary is crossed exactly at the chunk end
+            if (s->steps / s->lag != before / s->lag && s->steps % s->lag == 0) {
+                if (take_snapshot(s) != hipSuccess) return fail(FVLBM_E_DEVICE, "snapshot failed");
+            }
+        }
+        left -= chunk;
+    }
+    return FVLBM_OK;
+}
+
+void fvlbm_batch_destroy(fvlbm_batch *b) {
+    if (!b) return;
+    free_graphs(b->graphs);
+    if (b->desc_dev) hipFree(b->desc_dev);
+    for (auto &u : b->ut) if (u.units) hipFree(u.units);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,228 @@
+// Step 0 (equilibrium initialisation), Step 6 (macroscopic fields) and the
+// FP64 reductions (mass, velocity residual of Eq. 32, non-finite flag), plus
+// FP64 <-> storage conversions used by checkpoints and tests.
+#include "fvlbm_internal.h"
+
+namespace fvlbm {
+namespace {
+
+__device__ constexpr int EXd[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int EYd[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr double WD[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+// the FP32 weights the step kernels use; the FP16 unit w S is formed as a float
+// product on both sides so they agree bitwise
+__device__ constexpr float WF[Q] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
+                                    1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+constexpr int RB = 256;   // reduction block
+
+// the reference equilibrium f_eq(rho0, u_dev) as the step kernels see it (FP32)
+__device__ inline double wref(int a, const RefDev &r) { return (double)r.fref[a]; }
+
+// exact widening of a stored value to the FP64 deviation h = f - f_ref
+__device__ inline double load_dev(const void *p, int storage, size_t idx, int a, const RefDev &r) {
+    if (storage == FVLBM_STORE_FP32) return (double)static_cast<const float *>(p)[idx] - wref(a, r);
+    if (storage == FVLBM_STORE_FP32_DEV) return (double)static_cast<const float *>(p)[idx];
+    return (double)__half2float(static_cast<const __half *>(p)[idx]) * (double)(WF[a] * r.scale);
+}
+
+__device__ inline void store_dev(void *p, int storage, size_t idx, int a, double h, const RefDev &r) {
+    if (storage == FVLBM_STORE_FP32) {
+        static_cast<float *>(p)[idx] = (float)(wref(a, r) + h);
+    } else if (storage == FVLBM_STORE_FP32_DEV) {
+        static_cast<float *>(p)[idx] = (float)h;
+    } else {
+        static_cast<__half *>(p)[idx] = __float2half_rn((float)(h / (double)(WF[a] * r.scale)));
+    }
+}
+
+// Step 0: f = f_eq(rho, u) (Eq. 3), written as deviations from the reference equilibrium.
+__global__ void k_init_eq(void *dst, int storage, int n, int np, RefDev ref,
+                          const double *rho, const double *u, const int *perm, double rho_u) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = perm[i];
+    double r = rho ? rho[c] : rho_u;
+    double ux = u ? u[2 * c] : 0.0, uy = u ? u[2 * c + 1] : 0.0;
+    double uu = ux * ux + uy * uy;
+    for (int a = 0; a < Q; a++) {
+        double eu = EXd[a] * ux + EYd[a] * uy;
+        double feq = WD[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        store_dev(dst, storage, (size_t)a * np + i, a, feq - wref(a, ref), ref);
+    }
+}
+
+__global__ void k_get_f(const void *src, int storage, int n, int np, RefDev ref,
+                        const int *perm, double *f) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = perm[i];
+    for (int a = 0; a < Q; a++)
+        f[(size_t)c * Q + a] = wref(a, ref) + load_dev(src, storage, (size_t)a * np + i, a, ref);
+}
+
+__global__ void k_set_f(void *dst, int storage, int n, int np, RefDev ref,
+                        const int *perm, const double *f) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = perm[i];
+    for (int a = 0; a < Q; a++)
+        store_dev(dst, storage, (size_t)a * np + i, a, f[(size_t)c * Q + a] - wref(a, ref), ref);
+}
+
+__global__ void k_rhs_out(const float *rhs, int n, int np, const int *perm, double *out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = perm[i];
+    for (int a = 0; a < Q; a++) out[(size_t)c * Q + a] = (double)rhs[(size_t)a * np + i];
+}
+
+// Block sum of two FP64 values in a fixed tree order (deterministic).
+__device__ inline void block_sum2(double a, double b, double *partial) {
+    __shared__ double sa[RB], sb[RB];
+    sa[threadIdx.x] = a; sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = RB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) { sa[threadIdx.x] += sa[threadIdx.x + s]; sb[threadIdx.x] += sb[threadIdx.x + s]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { partial[2 * blockIdx.x] = sa[0]; partial[2 * blockIdx.x + 1] = sb[0]; }
+}
+
+// Step 6 (Eq. 5) in FP64 from the stored state; mass = sum A rho; flag on non-finite values.
+__global__ void k_macros(const void *src, int storage, int n, int np, RefDev ref,
+                         const double *area, const int *perm, double *rho_out, double *u_out,
+                         double *partial, int *flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double mass = 0.0;
+    if (i < n) {
+        double r = 0, mx = 0, my = 0;
+        for (int a = 0; a < Q; a++) {
+            double f = wref(a, ref) + load_dev(src, storage, (size_t)a * np + i, a, ref);
+            r += f;
+            mx += EXd[a] * f;
+            my += EYd[a] * f;
+        }
+        double ux = mx / r, uy = my / r;
+        if (!isfinite(r) || !isfinite(ux) || !isfinite(uy) || !(r > 0)) atomicOr(flag, 1);
+        int c = perm[i];
+        if (rho_out) rho_out[c] = r;
+        if (u_out) { u_out[2 * c] = ux; u_out[2 * c + 1] = uy; }
+        mass = area[i] * r;
+    }
+    block_sum2(mass, 0.0, partial);
+}
+
+// Velocity snapshot for the residual; partial sums of |u - u_old|^2 and |u_old|^2.
+__global__ void k_snapshot(const void *src, int storage, int n, int np, RefDev ref,
+                           double *snap_new, const double *snap_old, double *partial) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double num = 0, den = 0;
+    if (i < n) {
+        double r = 0, mx = 0, my = 0;
+        for (int a = 0; a < Q; a++) {
+            double f = wref(a, ref) + load_dev(src, storage, (size_t)a * np + i, a, ref);
+            r += f; mx += EXd[a] * f; my += EYd[a] * f;
+        }
+        double ux = mx / r, uy = my / r;
+        snap_new[2 * i] = ux; snap_new[2 * i + 1] = uy;
+        if (snap_old) {
+            double du = ux - snap_old[2 * i], dv = uy - snap_old[2 * i + 1];
+            num = du * du + dv * dv;
+            den = snap_old[2 * i] * snap_old[2 * i] + snap_old[2 * i + 1] * snap_old[2 * i + 1];
+        }
+    }
+    block_sum2(num, den, partial);
+}
+
+// mode 0: out[0] = sum col0 (mass); mode 1: out[1] = sqrt(sum col0)/sqrt(sum col1) (residual)
+__global__ void k_finish(const double *partial, int nblk, double *out, int mode) {
+    __shared__ double sa[RB], sb[RB];
+    double a = 0, b = 0;
+    for (int k = threadIdx.x; k < nblk; k += RB) { a += partial[2 * k]; b += partial[2 * k + 1]; }
+    sa[threadIdx.x] = a; sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = RB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) { sa[threadIdx.x] += sa[threadIdx.x + s]; sb[threadIdx.x] += sb[threadIdx.x + s]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (mode == 0) out[0] = sa[0];
+        else out[1] = sqrt(sa[0]) / sqrt(sb[0]);
+    }
+}
+
+inline dim3 grid(int n) { return dim3((n + RB - 1) / RB); }
+
+}  // namespace
+
+int reduce_blocks(int n) { return (n + RB - 1) / RB; }
+
+RefDev make_ref(double rho0, double ux, double uy, double scale) {
+    static const int ex[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static const int ey[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static const double w[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    RefDev r{};
+    r.rho0 = (float)rho0;
+    const double jx = rho0 * ux, jy = rho0 * uy;
+    r.jx0 = (float)jx;
+    r.jy0 = (float)jy;
+    r.scale = (float)scale;
+    const double uu = ux * ux + uy * uy;
+    for (int a = 0; a < Q; a++) {
+        const double eu = ex[a] * ux + ey[a] * uy;
+        r.fref[a] = (float)(w[a] * rho0 * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+        // use the FP32 momentum so that the step kernels' deviation form is consistent
+        const double ej = ex[a] * (double)r.jx0 + ey[a] * (double)r.jy0;
+        const double jj = (double)r.jx0 * r.jx0 + (double)r.jy0 * r.jy0;
+        r.c0[a] = (float)((4.5 * ej * ej - 1.5 * jj) / (double)r.rho0);
+    }
+    return r;
+}
+
+hipError_t launch_init_eq(void *dst, int storage, int n, int np, const RefDev &ref,
+                          const double *rho_dev, const double *u_dev, const int *perm_dev,
+                          double rho_u, hipStream_t stream) {
+    hipLaunchKernelGGL(k_init_eq, grid(n), dim3(RB), 0, stream, dst, storage, n, np, ref, rho_dev, u_dev, perm_dev, rho_u);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_f(const void *src, int storage, int n, int np, const RefDev &ref,
+                        const int *perm_dev, double *f_dev, hipStream_t stream) {
+    hipLaunchKernelGGL(k_get_f, grid(n), dim3(RB), 0, stream, src, storage, n, np, ref, perm_dev, f_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_f(void *dst, int storage, int n, int np, const RefDev &ref,
+                        const int *perm_dev, const double *f_dev, hipStream_t stream) {
+    hipLaunchKernelGGL(k_set_f, grid(n), dim3(RB), 0, stream, dst, storage, n, np, ref, perm_dev, f_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_out(const float *rhs32, int n, int np, const int *perm_dev, double *out_dev,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL(k_rhs_out, grid(n), dim3(RB), 0, stream, rhs32, n, np, perm_dev, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_macros(const void *src, int storage, int n, int np, const RefDev &ref,
+                         const double *area, const int *perm_dev, double *rho_out, double *u_out,
+                         double *partial, int *flag, hipStream_t stream) {
+    hipLaunchKernelGGL(k_macros, grid(n), dim3(RB), 0, stream, src, storage, n, np, ref, area, perm_dev, rho_out, u_out, partial, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(const void *src, int storage, int n, int np, const RefDev &ref,
+                           double *snap_new, const double *snap_old, double *partial,
+                           hipStream_t stream) {
+    hipLaunchKernelGGL(k_snapshot, grid(n), dim3(RB), 0, stream, src, storage, n, np, ref, snap_new, snap_old, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_sums(const double *partial, int nblk, double *out, int mode, hipStream_t stream) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(RB), 0, stream, partial, nblk, out, mode);
+    return hipGetLastError();
+}
+
+}  // namespace fvlbm

@@ -1,0 +1,153 @@
+// Internal declarations of the gfx950 FVLBM library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fvlbm.h"
+
+namespace fvlbm {
+
+constexpr int Q = 9;
+constexpr int MAX_GROUPS = 16;
+constexpr int MAX_NF = 4;
+// neighbour-slot codes: >= 0 neighbour cell, -1-g boundary group g, NB_PAD no face
+constexpr int NB_PAD = -1000000;
+
+// ---------------------------------------------------------------- host mesh
+
+struct HostTopology {
+    int n_cells = 0;
+    int nf = 0;                        // face slots per cell (3 all-triangle, else 4)
+    std::vector<int> perm;             // perm[new] = input index
+    std::vector<int> iperm;            // iperm[input] = new index
+    std::vector<int> ncorner;          // [n] corners of the cell (new order)
+    std::vector<double> corner_xy;     // [n][nf][2] corner coordinates (new order)
+    std::vector<int> nbr;              // [n][nf] slot code (new order)
+    std::vector<int> back;             // [n][nf] slot of the same face in the neighbour (or -1)
+    std::vector<double> shift;         // [n][nf][2] added to the neighbour centre (periodic image)
+    int n_boundary_cells = 0;
+};
+
+// Builds topology from the raw mesh, validates it and reorders cells.
+// Returns FVLBM_OK or FVLBM_E_ARG / FVLBM_E_MESH with a message in err.
+fvlbm_status build_topology(int32_t n_nodes, const double *xy, int32_t n_cells,
+                            const int32_t *cell_ptr, const int32_t *cell_nodes, int32_t n_bfaces,
+                            const int32_t *bface_nodes, const int32_t *bface_group, int32_t n_groups,
+                            const fvlbm_bc *groups, int32_t n_periodic,
+                            const int32_t *periodic_pairs, const double *periodic_shift,
+                            int32_t reorder, HostTopology &topo, std::string &err);
+
+// ---------------------------------------------------------------- device mesh
+
+struct GroupDev {
+    int kind;
+    int internal;
+    float ux, uy;        // u_w or u_inf
+    float drho;          // rho_inf - rho0 (deviation form)
+    float rho;           // rho_inf
+};
+
+struct MeshDev {
+    int n_cells = 0;
+    int np = 0;          // plane stride (cells padded to a multiple of 512)
+    int nf = 0;
+    int n_groups = 0;
+    fvlbm_bc groups_host[MAX_GROUPS];
+    // FP32 streaming coefficients, planes [slot][np]
+    int *nbr = nullptr;          // slot codes
+    float2 *cg = nullptr;        // M^-1 w_k d_k (least-squares gradient coefficient)
+    float2 *rf = nullptr;        // x_f - x_i
+    float2 *rj = nullptr;        // x_f - x_j (neighbour image), 0 on boundary slots
+    float2 *gn = nullptr;        // n_k dl_k / A_i
+    // FP64 per cell
+    double *area = nullptr;
+    double cfl_length = 0;       // min A/(Lx+Ly)
+    int n_boundary_cells = 0;
+    std::vector<int> perm;       // perm[new] = input index
+    int *perm_dev = nullptr;     // same, on the device
+    size_t bytes = 0;
+    void *block = nullptr;       // one allocation holding everything above
+};
+
+// FP64 geometry + FP32 coefficient pass on the device.
+fvlbm_status build_device_mesh(const HostTopology &topo, const fvlbm_bc *groups, int n_groups,
+                               hipStream_t stream, MeshDev &mesh, std::string &err);
+
+// Reference state of the deviation storage: h = f - f_eq(rho0, u_dev).
+struct RefDev {
+    float rho0;          // rho0
+    float jx0, jy0;      // rho0 u_dev
+    float scale;         // S of FP16 deviation storage (stored value h/(w S))
+    float fref[9];       // f_eq(rho0, u_dev) rounded to FP32 (the FP32-storage offset)
+    float c0[9];         // (4.5 (e.j0)^2 - 1.5 |j0|^2) / rho0
+};
+
+RefDev make_ref(double rho0, double ux, double uy, double scale);
+
+// ---------------------------------------------------------------- stage launch
+
+// One instance's view for a stage launch (device memory, read through scalar loads).
+struct InstDesc {
+    const int *nbr;
+    const float2 *cg, *rf, *rj, *gn;
+    const void *src;      // state the RHS is evaluated at
+    const void *base;     // f(0) of the update (== src for Euler / AB2)
+    void *dst;
+    float *rhs_prev;      // AB2 history (FP32 planes), or null
+    int n_cells, np;
+    float coef;           // dst = base + coef * RHS   (AB2: dt)
+    float inv_tau;
+    RefDev ref;
+    int mode;             // 0 base+coef*RHS, 1 AB2 first step (Euler, store RHS), 2 AB2, 3 RHS only (FP32 out to dst)
+    int n_groups;
+    GroupDev groups[MAX_GROUPS];
+};
+
+struct Schedule {
+    int block = 256;
+    int xcd_remap = 1;
+};
+
+// Work units: (instance, first cell) per block; built for a schedule.
+struct UnitTable {
+    int2 *units = nullptr;   // device
+    int n_units = 0;
+    int block = 0;
+};
+
+// Launch one RHS-evaluation stage over all units.  nf: 3 or 4; storage FVLBM_STORE_*.
+hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
+                        int xcd_remap, hipStream_t stream);
+// Same as a kernel node for a graph.
+hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
+                          const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
+                          int xcd_remap, void **argbuf);
+
+// Step 0 and conversions (FP64 host data in input order <-> device storage).
+hipError_t launch_init_eq(void *dst, int storage, int n, int np, const RefDev &ref,
+                          const double *rho_dev, const double *u_dev, const int *perm_dev,
+                          double rho_u, hipStream_t stream);
+hipError_t launch_get_f(const void *src, int storage, int n, int np, const RefDev &ref,
+                        const int *perm_dev, double *f_dev, hipStream_t stream);
+hipError_t launch_set_f(void *dst, int storage, int n, int np, const RefDev &ref,
+                        const int *perm_dev, const double *f_dev, hipStream_t stream);
+hipError_t launch_rhs_out(const float *rhs32, int n, int np, const int *perm_dev, double *out_dev,
+                          hipStream_t stream);
+
+// Step 6 + FP64 reductions.  Writes rho/u (input order, FP64) and partial sums.
+hipError_t launch_macros(const void *src, int storage, int n, int np, const RefDev &ref,
+                         const double *area, const int *perm_dev, double *rho_out, double *u_out,
+                         double *partial, int *flag, hipStream_t stream);
+hipError_t launch_snapshot(const void *src, int storage, int n, int np, const RefDev &ref,
+                           double *snap_new, const double *snap_old, double *partial,
+                           hipStream_t stream);
+// partial: [nblk][2] -> out[0] = sum col0, out[1] = sum col1 (fixed order)
+hipError_t launch_finish_sums(const double *partial, int nblk, double *out, int mode, hipStream_t stream);
+int reduce_blocks(int n);
+
+}  // namespace fvlbm

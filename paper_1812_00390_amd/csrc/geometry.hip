@@ -1,0 +1,204 @@
+// FP64 geometry and least-squares precompute on the device (once per mesh).
+//
+// Per cell: area and area centroid (Section 2.2: f lives at the polygon's
+// centre), bounding-box extents for the CFL length of Eq. 14.  Per face slot:
+// outward unit normal, length, midpoint; the least-squares stencil point
+// (neighbour centre or its periodic image, the wall-face centre P, or the
+// ghost mirrored across the face line); the 2x2 weighted normal matrix of
+// Eq. 12 with w = 1/|d|^2 and its inverse.  The streaming coefficients
+// handed to the step kernels are rounded to FP32 only at the end.
+#include <cmath>
+#include <cstring>
+
+#include "fvlbm_internal.h"
+
+namespace fvlbm {
+namespace {
+
+__global__ void k_cell_geometry(int n, int nf, const int *__restrict__ ncorner,
+                                const double *__restrict__ xy, double *__restrict__ cen,
+                                double *__restrict__ area, double *__restrict__ cfl_len) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int m = ncorner[i];
+    const double *p = xy + (size_t)i * nf * 2;
+    double a2 = 0, sx = 0, sy = 0;
+    double x0 = p[0], x1 = p[0], y0 = p[1], y1 = p[1];
+    for (int k = 0; k < m; k++) {
+        int k1 = (k + 1 == m) ? 0 : k + 1;
+        double xa = p[2 * k], ya = p[2 * k + 1], xb = p[2 * k1], yb = p[2 * k1 + 1];
+        double cr = __dmul_rn(xa, yb) - __dmul_rn(xb, ya);
+        a2 += cr;
+        sx += (xa + xb) * cr;
+        sy += (ya + yb) * cr;
+        x0 = fmin(x0, xa); x1 = fmax(x1, xa);
+        y0 = fmin(y0, ya); y1 = fmax(y1, ya);
+    }
+    area[i] = 0.5 * a2;
+    cen[2 * i] = sx / (3.0 * a2);
+    cen[2 * i + 1] = sy / (3.0 * a2);
+    cfl_len[i] = 0.5 * a2 / ((x1 - x0) + (y1 - y0));
+}
+
+__global__ void k_face_coefficients(int n, int nf, int np, const int *__restrict__ ncorner,
+                                    const double *__restrict__ xy, const int *__restrict__ nbr_in,
+                                    const double *__restrict__ shift, const double *__restrict__ cen,
+                                    const double *__restrict__ area, const int *__restrict__ gkind,
+                                    int *__restrict__ nbr, float2 *__restrict__ cg,
+                                    float2 *__restrict__ rf, float2 *__restrict__ rj,
+                                    float2 *__restrict__ gn, int *__restrict__ bad) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int m = ncorner[i];
+    const double *p = xy + (size_t)i * nf * 2;
+    const double cx = cen[2 * i], cy = cen[2 * i + 1];
+    double dxs[MAX_NF], dys[MAX_NF], ws[MAX_NF];
+    double m11 = 0, m12 = 0, m22 = 0;
+    for (int k = 0; k < nf; k++) {
+        size_t s = (size_t)k * np + i;
+        if (k >= m) {                      // padded slot of a triangle in a mixed mesh
+            nbr[s] = NB_PAD;
+            cg[s] = make_float2(0.f, 0.f); rf[s] = cg[s]; rj[s] = cg[s]; gn[s] = cg[s];
+            ws[k] = 0; dxs[k] = 0; dys[k] = 0;
+            continue;
+        }
+        int k1 = (k + 1 == m) ? 0 : k + 1;
+        double ex = p[2 * k1] - p[2 * k], ey = p[2 * k1 + 1] - p[2 * k + 1];
+        double len = sqrt(ex * ex + ey * ey);
+        double nx = ey / len, ny = -ex / len;          // outward for CCW corners
+        double fx = 0.5 * (p[2 * k] + p[2 * k1]), fy = 0.5 * (p[2 * k + 1] + p[2 * k1 + 1]);
+        int code = nbr_in[(size_t)i * nf + k];
+        double stx, sty;
+        double rjx = 0, rjy = 0;
+        if (code >= 0) {
+            double jx = cen[2 * code] + shift[((size_t)i * nf + k) * 2];
+            double jy = cen[2 * code + 1] + shift[((size_t)i * nf + k) * 2 + 1];
+            stx = jx; sty = jy;
+            rjx = fx - jx; rjy = fy - jy;
+        } else if (gkind[-1 - code] == FVLBM_BC_WALL) {
+            stx = fx; sty = fy;                        // wall-face centre P
+        } else {
+            double dn = (fx - cx) * nx + (fy - cy) * ny;
+            stx = cx + 2.0 * dn * nx; sty = cy + 2.0 * dn * ny;   // mirrored ghost
+        }
+        double dx = stx - cx, dy = sty - cy;
+        double w = 1.0 / (dx * dx + dy * dy);
+        dxs[k] = dx; dys[k] = dy; ws[k] = w;
+        m11 += w * dx * dx; m12 += w * dx * dy; m22 += w * dy * dy;
+        nbr[s] = code;
+        rf[s] = make_float2((float)(fx - cx), (float)(fy - cy));
+        rj[s] = make_float2((float)rjx, (float)rjy);
+        double ia = len / area[i];
+        gn[s] = make_float2((float)(nx * ia), (float)(ny * ia));
+    }
+    double det = m11 * m22 - m12 * m12;
+    double tr = m11 + m22;
+    if (!(det > 1e-12 * tr * tr)) { atomicOr(bad, 1); det = 1.0; }
+    double i11 = m22 / det, i12 = -m12 / det, i22 = m11 / det;
+    for (int k = 0; k < m; k++) {
+        size_t s = (size_t)k * np + i;
+        double bx = ws[k] * dxs[k], by = ws[k] * dys[k];
+        cg[s] = make_float2((float)(i11 * bx + i12 * by), (float)(i12 * bx + i22 * by));
+    }
+}
+
+__global__ void k_min_reduce(const double *__restrict__ v, int n, double *__restrict__ out) {
+    __shared__ double sh[1024];
+    double m = 1e300;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmin(m, v[i]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+fvlbm_status build_device_mesh(const HostTopology &topo, const fvlbm_bc *groups, int n_groups,
+                               hipStream_t stream, MeshDev &mesh, std::string &err) {
+    const int n = topo.n_cells, nf = topo.nf;
+    const int np = (n + 511) / 512 * 512;
+    mesh.n_cells = n; mesh.np = np; mesh.nf = nf; mesh.n_groups = n_groups;
+    for (int g = 0; g < n_groups; g++) mesh.groups_host[g] = groups[g];
+    mesh.n_boundary_cells = topo.n_boundary_cells;
+    mesh.perm = topo.perm;
+
+    // persistent arrays
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    size_t o_nbr = take((size_t)nf * np * sizeof(int));
+    size_t o_cg = take((size_t)nf * np * sizeof(float2));
+    size_t o_rf = take((size_t)nf * np * sizeof(float2));
+    size_t o_rj = take((size_t)nf * np * sizeof(float2));
+    size_t o_gn = take((size_t)nf * np * sizeof(float2));
+    size_t o_area = take((size_t)n * sizeof(double));
+    size_t o_perm = take((size_t)n * sizeof(int));
+    size_t total = off;
+    char *blk = nullptr;
+    if (hipMalloc(&blk, total) != hipSuccess) { err = "device allocation of mesh arrays failed"; return FVLBM_E_NOMEM; }
+    mesh.block = blk; mesh.bytes = total;
+    mesh.nbr = (int *)(blk + o_nbr);
+    mesh.cg = (float2 *)(blk + o_cg);
+    mesh.rf = (float2 *)(blk + o_rf);
+    mesh.rj = (float2 *)(blk + o_rj);
+    mesh.gn = (float2 *)(blk + o_gn);
+    mesh.area = (double *)(blk + o_area);
+    mesh.perm_dev = (int *)(blk + o_perm);
+
+    // scratch for the FP64 pass
+    size_t soff = 0;
+    auto stake = [&](size_t bytes) { size_t o = soff; soff = align256(soff + bytes); return o; };
+    size_t s_nc = stake((size_t)n * sizeof(int));
+    size_t s_xy = stake((size_t)n * nf * 2 * sizeof(double));
+    size_t s_nb = stake((size_t)n * nf * sizeof(int));
+    size_t s_sh = stake((size_t)n * nf * 2 * sizeof(double));
+    size_t s_cen = stake((size_t)n * 2 * sizeof(double));
+    size_t s_cfl = stake((size_t)n * sizeof(double));
+    size_t s_gk = stake(MAX_GROUPS * sizeof(int));
+    size_t s_bad = stake(sizeof(int) + sizeof(double));
+    char *scr = nullptr;
+    if (hipMalloc(&scr, soff) != hipSuccess) { err = "device allocation of geometry scratch failed"; return FVLBM_E_NOMEM; }
+    int gk[MAX_GROUPS] = {0};
+    for (int g = 0; g < n_groups; g++) gk[g] = groups[g].kind;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    chk(hipMemcpyAsync(scr + s_nc, topo.ncorner.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, stream));
+    chk(hipMemcpyAsync(scr + s_xy, topo.corner_xy.data(), (size_t)n * nf * 2 * sizeof(double), hipMemcpyHostToDevice, stream));
+    chk(hipMemcpyAsync(scr + s_nb, topo.nbr.data(), (size_t)n * nf * sizeof(int), hipMemcpyHostToDevice, stream));
+    chk(hipMemcpyAsync(scr + s_sh, topo.shift.data(), (size_t)n * nf * 2 * sizeof(double), hipMemcpyHostToDevice, stream));
+    chk(hipMemcpyAsync(scr + s_gk, gk, sizeof(gk), hipMemcpyHostToDevice, stream));
+    chk(hipMemsetAsync(scr + s_bad, 0, sizeof(int), stream));
+    chk(hipMemcpyAsync(mesh.perm_dev, topo.perm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, stream));
+    // zero the padded tails of every plane so stray reads see finite values
+    chk(hipMemsetAsync(blk, 0, o_area, stream));
+    int nb = (n + 255) / 256;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_cell_geometry, dim3(nb), dim3(256), 0, stream, n, nf, (const int *)(scr + s_nc),
+                           (const double *)(scr + s_xy), (double *)(scr + s_cen), mesh.area, (double *)(scr + s_cfl));
+        chk(hipGetLastError());
+        hipLaunchKernelGGL(k_face_coefficients, dim3(nb), dim3(256), 0, stream, n, nf, np,
+                           (const int *)(scr + s_nc), (const double *)(scr + s_xy), (const int *)(scr + s_nb),
+                           (const double *)(scr + s_sh), (const double *)(scr + s_cen), mesh.area,
+                           (const int *)(scr + s_gk), mesh.nbr, mesh.cg, mesh.rf, mesh.rj, mesh.gn,
+                           (int *)(scr + s_bad));
+        chk(hipGetLastError());
+        hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, stream, (const double *)(scr + s_cfl), n,
+                           (double *)(scr + s_bad + 8));
+        chk(hipGetLastError());
+    }
+    struct { int bad; int pad; double minlen; } res = {0, 0, 0};
+    chk(hipMemcpyAsync(&res, scr + s_bad, sizeof(res), hipMemcpyDeviceToHost, stream));
+    chk(hipStreamSynchronize(stream));
+    hipFree(scr);
+    if (e != hipSuccess) { err = std::string("HIP error in geometry pass: ") + hipGetErrorString(e); return FVLBM_E_DEVICE; }
+    if (res.bad) { err = "singular least-squares stencil"; return FVLBM_E_MESH; }
+    mesh.cfl_length = res.minlen;
+    return FVLBM_OK;
+}
+
+}  // namespace fvlbm

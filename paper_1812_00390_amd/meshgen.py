@@ -474,3 +474,39 @@ def random_instance(rng: np.random.Generator, n_cells: int, kind: Optional[str] 
         nr = max(4, int(round(math.sqrt(n_cells / 4.0))))
         m = two_cylinders(nr=nr, nt=2 * nr, h0=min(0.005, 25.0 / nr / 2))
     return m, Re, kind
+
+
+def hybrid(n: int = 12, jitter: float = 0.15, seed: int = 0, lid_u: float = 0.1) -> RawMesh:
+    """Mixed triangle/quad cavity: the lower half of an n x n grid stays quads,
+    the upper half is split into triangles (a quad layer under a triangle
+    region, like the paper's hybrid cylinder meshes, Section 3.3)."""
+    xs = np.linspace(0.0, 1.0, n + 1); ys = xs.copy()
+    nodes = _structured_nodes(xs, ys)
+    nx1 = n + 1
+    ptr = [0]; cells = []
+    for j in range(n):
+        for i in range(n):
+            a, b = _nid(i, j, nx1), _nid(i + 1, j, nx1)
+            c, d = _nid(i + 1, j + 1, nx1), _nid(i, j + 1, nx1)
+            if j < n // 2:
+                cells.extend([a, b, c, d]); ptr.append(len(cells))
+            else:
+                cells.extend([a, b, c]); ptr.append(len(cells))
+                cells.extend([a, c, d]); ptr.append(len(cells))
+    if jitter > 0.0:
+        # quads and triangles share corner nodes: jitter-check both shapes
+        P = nodes.reshape(n + 1, nx1, 2)
+        rng = np.random.default_rng(seed)
+        base = P.copy()
+        for _ in range(40):
+            cand = base.copy()
+            cand[1:n, 1:n, 0] += rng.uniform(-jitter, jitter, (n - 1, n - 1)) / n
+            cand[1:n, 1:n, 1] += rng.uniform(-jitter, jitter, (n - 1, n - 1)) / n
+            if not (_bad_nodes(cand, n, n, True).any() or _bad_nodes(cand, n, n, False).any()):
+                P = cand
+                break
+        nodes = P.reshape(-1, 2)
+    groups = [BCGroup(WALL, (0.0, 0.0)), BCGroup(WALL, (lid_u, 0.0))]
+    bf, grp, per, sh = _rect_boundary(n, n, {"bottom": 0, "right": 0, "left": 0, "top": 1})
+    return RawMesh(nodes.astype(np.float64), np.asarray(ptr, np.int32), np.asarray(cells, np.int32),
+                   bf, grp, groups, per, sh, name=f"hybrid_{n}", meta=dict(kind="hybrid", U=lid_u))

@@ -1,0 +1,54 @@
+"""Writes the stored oracle references used by the full-size GPU parity tests.
+
+Calls only the FP64 oracle (oracle/) and the seeded mesh generators; nothing
+here touches the HIP library.  Each file holds the oracle's density and
+velocity at seeded sample cells after a fixed number of steps:
+
+  oracle_cavity100_rk4_2000.npz   lid-driven cavity, 100x100 tanh-clustered
+                                  (growth 1.08) jittered grid split into 20,000
+                                  triangles (seed 0), Re = 1000, U = 0.1,
+                                  four-stage RK, CFL 0.5, 2000 steps
+  oracle_cylinder256_rk4_100.npz  O-grid 256 x 384 quads around a cylinder,
+                                  h0 = 0.005 D to 30 D, Re = 100, U = 0.1,
+                                  four-stage RK, CFL 0.5, u_ref 0.2, 100 steps
+
+Run: python tests/golden/make_oracle_refs.py   (a few minutes, one core)
+"""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import oracle as O                      # noqa: E402
+from paper_1812_00390_amd import meshgen as mg      # noqa: E402
+
+CASES = {
+    "oracle_cavity100_rk4_2000.npz": dict(mesh=lambda: mg.cavity(n=100, ratio=1.08, jitter=0.2, seed=0, lid_u=0.1),
+                                          tau=3 * 0.1 * 1.0 / 1000, cfl=0.5, u_ref=0.1, steps=2000,
+                                          u0=(0.0, 0.0)),
+    "oracle_cylinder256_rk4_100.npz": dict(mesh=lambda: mg.cylinder(nr=256, nt=384), tau=3 * 0.1 * 1.0 / 100,
+                                           cfl=0.5, u_ref=0.2, steps=100, u0=(0.1, 0.0)),
+}
+
+
+def make(name, c):
+    m = c["mesh"]()
+    o = O.Oracle(m, tau=c["tau"], cfl=c["cfl"], u_ref=c["u_ref"], scheme="rk4")
+    o.init(rho0=1.0, u0=c["u0"])
+    o.step(c["steps"])
+    rho, u = o.macros()
+    rng = np.random.default_rng(12345)
+    idx = np.sort(rng.choice(m.n_cells, size=min(4000, m.n_cells), replace=False))
+    np.savez_compressed(os.path.join(HERE, name), idx=idx, rho=rho[idx], u=u[idx], dt=o.dt,
+                        steps=c["steps"], tau=c["tau"], umax=np.abs(u).max())
+    print(name, "dt", o.dt, "max|u|", np.abs(u).max())
+
+
+if __name__ == "__main__":
+    for name, c in CASES.items():
+        if len(sys.argv) > 1 and name not in sys.argv[1:]:
+            continue
+        make(name, c)

@@ -1,0 +1,307 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances:
+  * one RHS evaluation (Eq. 10): |rhs_gpu - rhs_oracle| <= 64 eps32 * scale_i,
+    scale_i = sqrt(2) H sum_k dl_k / A_i + 2 H / tau, H = max |f - w rho0|;
+    this bounds FP32 rounding of the face-value and flux sums in deviation form;
+  * whole runs: max |u - u_ref| <= 1e-5 U for FP32 storage, 1e-3 U for FP16
+    deviation storage (the accuracy targets of this library), and
+    max |rho - rho_ref| <= 1e-6 / 1e-4.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1812_00390_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EPS32 = np.finfo(np.float32).eps
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1812_00390_amd import fvlbm
+    fvlbm.lib()
+    return fvlbm
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def _smooth_state(O, o, seed=0, amp=1e-4):
+    g = o.geometry()
+    x, y = g["cx"], g["cy"]
+    rho = 1.0 + 0.02 * np.sin(3.1 * x + 0.7) * np.cos(2.3 * y)
+    u = np.stack([0.05 * np.cos(2.0 * y + 0.3 * x), 0.04 * np.sin(1.7 * x - 0.5 * y)], axis=1)
+    o.init(rho=rho, u=u)
+    rng = np.random.default_rng(seed)
+    f = o.f + amp * rng.standard_normal((o.n, 9)) * np.array([4, 1, 1, 1, 1, .25, .25, .25, .25]) / 9
+    return f, rho, u
+
+
+def _rhs_scale(O, o, f, tau):
+    g, fc = o.geometry(), o.faces()
+    mask = np.arange(O.MAXF)[None, :] < g["nf"][:, None]
+    perim = np.where(mask, fc["len"], 0).sum(1) / g["area"]
+    _, _, w = O.lattice()
+    H = np.abs(f - w[None, :]).max()
+    return math.sqrt(2) * H * perim + 2 * H / tau
+
+
+RHS_MESHES = {
+    "couette_quad": (lambda: mg.couette(16, 16), 0.8),
+    "cavity_tri_ragged": (lambda: mg.cavity(n=13, jitter=0.2, seed=1), 0.003),
+    "channel_ext": (lambda: mg.channel(14, 7, jitter=0.2, seed=2, tri=True, top="inlet", bottom="inlet"), 0.01),
+    "channel_int_sym": (lambda: mg.channel(14, 7, jitter=0.2, seed=3, tri=True, internal=1,
+                                           top="symmetry", bottom="wall"), 0.01),
+    "cylinder": (lambda: mg.cylinder(nr=24, nt=36, R=8.0, h0=0.02), 0.003),
+    "two_cylinders": (lambda: mg.two_cylinders(nr=10, nt=24, half_width=8.0, height=8.0, h0=0.03), 0.003),
+    "pbox_tri": (lambda: mg.periodic_box(9, 7, jitter=0.25, seed=4), 0.02),
+    "pbox_single_cell": (lambda: mg.periodic_box(1, 1, jitter=0.0, tri=False), 0.05),
+    "pbox_2x2": (lambda: mg.periodic_box(2, 2, jitter=0.0, tri=True), 0.05),
+    "hybrid": (lambda: mg.hybrid(12), 0.003),
+}
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp32dev"])
+@pytest.mark.parametrize("reorder", [0, 1, 2])
+@pytest.mark.parametrize("name", list(RHS_MESHES))
+def test_rhs_matches_oracle(F, O, name, reorder, storage):
+    make, tau = RHS_MESHES[name]
+    m = make()
+    o = O.Oracle(m, tau=tau, dt=1e-4)
+    f, _, _ = _smooth_state(O, o)
+    ref = o.rhs(f)
+    mesh = F.Mesh(m, reorder=reorder)
+    s = F.Solver(mesh, F.make_params(tau=tau, dt=1e-4, scheme="euler", storage=storage))
+    s.f = f
+    got = s.rhs()
+    # the RHS is evaluated at the stored (rounded) state: evaluate the oracle there too
+    ref = o.rhs(s.f)
+    tol = 64 * EPS32 * _rhs_scale(O, o, f, tau)
+    err = np.abs(got - ref).max(axis=1)
+    assert np.all(err <= tol), (name, err.max(), tol[np.argmax(err / tol)])
+
+
+def _run_pair(F, O, m, tau, scheme, steps, storage="fp32dev", cfl=0.5, u_ref=0.1, u0=(0.0, 0.0),
+              reorder=1, block=None, chunks=None):
+    o = O.Oracle(m, tau=tau, cfl=cfl, u_ref=u_ref, scheme=scheme)
+    o.init(rho0=1.0, u0=u0)
+    mesh = F.Mesh(m, reorder=reorder)
+    s = F.Solver(mesh, F.make_params(tau=tau, dt=o.dt, scheme=scheme, storage=storage, u_ref=u_ref, u_dev=u0),
+                 u=np.tile(np.asarray(u0, float), (m.n_cells, 1)))
+    if block:
+        s.set_schedule(block, True)
+    o.step(steps)
+    for c in (chunks or [steps]):
+        s.step(c)
+    rho_g, u_g, st = s.macros()
+    rho_o, u_o = o.macros()
+    return (rho_g, u_g, st), (rho_o, u_o), o, s
+
+
+@pytest.mark.parametrize("scheme", ["euler", "rk4", "ab2"])
+@pytest.mark.parametrize("storage,utol,rtol", [("fp32", 1e-5, 1e-6), ("fp32dev", 1e-5, 1e-6),
+                                                ("fp16dev", 1e-3, 1e-4)])
+def test_cavity_run_matches_oracle(F, O, scheme, storage, utol, rtol):
+    U = 0.1
+    m = mg.cavity(n=24, jitter=0.2, seed=5, lid_u=U)
+    tau = 3 * U / 100
+    (rg, ug, st), (ro, uo), o, s = _run_pair(F, O, m, tau, scheme, 300, storage=storage)
+    assert np.abs(uo).max() > 0.02
+    assert np.abs(ug - uo).max() <= utol * U, np.abs(ug - uo).max()
+    assert np.abs(rg - ro).max() <= rtol
+    assert st["steps"] == 300
+
+
+def test_couette_cfg1_full_run(F, O):
+    """16x16 quads, tau 0.8, Euler at CFL 0.5, 6000 steps: GPU FP32 vs FP64 oracle,
+    both against u = U y."""
+    m = mg.couette(16, 16, U=0.1)
+    (rg, ug, st), (ro, uo), o, s = _run_pair(F, O, m, 0.8, "euler", 6000, storage="fp32dev")
+    y = o.geometry()["cy"]
+    assert np.abs(ug - uo).max() <= 1e-5 * 0.1
+    assert np.abs(ug[:, 0] - 0.1 * y).max() <= 1e-5 * 0.1
+    assert 0 <= st["residual"] < 1e-5
+
+
+@pytest.mark.parametrize("name", ["channel_ext", "channel_int_sym", "cylinder", "two_cylinders", "hybrid"])
+def test_boundary_runs_match_oracle(F, O, name):
+    make, tau = RHS_MESHES[name]
+    m = make()
+    u0 = (0.1, 0.0) if name != "hybrid" else (0.0, 0.0)
+    (rg, ug, st), (ro, uo), o, s = _run_pair(F, O, m, tau, "rk4", 150, u0=u0, u_ref=0.2)
+    assert np.abs(ug - uo).max() <= 1e-5 * 0.1, np.abs(ug - uo).max()
+    assert np.abs(rg - ro).max() <= 1e-6
+
+
+def test_mass_conserved_closed_cavity(F):
+    m = mg.cavity(n=40, jitter=0.2, seed=6)
+    mesh = F.Mesh(m)
+    s = F.Solver(mesh, F.make_params(tau=3e-4, scheme="rk4", storage="fp32dev"))
+    m0 = s.stats()["mass"]
+    s.step(500)
+    rho, u, st = s.macros()
+    assert np.abs(u).max() > 1e-3
+    assert abs(st["mass"] - m0) / m0 < 2e-6
+
+
+def test_uniform_states_preserved(F):
+    for m, u0, tau in [(mg.cavity(n=30, jitter=0.2, seed=7, lid_u=0.0), (0.0, 0.0), 1e-3),
+                       (mg.periodic_box(20, 20, jitter=0.25, seed=8), (0.06, -0.03), 1e-2),
+                       (mg.channel(30, 12, jitter=0.2, seed=9, tri=True, top="symmetry", bottom="symmetry"),
+                        (0.1, 0.0), 1e-2)]:
+        mesh = F.Mesh(m)
+        s = F.Solver(mesh, F.make_params(tau=tau, scheme="rk4", storage="fp32dev"),
+                     u=np.tile(np.asarray(u0, float), (m.n_cells, 1)))
+        f0 = s.f
+        s.step(200)
+        assert np.abs(s.f - f0).max() < 1e-6 * 1e-2 + 64 * EPS32 * 0.05
+
+
+def test_batched_equals_single_bitwise(F):
+    meshes = [mg.cavity(n=20, jitter=0.2, seed=10), mg.cylinder(nr=12, nt=18, R=6.0, h0=0.05),
+              mg.cavity(n=9, jitter=0.2, seed=11), mg.hybrid(8)]
+    taus = [3e-4, 3e-3, 1e-3, 2e-3]
+    alone, mixed = [], []
+    for m, tau in zip(meshes, taus):
+        for dst in (alone, mixed):
+            mesh = F.Mesh(m)
+            dst.append((mesh, F.Solver(mesh, F.make_params(tau=tau, scheme="rk4", storage="fp16dev", u_ref=0.2))))
+    for _, s in alone:
+        s.step(70)
+    b = F.Batch([s for _, s in mixed])
+    b.step(70)
+    for (_, a), (_, x) in zip(alone, mixed):
+        assert np.array_equal(a.f, x.f)
+
+
+def test_graph_and_direct_launches_bitwise(F):
+    m = mg.cavity(n=20, jitter=0.2, seed=12)
+    outs = []
+    for chunks in ([100], [1] * 100, [7, 33, 60]):
+        mesh = F.Mesh(m)
+        s = F.Solver(mesh, F.make_params(tau=3e-4, scheme="rk4"))
+        for c in chunks:
+            s.step(c)
+        outs.append(s.f)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("scheme", ["euler", "ab2"])
+def test_schedules_do_not_change_results(F, scheme):
+    m = mg.cavity(n=22, jitter=0.2, seed=13)
+    outs = []
+    for block, x in [(256, True), (64, False), (128, True), (512, False)]:
+        mesh = F.Mesh(m)
+        s = F.Solver(mesh, F.make_params(tau=3e-4, scheme=scheme))
+        s.set_schedule(block, x)
+        s.step(41)
+        outs.append(s.f)
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "ab2"])
+def test_checkpoint_restore_bitwise(F, scheme):
+    m = mg.cavity(n=16, jitter=0.2, seed=14)
+    mesh = F.Mesh(m)
+    a = F.Solver(mesh, F.make_params(tau=1e-3, scheme=scheme))
+    a.step(60)
+    ref = a.f
+    b = F.Solver(mesh, F.make_params(tau=1e-3, scheme=scheme))
+    b.step(25)
+    ck = b.checkpoint()
+    c = F.Solver(mesh, F.make_params(tau=1e-3, scheme=scheme))
+    c.restore(ck)
+    c.step(35)
+    assert np.array_equal(c.f, ref)
+
+
+def test_errors(F):
+    m = mg.cavity(n=6)
+    mesh = F.Mesh(m)
+    with pytest.raises(F.FvlbmError) as e:
+        F.Solver(mesh, F.make_params(tau=1e-3, dt=1e-2))          # dt > 2 tau
+    assert e.value.status == -3
+    with pytest.raises(F.FvlbmError):
+        F.Solver(mesh, F.make_params(tau=-1.0))
+    s = F.Solver(mesh, F.make_params(tau=1e-3, dt=1e-2, flags=F.FLAG_FORCE_DT))
+    s.step(400)
+    with pytest.raises(F.FvlbmError) as e:
+        s.macros()
+    assert e.value.status == -6
+
+
+# ------------------------------------------------------- full-size configs --
+
+def test_cavity_cfg2_full_size_one_rhs_and_short_run(F, O):
+    """The 20,000-triangle cavity in the benchmark's launch configuration."""
+    m = mg.cavity(n=100, ratio=1.08, jitter=0.2, seed=0, lid_u=0.1)
+    tau = 3e-4
+    o = O.Oracle(m, tau=tau, cfl=0.5, u_ref=0.1, scheme="rk4")
+    f, _, _ = _smooth_state(O, o, seed=3)
+    mesh = F.Mesh(m)
+    s = F.Solver(mesh, F.make_params(tau=tau, dt=o.dt, scheme="rk4"))
+    s.f = f
+    ref = o.rhs(s.f)
+    got = s.rhs()
+    tol = 64 * EPS32 * _rhs_scale(O, o, f, tau)
+    assert np.all(np.abs(got - ref).max(axis=1) <= tol)
+    o.init(); s2 = F.Solver(mesh, F.make_params(tau=tau, dt=o.dt, scheme="rk4"))
+    o.step(20); s2.step(20)
+    assert np.abs(s2.macros()[1] - o.macros()[1]).max() <= 1e-5 * 0.1
+
+
+def test_cavity_cfg2_full_run_vs_stored_oracle(F):
+    ref = np.load(os.path.join(GOLDEN, "oracle_cavity100_rk4_2000.npz"))
+    m = mg.cavity(n=100, ratio=1.08, jitter=0.2, seed=0, lid_u=0.1)
+    mesh = F.Mesh(m)
+    for storage, utol in (("fp32", 1e-5), ("fp32dev", 1e-5), ("fp16dev", 1e-3)):
+        s = F.Solver(mesh, F.make_params(tau=float(ref["tau"]), dt=float(ref["dt"]), scheme="rk4", storage=storage))
+        s.step(int(ref["steps"]))
+        rho, u, _ = s.macros()
+        idx = ref["idx"]
+        err = np.abs(u[idx] - ref["u"]).max()
+        print(f"cavity 20k tri RK4 2000 steps {storage}: max|u-u_ref| = {err:.3e} (U = 0.1)")
+        assert err <= utol * 0.1
+        assert np.abs(rho[idx] - ref["rho"]).max() <= utol * 0.1
+
+
+def test_cylinder_cfg3_full_size_vs_stored_oracle(F):
+    ref = np.load(os.path.join(GOLDEN, "oracle_cylinder256_rk4_100.npz"))
+    m = mg.cylinder(nr=256, nt=384)
+    mesh = F.Mesh(m)
+    for storage, utol in (("fp32", 1e-5), ("fp32dev", 1e-5), ("fp16dev", 1e-3)):
+        s = F.Solver(mesh, F.make_params(tau=float(ref["tau"]), dt=float(ref["dt"]), scheme="rk4",
+                                         storage=storage, u_ref=0.2, u_dev=(0.1, 0.0)),
+                     u=np.tile([0.1, 0.0], (m.n_cells, 1)))
+        s.step(int(ref["steps"]))
+        rho, u, _ = s.macros()
+        idx = ref["idx"]
+        err = np.abs(u[idx] - ref["u"]).max()
+        print(f"cylinder 98k quads RK4 100 steps {storage}: max|u-u_ref| = {err:.3e}")
+        assert err <= utol * 0.1
+
+
+def test_streaming_size_mesh_invariants(F):
+    """8.4M triangles (the roofline workload): rest state preserved, mass conserved."""
+    m = mg.cavity(n=2048, ratio=1.08, jitter=0.2, seed=0, lid_u=0.0)
+    mesh = F.Mesh(m)
+    s = F.Solver(mesh, F.make_params(tau=3e-5, scheme="euler", storage="fp32dev"))
+    st0 = s.stats()
+    s.step(20)
+    rho, u, st = s.macros()
+    assert np.abs(u).max() < 1e-7
+    assert abs(st["mass"] - st0["mass"]) / st0["mass"] < 1e-7
