@@ -63,12 +63,12 @@ def cpu_baseline(mesh_raw, tau, scheme, target_s=12.0):
 
 def streaming(F, mg, stream, schemes=("euler", "rk4"), n=2048, steps=None):
     out = {}
-    m = mg.cavity(n=n, ratio=1.08, jitter=0.2, seed=0, lid_u=0.1)
+    m = mg.streaming_cavity(n=n)
     mesh = F.Mesh(m, reorder=F.REORDER_RCM)
     nf = mesh.info()["nf"]
     for scheme in schemes:
         k = steps or (20 if scheme == "euler" else 5)
-        s = F.Solver(mesh, F.make_params(tau=3e-5, scheme=scheme, storage="fp32"))
+        s = F.Solver(mesh, F.make_params(tau=3e-5, scheme=scheme, storage="fp32dev"))
         el = timed_run(F, s, k, 2, stream)
         n_launch = k * (4 if scheme == "rk4" else 1)
         t_launch = el / n_launch

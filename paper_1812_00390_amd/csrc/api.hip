@@ -78,6 +78,7 @@ struct fvlbm_solver {
     InstDesc *desc_dev = nullptr;   // [N_KINDS]
     UnitTable ut;
     Schedule sched;
+    const TileTables *tiles = nullptr;
     // graph cache: key (start buffer, steps)
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     ~fvlbm_solver();
@@ -87,6 +88,7 @@ struct fvlbm_batch {
     std::vector<fvlbm_solver *> members;
     InstDesc *desc_dev = nullptr;     // [N_KINDS][n]
     UnitTable ut[2];                  // by face-slot count (3, 4)
+    int hmax[2] = {0, 0};
     int scheme = 0, storage = 0;
     hipStream_t stream = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -100,11 +102,11 @@ void free_graphs(std::map<std::pair<int, int>, hipGraphExec_t> &g) {
     g.clear();
 }
 
-// Build the unit table (instance, first cell) for a list of (instance, n_cells).
+// Build the unit table (instance, tile) for a list of (instance, n_cells).
 fvlbm_status make_units(const std::vector<std::pair<int, int>> &inst, int block, UnitTable &ut) {
     std::vector<int2> units;
     for (auto &pr : inst)
-        for (int c = 0; c < pr.second; c += block) units.push_back(make_int2(pr.first, c));
+        for (int t = 0; t * block < pr.second; t++) units.push_back(make_int2(pr.first, t));
     if (ut.units) { hipFree(ut.units); ut.units = nullptr; }
     ut.n_units = (int)units.size();
     ut.block = block;
@@ -117,10 +119,11 @@ fvlbm_status make_units(const std::vector<std::pair<int, int>> &inst, int block,
 
 void *fptr(fvlbm_solver *s, int k) { return s->buf + s->L.fbuf[k]; }
 
-InstDesc base_desc(fvlbm_solver *s) {
+InstDesc base_desc(fvlbm_solver *s, const TileTables *tt) {
     const MeshDev &m = s->mesh->dev;
     InstDesc d{};
-    d.nbr = m.nbr; d.cg = m.cg; d.rf = m.rf; d.rj = m.rj; d.gn = m.gn;
+    d.vxy = m.vxy; d.dxy = m.dxy; d.inva = m.inva; d.minv = m.minv;
+    d.lnbr = tt->lnbr; d.halo_ptr = tt->halo_ptr; d.halo_idx = tt->halo_idx; d.halo_code = tt->halo_code;
     d.n_cells = m.n_cells; d.np = m.np;
     d.inv_tau = (float)(1.0 / s->p.tau);
     d.ref = s->ref;
@@ -138,9 +141,9 @@ InstDesc base_desc(fvlbm_solver *s) {
     return d;
 }
 
-// Descriptors of every stage kind for one solver.
-void fill_descs(fvlbm_solver *s, InstDesc out[N_KINDS]) {
-    InstDesc b = base_desc(s);
+// Descriptors of every stage kind for one solver, for tile tables tt.
+void fill_descs(fvlbm_solver *s, const TileTables *tt, InstDesc out[N_KINDS]) {
+    InstDesc b = base_desc(s, tt);
     auto set = [&](int k, int src, int base, int dst, double coef, int mode) {
         out[k] = b;
         out[k].src = fptr(s, src);
@@ -219,7 +222,7 @@ hipGraphExec_t solver_graph(fvlbm_solver *s, int cur, int nsteps) {
             ab[0] = new char[64];
             hipGraphNode_t node;
             ok = add_stage_node(g, &node, prev ? &prev : nullptr, prev ? 1 : 0, s->desc_dev + k, s->ut,
-                                s->mesh->dev.nf, s->p.storage, s->sched.xcd_remap, ab) == hipSuccess;
+                                s->mesh->dev.nf, s->p.storage, s->sched.xcd_remap, s->tiles->hmax, ab) == hipSuccess;
             prev = node;
             if (!ok) break;
         }
@@ -254,7 +257,7 @@ fvlbm_status enqueue_steps(fvlbm_solver *s, int64_t n) {
         }
         step_kinds(s->p.scheme, s->cur, s->have_prev, ks);
         for (int k : ks) {
-            hipError_t e = launch_stage(s->desc_dev + k, s->ut, nf, s->p.storage, s->sched.xcd_remap, s->stream);
+            hipError_t e = launch_stage(s->desc_dev + k, s->ut, nf, s->p.storage, s->sched.xcd_remap, s->tiles->hmax, s->stream);
             if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("stage launch failed: ") + hipGetErrorString(e));
         }
         advance_position(s->p.scheme, s->cur, s->have_prev);
@@ -266,7 +269,7 @@ fvlbm_status enqueue_steps(fvlbm_solver *s, int64_t n) {
 
 fvlbm_status upload_descs(fvlbm_solver *s) {
     InstDesc d[N_KINDS];
-    fill_descs(s, d);
+    fill_descs(s, s->tiles, d);
     if (hipMemcpy(s->desc_dev, d, sizeof(d), hipMemcpyHostToDevice) != hipSuccess)
         return fail(FVLBM_E_DEVICE, "descriptor upload failed");
     return FVLBM_OK;
@@ -329,6 +332,7 @@ double fvlbm_mesh_cfl_length(const fvlbm_mesh *mesh) { return mesh ? mesh->dev.c
 
 void fvlbm_mesh_destroy(fvlbm_mesh *mesh) {
     if (!mesh) return;
+    free_tiles(mesh->dev);
     if (mesh->dev.block) hipFree(mesh->dev.block);
     delete mesh;
 }
@@ -373,6 +377,16 @@ fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const doub
     s->L = L;
     s->lag = p.residual_lag > 0 ? p.residual_lag : 1000;
     if (hipMalloc(&s->desc_dev, sizeof(InstDesc) * N_KINDS) != hipSuccess) return fail(FVLBM_E_NOMEM, "descriptor allocation failed");
+    {
+        std::string err;
+        fvlbm_status tst = get_tiles(mesh->dev, s->sched.block, &s->tiles, err);
+        if (tst != FVLBM_OK) return fail(tst, err);
+        if (stage_lds_bytes(s->sched.block, s->tiles->hmax) > 65536) {
+            s->sched.block = 128;
+            tst = get_tiles(mesh->dev, s->sched.block, &s->tiles, err);
+            if (tst != FVLBM_OK) return fail(tst, err);
+        }
+    }
     fvlbm_status st = make_units({{0, m.n_cells}}, s->sched.block, s->ut);
     if (st != FVLBM_OK) return st;
     st = upload_descs(s.get());
@@ -492,7 +506,7 @@ fvlbm_status fvlbm_rhs(fvlbm_solver *s, double *rhs) {
     const MeshDev &m = s->mesh->dev;
     double *out = reinterpret_cast<double *>(s->buf + s->L.out);
     int k = s->cur == 0 ? RH0 : (s->cur == 1 ? RH1 : RH2);
-    hipError_t e = launch_stage(s->desc_dev + k, s->ut, m.nf, s->p.storage, s->sched.xcd_remap, s->stream);
+    hipError_t e = launch_stage(s->desc_dev + k, s->ut, m.nf, s->p.storage, s->sched.xcd_remap, s->tiles->hmax, s->stream);
     if (e == hipSuccess) e = launch_rhs_out(reinterpret_cast<float *>(s->buf + s->L.r32), m.n_cells, m.np, m.perm_dev, out, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(rhs, out, (size_t)Q * m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -546,10 +560,18 @@ fvlbm_status fvlbm_restore(fvlbm_solver *s, const void *host_buf, size_t bytes) 
 
 fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap) {
     if (!s || (block != 64 && block != 128 && block != 256 && block != 512)) return fail(FVLBM_E_ARG, "unsupported block size");
+    const TileTables *tt = nullptr;
+    std::string err;
+    fvlbm_status st = get_tiles(s->mesh->dev, block, &tt, err);
+    if (st != FVLBM_OK) return fail(st, err);
+    if (stage_lds_bytes(block, tt->hmax) > 65536) return fail(FVLBM_E_ARG, "tile and halo do not fit the LDS at this block size");
     s->sched.block = block;
     s->sched.xcd_remap = xcd_remap ? 1 : 0;
+    s->tiles = tt;
     free_graphs(s->graphs);
-    return make_units({{0, s->mesh->dev.n_cells}}, block, s->ut);
+    st = make_units({{0, s->mesh->dev.n_cells}}, block, s->ut);
+    if (st != FVLBM_OK) return st;
+    return upload_descs(s);
 }
 
 fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap) {
@@ -580,10 +602,19 @@ fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_b
     }
     std::vector<InstDesc> all((size_t)N_KINDS * n);
     for (int i = 0; i < n; i++) {
+        fvlbm_solver *s = b->members[i];
+        const TileTables *tt = nullptr;
+        std::string err;
+        fvlbm_status st = get_tiles(s->mesh->dev, b->sched.block, &tt, err);
+        if (st != FVLBM_OK) return fail(st, err);
+        int t = s->mesh->dev.nf - 3;
+        b->hmax[t] = std::max(b->hmax[t], tt->hmax);
         InstDesc d[N_KINDS];
-        fill_descs(b->members[i], d);
+        fill_descs(s, tt, d);
         for (int k = 0; k < N_KINDS; k++) all[(size_t)k * n + i] = d[k];
     }
+    for (int t = 0; t < 2; t++)
+        if (stage_lds_bytes(b->sched.block, b->hmax[t]) > 65536) return fail(FVLBM_E_PARAM, "batch tiles do not fit the LDS");
     if (hipMalloc(&b->desc_dev, all.size() * sizeof(InstDesc)) != hipSuccess) return fail(FVLBM_E_NOMEM, "batch descriptor allocation failed");
     if (hipMemcpy(b->desc_dev, all.data(), all.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess)
         return fail(FVLBM_E_DEVICE, "batch descriptor upload failed");
@@ -623,7 +654,7 @@ hipGraphExec_t batch_graph(fvlbm_batch *b, int cur, int nsteps) {
                 hipGraphNode_t node;
                 ok = add_stage_node(g, &node, prev.empty() ? nullptr : prev.data(), (int)prev.size(),
                                     b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
-                                    b->sched.xcd_remap, ab) == hipSuccess;
+                                    b->sched.xcd_remap, b->hmax[t], ab) == hipSuccess;
                 now.push_back(node);
             }
             prev = now;
@@ -659,7 +690,7 @@ fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps) {
                 for (int k : ks)
                     for (int t = 0; t < 2; t++) {
                         hipError_t e = launch_stage(b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
-                                                    b->sched.xcd_remap, b->stream);
+                                                    b->sched.xcd_remap, b->hmax[t], b->stream);
                         if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
                     }
                 advance_position(b->scheme, c, hp);

@@ -177,6 +177,7 @@ RefDev make_ref(double rho0, double ux, double uy, double scale) {
         const double ej = ex[a] * (double)r.jx0 + ey[a] * (double)r.jy0;
         const double jj = (double)r.jx0 * r.jx0 + (double)r.jy0 * r.jy0;
         r.c0[a] = (float)((4.5 * ej * ej - 1.5 * jj) / (double)r.rho0);
+        r.inv_unit[a] = (float)(1.0 / (double)((float)w[a] * r.scale));
     }
     return r;
 }

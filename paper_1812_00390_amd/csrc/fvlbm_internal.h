@@ -5,6 +5,7 @@
 #include <hip/hip_fp16.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -52,18 +53,36 @@ struct GroupDev {
     float rho;           // rho_inf
 };
 
+// Per tile size T: cells [t*T, t*T+T) form tile t; its halo is the set of
+// face neighbours outside the tile.  Local indices: tile cell i -> i - t*T,
+// halo entry k -> T + k.
+struct TileTables {
+    int T = 0;
+    int n_tiles = 0;
+    int hmax = 0;                // largest halo
+    uint2 *lnbr = nullptr;       // [np] four int16 slot codes per tile cell: local index, -1-g, or LN_PAD
+    int *halo_ptr = nullptr;     // [n_tiles+1]
+    int *halo_idx = nullptr;     // cell of each halo entry
+    int *halo_code = nullptr;    // [entries][nf]: local index (< LOCAL_LIM), LOCAL_LIM + cell, -1-g, NB_PAD
+    size_t bytes = 0;
+    void *block = nullptr;
+};
+constexpr int LOCAL_LIM = 1 << 16;
+constexpr int LN_PAD = -32768;
+
 struct MeshDev {
     int n_cells = 0;
     int np = 0;          // plane stride (cells padded to a multiple of 512)
     int nf = 0;
     int n_groups = 0;
     fvlbm_bc groups_host[MAX_GROUPS];
-    // FP32 streaming coefficients, planes [slot][np]
-    int *nbr = nullptr;          // slot codes
-    float2 *cg = nullptr;        // M^-1 w_k d_k (least-squares gradient coefficient)
-    float2 *rf = nullptr;        // x_f - x_i
-    float2 *rj = nullptr;        // x_f - x_j (neighbour image), 0 on boundary slots
-    float2 *gn = nullptr;        // n_k dl_k / A_i
+    // FP32 per-cell description, planes [slot][np] (see the geometry pass)
+    float2 *vxy = nullptr;       // corner k - centroid
+    float2 *dxy = nullptr;       // stencil offset of slot k
+    float *inva = nullptr;       // 1/A
+    float *minv = nullptr;       // [3][np] inverse least-squares matrix (m11, m12, m22)
+    std::vector<int> nbr_host;   // [n][nf] slot codes (new order), for the tile tables
+    std::map<int, struct TileTables> tiles;   // by tile size
     // FP64 per cell
     double *area = nullptr;
     double cfl_length = 0;       // min A/(Lx+Ly)
@@ -85,16 +104,31 @@ struct RefDev {
     float scale;         // S of FP16 deviation storage (stored value h/(w S))
     float fref[9];       // f_eq(rho0, u_dev) rounded to FP32 (the FP32-storage offset)
     float c0[9];         // (4.5 (e.j0)^2 - 1.5 |j0|^2) / rho0
+    float inv_unit[9];   // 1 / (w S), FP16 storage unit
 };
 
 RefDev make_ref(double rho0, double ux, double uy, double scale);
 
 // ---------------------------------------------------------------- stage launch
 
+// Host form of the tile tables (see TileTables).
+struct HostTiles {
+    int T = 0, n_tiles = 0, hmax = 0;
+    std::vector<uint16_t> lnbr;      // [np][4]
+    std::vector<int> halo_ptr, halo_idx, halo_code;
+};
+void build_tile_tables_host(const std::vector<int> &nbr, int n, int nf, int np, int T, HostTiles &out);
+
+// Tile tables for tile size T (built on first use, kept with the mesh).
+fvlbm_status get_tiles(MeshDev &mesh, int T, const TileTables **out, std::string &err);
+void free_tiles(MeshDev &mesh);
+
 // One instance's view for a stage launch (device memory, read through scalar loads).
 struct InstDesc {
-    const int *nbr;
-    const float2 *cg, *rf, *rj, *gn;
+    const float2 *vxy, *dxy;
+    const float *inva, *minv;
+    const uint2 *lnbr;
+    const int *halo_ptr, *halo_idx, *halo_code;
     const void *src;      // state the RHS is evaluated at
     const void *base;     // f(0) of the update (== src for Euler / AB2)
     void *dst;
@@ -113,20 +147,22 @@ struct Schedule {
     int xcd_remap = 1;
 };
 
-// Work units: (instance, first cell) per block; built for a schedule.
+// Work units: (instance, tile index) per block; built for a schedule.
 struct UnitTable {
     int2 *units = nullptr;   // device
     int n_units = 0;
     int block = 0;
 };
 
-// Launch one RHS-evaluation stage over all units.  nf: 3 or 4; storage FVLBM_STORE_*.
+// Launch one RHS-evaluation stage over all units (one unit = one tile of
+// ut.block cells).  nf: 3 or 4; storage FVLBM_STORE_*; hmax: largest halo.
 hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                        int xcd_remap, hipStream_t stream);
+                        int xcd_remap, int hmax, hipStream_t stream);
+size_t stage_lds_bytes(int T, int hmax);
 // Same as a kernel node for a graph.
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                          int xcd_remap, void **argbuf);
+                          int xcd_remap, int hmax, void **argbuf);
 
 // Step 0 and conversions (FP64 host data in input order <-> device storage).
 hipError_t launch_init_eq(void *dst, int storage, int n, int np, const RefDev &ref,

@@ -40,26 +40,33 @@ __global__ void k_cell_geometry(int n, int nf, const int *__restrict__ ncorner,
     cfl_len[i] = 0.5 * a2 / ((x1 - x0) + (y1 - y0));
 }
 
+// Compact FP32 per-cell description consumed by the step kernels:
+//   v[k]   corner k minus the centroid (corners padded with corner 0 up to nf)
+//   inva   1 / A
+//   d[k]   least-squares stencil offset x_n - x_i of slot k (0 on padded slots)
+//   minv   the 2x2 inverse of M = sum_k w_k d_k d_k^T, w_k = 1/|d_k|^2 (Eq. 12)
+// From these the kernels form the face midpoint offset (v_k + v_k+1)/2, the
+// scaled normal rot(v_k+1 - v_k)/A = n dl / A, the gradient coefficient
+// M^-1 w_k d_k, and the neighbour's offset to the face (midpoint - d_k).
 __global__ void k_face_coefficients(int n, int nf, int np, const int *__restrict__ ncorner,
                                     const double *__restrict__ xy, const int *__restrict__ nbr_in,
                                     const double *__restrict__ shift, const double *__restrict__ cen,
                                     const double *__restrict__ area, const int *__restrict__ gkind,
-                                    int *__restrict__ nbr, float2 *__restrict__ cg,
-                                    float2 *__restrict__ rf, float2 *__restrict__ rj,
-                                    float2 *__restrict__ gn, int *__restrict__ bad) {
+                                    float2 *__restrict__ vxy, float *__restrict__ inva,
+                                    float2 *__restrict__ dxy, float *__restrict__ minv,
+                                    int *__restrict__ bad) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int m = ncorner[i];
     const double *p = xy + (size_t)i * nf * 2;
     const double cx = cen[2 * i], cy = cen[2 * i + 1];
-    double dxs[MAX_NF], dys[MAX_NF], ws[MAX_NF];
     double m11 = 0, m12 = 0, m22 = 0;
     for (int k = 0; k < nf; k++) {
         size_t s = (size_t)k * np + i;
-        if (k >= m) {                      // padded slot of a triangle in a mixed mesh
-            nbr[s] = NB_PAD;
-            cg[s] = make_float2(0.f, 0.f); rf[s] = cg[s]; rj[s] = cg[s]; gn[s] = cg[s];
-            ws[k] = 0; dxs[k] = 0; dys[k] = 0;
+        int kc = k < m ? k : 0;           // padded corner repeats corner 0
+        vxy[s] = make_float2((float)(p[2 * kc] - cx), (float)(p[2 * kc + 1] - cy));
+        if (k >= m) {
+            dxy[s] = make_float2(0.f, 0.f);
             continue;
         }
         int k1 = (k + 1 == m) ? 0 : k + 1;
@@ -69,12 +76,9 @@ __global__ void k_face_coefficients(int n, int nf, int np, const int *__restrict
         double fx = 0.5 * (p[2 * k] + p[2 * k1]), fy = 0.5 * (p[2 * k + 1] + p[2 * k1 + 1]);
         int code = nbr_in[(size_t)i * nf + k];
         double stx, sty;
-        double rjx = 0, rjy = 0;
         if (code >= 0) {
-            double jx = cen[2 * code] + shift[((size_t)i * nf + k) * 2];
-            double jy = cen[2 * code + 1] + shift[((size_t)i * nf + k) * 2 + 1];
-            stx = jx; sty = jy;
-            rjx = fx - jx; rjy = fy - jy;
+            stx = cen[2 * code] + shift[((size_t)i * nf + k) * 2];
+            sty = cen[2 * code + 1] + shift[((size_t)i * nf + k) * 2 + 1];
         } else if (gkind[-1 - code] == FVLBM_BC_WALL) {
             stx = fx; sty = fy;                        // wall-face centre P
         } else {
@@ -83,23 +87,16 @@ __global__ void k_face_coefficients(int n, int nf, int np, const int *__restrict
         }
         double dx = stx - cx, dy = sty - cy;
         double w = 1.0 / (dx * dx + dy * dy);
-        dxs[k] = dx; dys[k] = dy; ws[k] = w;
         m11 += w * dx * dx; m12 += w * dx * dy; m22 += w * dy * dy;
-        nbr[s] = code;
-        rf[s] = make_float2((float)(fx - cx), (float)(fy - cy));
-        rj[s] = make_float2((float)rjx, (float)rjy);
-        double ia = len / area[i];
-        gn[s] = make_float2((float)(nx * ia), (float)(ny * ia));
+        dxy[s] = make_float2((float)dx, (float)dy);
     }
     double det = m11 * m22 - m12 * m12;
     double tr = m11 + m22;
     if (!(det > 1e-12 * tr * tr)) { atomicOr(bad, 1); det = 1.0; }
-    double i11 = m22 / det, i12 = -m12 / det, i22 = m11 / det;
-    for (int k = 0; k < m; k++) {
-        size_t s = (size_t)k * np + i;
-        double bx = ws[k] * dxs[k], by = ws[k] * dys[k];
-        cg[s] = make_float2((float)(i11 * bx + i12 * by), (float)(i12 * bx + i22 * by));
-    }
+    minv[i] = (float)(m22 / det);
+    minv[(size_t)np + i] = (float)(-m12 / det);
+    minv[2 * (size_t)np + i] = (float)(m11 / det);
+    inva[i] = (float)(1.0 / area[i]);
 }
 
 __global__ void k_min_reduce(const double *__restrict__ v, int n, double *__restrict__ out) {
@@ -131,22 +128,21 @@ fvlbm_status build_device_mesh(const HostTopology &topo, const fvlbm_bc *groups,
     // persistent arrays
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
-    size_t o_nbr = take((size_t)nf * np * sizeof(int));
-    size_t o_cg = take((size_t)nf * np * sizeof(float2));
-    size_t o_rf = take((size_t)nf * np * sizeof(float2));
-    size_t o_rj = take((size_t)nf * np * sizeof(float2));
-    size_t o_gn = take((size_t)nf * np * sizeof(float2));
+    size_t o_vxy = take((size_t)nf * np * sizeof(float2));
+    size_t o_dxy = take((size_t)nf * np * sizeof(float2));
+    size_t o_inva = take((size_t)np * sizeof(float));
+    size_t o_minv = take((size_t)3 * np * sizeof(float));
     size_t o_area = take((size_t)n * sizeof(double));
     size_t o_perm = take((size_t)n * sizeof(int));
     size_t total = off;
     char *blk = nullptr;
     if (hipMalloc(&blk, total) != hipSuccess) { err = "device allocation of mesh arrays failed"; return FVLBM_E_NOMEM; }
     mesh.block = blk; mesh.bytes = total;
-    mesh.nbr = (int *)(blk + o_nbr);
-    mesh.cg = (float2 *)(blk + o_cg);
-    mesh.rf = (float2 *)(blk + o_rf);
-    mesh.rj = (float2 *)(blk + o_rj);
-    mesh.gn = (float2 *)(blk + o_gn);
+    mesh.vxy = (float2 *)(blk + o_vxy);
+    mesh.dxy = (float2 *)(blk + o_dxy);
+    mesh.inva = (float *)(blk + o_inva);
+    mesh.minv = (float *)(blk + o_minv);
+    mesh.nbr_host = topo.nbr;
     mesh.area = (double *)(blk + o_area);
     mesh.perm_dev = (int *)(blk + o_perm);
 
@@ -184,7 +180,7 @@ fvlbm_status build_device_mesh(const HostTopology &topo, const fvlbm_bc *groups,
         hipLaunchKernelGGL(k_face_coefficients, dim3(nb), dim3(256), 0, stream, n, nf, np,
                            (const int *)(scr + s_nc), (const double *)(scr + s_xy), (const int *)(scr + s_nb),
                            (const double *)(scr + s_sh), (const double *)(scr + s_cen), mesh.area,
-                           (const int *)(scr + s_gk), mesh.nbr, mesh.cg, mesh.rf, mesh.rj, mesh.gn,
+                           (const int *)(scr + s_gk), mesh.vxy, mesh.inva, mesh.dxy, mesh.minv,
                            (int *)(scr + s_bad));
         chk(hipGetLastError());
         hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, stream, (const double *)(scr + s_cfl), n,

@@ -1,17 +1,17 @@
-// The FVLBM right-hand side and time-integrator update, fused per cell.
+// The FVLBM right-hand side and time-integrator update, fused per tile.
 //
-// One thread owns one cell and all nine directions.  Per RHS evaluation
-// (paper Section 2.5, Steps 1-5):
-//   Step 1/3  wall value f_P and ghost values f_GC of the cell's boundary
-//             slots (Eqs. 18-22), from the cell's own current-stage state;
-//   Step 2    least-squares gradient (Eq. 12) as sum_k c_k (phi_k - f_i),
-//             with c_k = M^-1 w_k d_k precomputed in FP64;
+// A workgroup owns a tile of consecutive cells (one thread per cell, all nine
+// directions per thread) and stages the tile and its face-neighbour halo in
+// LDS.  Per RHS evaluation (paper Section 2.5, Steps 1-5):
+//   Step 1/3  wall value f_P and ghost values f_GC of a cell's boundary
+//             slots (Eqs. 18-22), from that cell's own current-stage state;
+//   Step 2    least-squares gradient (Eq. 12) as sum_k M^-1 w_k d_k (phi_k - f_i)
+//             for every tile and halo cell, once, into LDS;
 //   Step 4    upwind face values (Eq. 11; border faces Eqs. 23-26): the
-//             outgoing side uses the cell's own gradient, the incoming side
-//             the upwind neighbour's gradient, which this thread recomputes
-//             from the neighbour's stencil (a cell-centric gather: no atomics
-//             and no gradient array in HBM);
-//             flux sum over faces of (e.n dl/A) phi and the BGK source;
+//             outgoing side from the cell's own gradient, the incoming side
+//             from the neighbour's staged value and gradient (a cell-centric
+//             gather: no atomics and no gradient array in HBM); flux sum over
+//             faces of (e.n dl/A) phi and the BGK source;
 //   Step 5    dst = base + coef * RHS (Euler, and each stage of the
 //             four-stage scheme), or the AB2 combination.
 // Everything is computed on deviations h = f - f_eq(rho0, u_dev) in FP32,
@@ -27,6 +27,28 @@ __device__ constexpr int EX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int EY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __device__ constexpr float WT[Q] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
                                     1.f / 36, 1.f / 36, 1.f / 36, 1.f / 36};
+
+// ---------------------------------------------------------------- memory
+//
+// The descriptor's pointers are read from memory, so the compiler cannot
+// infer their address space and would emit FLAT instructions (which also
+// count against the LDS wait counter).  Every device-memory access goes
+// through these global-address-space accessors instead.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FVLBM_GLOBAL_AS __attribute__((address_space(1)))   // the device pass only; the host pass never runs these
+#else
+#define FVLBM_GLOBAL_AS
+#endif
+template <class T>
+__device__ inline T ldg(const T *p, size_t i) {
+    return ((const FVLBM_GLOBAL_AS T *)p)[i];
+}
+template <class T>
+__device__ inline void stg(T *p, size_t i, T v) {
+    ((FVLBM_GLOBAL_AS T *)p)[i] = v;
+}
+
+__device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------- rounding
 //
@@ -75,7 +97,10 @@ __device__ inline float unit_random(uint32_t h) { return (float)(h >> 8) * (1.0f
 // unbiased rounding of s + e to FP32
 __device__ inline float round_fp32(Exact v, uint32_t salt) {
     if (v.e == 0.f) return v.s;
-    const float nb = nextafterf(v.s, v.e > 0.f ? INFINITY : -INFINITY);
+    // neighbour of s in the direction of e (s is finite and, as |e| <= ulp(s)/2, nonzero)
+    const uint32_t bs = __float_as_uint(v.s);
+    const bool up_mag = (v.e > 0.f) == (v.s > 0.f);
+    const float nb = __uint_as_float(up_mag ? bs + 1u : bs - 1u);
     const float gap = fabsf(nb - v.s);
     const uint32_t h = mix32(__float_as_uint(v.e) ^ mix32(__float_as_uint(v.s) ^ salt));
     return unit_random(h) * gap < fabsf(v.e) ? nb : v.s;
@@ -96,28 +121,29 @@ struct Storage;
 template <>
 struct Storage<FVLBM_STORE_FP32> {
     __device__ static float load(const void *p, size_t idx, int a, const RefDev &r) {
-        return static_cast<const float *>(p)[idx] - r.fref[a];
+        return ldg(static_cast<const float *>(p), idx) - r.fref[a];
     }
     __device__ static void store(void *p, size_t idx, int a, Exact h, const RefDev &r, uint32_t salt) {
-        static_cast<float *>(p)[idx] = round_fp32(add_exact(r.fref[a], h), salt);
+        stg(static_cast<float *>(p), idx, round_fp32(add_exact(r.fref[a], h), salt));
     }
 };
 template <>
 struct Storage<FVLBM_STORE_FP32_DEV> {
     __device__ static float load(const void *p, size_t idx, int, const RefDev &) {
-        return static_cast<const float *>(p)[idx];
+        return ldg(static_cast<const float *>(p), idx);
     }
     __device__ static void store(void *p, size_t idx, int, Exact h, const RefDev &, uint32_t salt) {
-        static_cast<float *>(p)[idx] = round_fp32(h, salt);
+        stg(static_cast<float *>(p), idx, round_fp32(h, salt));
     }
 };
 template <>
 struct Storage<FVLBM_STORE_FP16_DEV> {
     __device__ static float load(const void *p, size_t idx, int a, const RefDev &r) {
-        return __half2float(static_cast<const __half *>(p)[idx]) * (WT[a] * r.scale);
+        const __half v = ldg(static_cast<const __half *>(p), idx);
+        return __half2float(v) * (WT[a] * r.scale);
     }
     __device__ static void store(void *p, size_t idx, int a, Exact h, const RefDev &r, uint32_t salt) {
-        static_cast<__half *>(p)[idx] = round_fp16((h.s + h.e) / (WT[a] * r.scale), salt);
+        stg(static_cast<__half *>(p), idx, round_fp16((h.s + h.e) * r.inv_unit[a], salt));
     }
 };
 
@@ -143,7 +169,7 @@ __device__ inline Macro moments(const float h[Q], const RefDev &r) {
     m.rho = r.rho0 + s;
     m.jx = r.jx0 + mx;
     m.jy = r.jy0 + my;
-    const float ir = 1.f / m.rho;
+    const float ir = frcp(m.rho);
     m.ux = m.jx * ir;
     m.uy = m.jy * ir;
     return m;
@@ -152,7 +178,7 @@ __device__ inline Macro moments(const float h[Q], const RefDev &r) {
 // Eq. 3 as a deviation from the reference equilibrium, written with the momentum j = rho u:
 // f_eq(rho, u) - f_eq(rho0, u_dev) = w [ (rho - rho0) + 3 e.(j - j0) + (4.5 (e.j)^2 - 1.5 |j|^2)/rho - c0 ]
 __device__ inline void heq(float drho, float rho, float jx, float jy, const RefDev &r, float out[Q]) {
-    const float ir = 1.f / rho;
+    const float ir = frcp(rho);
     const float jj = 1.5f * (jx * jx + jy * jy);
     const float dx = jx - r.jx0, dy = jy - r.jy0;
 #pragma unroll
@@ -201,106 +227,190 @@ __device__ inline void boundary_value(const GroupDev &g, const float h[Q], const
     }
 }
 
-template <int NF, int STORE>
-struct Cell {
-    // Gradient of cell c (Eq. 12) given its own deviations hc.  If one
-    // neighbour's deviations are already in registers (known, hk) they are reused.
-    __device__ static void gradient(const InstDesc &d, int c, const float hc[Q], int known,
-                                    const float hk[Q], float gx[Q], float gy[Q]) {
+constexpr int PAD_BELOW = -MAX_GROUPS;   // slot codes below this are padded slots
+
+// Least-squares coefficient of slot k of cell c: M^-1 w_k d_k (Eq. 12).
+__device__ inline float2 lsq_coef(float2 dk, float m11, float m12, float m22) {
+    const float w = frcp(dk.x * dk.x + dk.y * dk.y);
+    return make_float2(w * (m11 * dk.x + m12 * dk.y), w * (m12 * dk.x + m22 * dk.y));
+}
+
+// n dl / A of slot k from the corner offsets v_k, v_k+1 (CCW corners: outward normal).
+__device__ inline float2 scaled_normal(float2 v0, float2 v1, float inva) {
+    return make_float2((v1.y - v0.y) * inva, -(v1.x - v0.x) * inva);
+}
+
+template <int NF>
+__device__ inline float2 corner(const InstDesc &d, int k, int c) {
+    return ldg(d.vxy, (size_t)(k % NF) * d.np + c);
+}
+
+// Gradient of cell c (Eq. 12): sum_k M^-1 w_k d_k (phi_k - f_c), where phi_k is
+// the neighbour's value (fetched by `fetch` from a slot code >= 0) or the wall /
+// ghost value of a boundary slot (Eqs. 18-22), formed from the cell's own state.
+template <int NF, class Fetch>
+__device__ inline void gradient(const InstDesc &d, int c, const float hc[Q], const int code[NF],
+                                Fetch fetch, float gx[Q], float gy[Q]) {
+    const float m11 = ldg(d.minv, c), m12 = ldg(d.minv, (size_t)d.np + c), m22 = ldg(d.minv, 2 * (size_t)d.np + c);
 #pragma unroll
-        for (int a = 0; a < Q; a++) { gx[a] = 0.f; gy[a] = 0.f; }
-        bool have_m = false;
-        Macro m;
-        float he[Q];
+    for (int a = 0; a < Q; a++) { gx[a] = 0.f; gy[a] = 0.f; }
+    bool have_m = false;
+    Macro m;
+    float he[Q];
 #pragma unroll
-        for (int k = 0; k < NF; k++) {
-            const size_t s = (size_t)k * d.np + c;
-            const int j = d.nbr[s];
-            if (NF == 4 && j == NB_PAD) continue;
-            const float2 w = d.cg[s];
-            float phi[Q];
-            if (j == known) {
-#pragma unroll
-                for (int a = 0; a < Q; a++) phi[a] = hk[a];
-            } else if (j >= 0) {
-#pragma unroll
-                for (int a = 0; a < Q; a++)
-                    phi[a] = Storage<STORE>::load(d.src, (size_t)a * d.np + j, a, d.ref);
-            } else {
-                if (!have_m) {
-                    m = moments(hc, d.ref);
-                    heq(m.drho, m.rho, m.jx, m.jy, d.ref, he);
-                    have_m = true;
-                }
-                boundary_value(d.groups[-1 - j], hc, m, he, d.gn[s], d.ref, phi);
+    for (int k = 0; k < NF; k++) {
+        if (code[k] < PAD_BELOW) continue;
+        const float2 w = lsq_coef(ldg(d.dxy, (size_t)k * d.np + c), m11, m12, m22);
+        float phi[Q];
+        if (code[k] >= 0) {
+            fetch(code[k], phi);
+        } else {
+            if (!have_m) {
+                m = moments(hc, d.ref);
+                heq(m.drho, m.rho, m.jx, m.jy, d.ref, he);
+                have_m = true;
             }
+            const float2 gn = scaled_normal(corner<NF>(d, k, c), corner<NF>(d, k + 1, c), ldg(d.inva, c));
+            boundary_value(d.groups[-1 - code[k]], hc, m, he, gn, d.ref, phi);
+        }
 #pragma unroll
-            for (int a = 0; a < Q; a++) {
-                float df = phi[a] - hc[a];
-                gx[a] = fmaf(w.x, df, gx[a]);
-                gy[a] = fmaf(w.y, df, gy[a]);
-            }
+        for (int a = 0; a < Q; a++) {
+            const float df = phi[a] - hc[a];
+            gx[a] = fmaf(w.x, df, gx[a]);
+            gy[a] = fmaf(w.y, df, gy[a]);
         }
     }
-};
+}
 
 __device__ inline int remap_block(int b, int nb, int xcd_remap) {
     // Blocks are dispatched round-robin over the 8 XCDs; renumber them so that
-    // each XCD walks one contiguous range of tiles (neighbour gathers then hit
-    // that XCD's L2).
+    // each XCD walks one contiguous range of tiles (halo reads then hit that
+    // XCD's L2).
     if (!xcd_remap) return b;
     const int x = b & 7, r = b >> 3;
     const int per = nb >> 3, extra = nb & 7;
-    // XCD x owns per (+1 for x < extra) consecutive logical blocks
     return x * per + (x < extra ? x : extra) + r;
 }
 
-template <int NF, int STORE>
-__global__ void __launch_bounds__(512) k_stage(const InstDesc *__restrict__ descs,
-                                               const int2 *__restrict__ units, int n_units,
-                                               int xcd_remap) {
-    const int lb = remap_block(blockIdx.x, n_units, xcd_remap);
-    const int2 u = units[lb];
+__device__ inline int unpack16(uint32_t w, int hi) { return (int)(int16_t)(hi ? (w >> 16) : (w & 0xffffu)); }
+
+// One RHS evaluation and update for one tile of T cells.
+//   Phase 1  stage the deviations of the tile and its halo in LDS;
+//   Phase 2  gradients of tile and halo cells into LDS (each computed once);
+//   Phase 3  per tile cell: face values (own gradient outgoing, staged
+//            neighbour gradient incoming), flux sum, BGK source, update, store.
+template <int NF, int STORE, int T>
+__global__ void __launch_bounds__(T) k_tile(const InstDesc *__restrict__ descs,
+                                            const int2 *__restrict__ units, int n_units,
+                                            int xcd_remap, int L) {
+    extern __shared__ float lds[];
+    float *fs = lds;               // [Q][L] deviations
+    float *gxs = lds + Q * L;      // [Q][L]
+    float *gys = lds + 2 * Q * L;  // [Q][L]
+
+    const int2 u = units[remap_block(blockIdx.x, n_units, xcd_remap)];
     const InstDesc &d = descs[u.x];
-    const int i = u.y + threadIdx.x;
-    if (i >= d.n_cells) return;
+    const int tile = u.y;
+    const int t0 = tile * T;
+    const int tid = threadIdx.x;
+    const int i = t0 + tid;
+    const bool valid = i < d.n_cells;
+    const int hb = ldg(d.halo_ptr, tile);
+    const int nh = ldg(d.halo_ptr, tile + 1) - hb;
+
+    // ---- phase 1
     float hi[Q];
+    int code[NF];
+    if (valid) {
 #pragma unroll
-    for (int a = 0; a < Q; a++) hi[a] = Storage<STORE>::load(d.src, (size_t)a * d.np + i, a, d.ref);
+        for (int a = 0; a < Q; a++) {
+            hi[a] = Storage<STORE>::load(d.src, (size_t)a * d.np + i, a, d.ref);
+            fs[a * L + tid] = hi[a];
+        }
+        const uint2 ln = ldg(d.lnbr, i);
+#pragma unroll
+        for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
+    }
+    for (int k = tid; k < nh; k += T) {
+        const int c = ldg(d.halo_idx, hb + k);
+#pragma unroll
+        for (int a = 0; a < Q; a++) fs[a * L + T + k] = Storage<STORE>::load(d.src, (size_t)a * d.np + c, a, d.ref);
+    }
+    __syncthreads();
+
+    // ---- phase 2
+    float gxi[Q], gyi[Q];
+    if (valid) {
+        auto from_lds = [&](int l, float phi[Q]) {
+#pragma unroll
+            for (int a = 0; a < Q; a++) phi[a] = fs[a * L + l];
+        };
+        gradient<NF>(d, i, hi, code, from_lds, gxi, gyi);
+#pragma unroll
+        for (int a = 0; a < Q; a++) {
+            gxs[a * L + tid] = gxi[a];
+            gys[a * L + tid] = gyi[a];
+        }
+    }
+    for (int k = tid; k < nh; k += T) {
+        const int c = ldg(d.halo_idx, hb + k);
+        float hc[Q], gx[Q], gy[Q];
+        int hcode[NF];
+#pragma unroll
+        for (int a = 0; a < Q; a++) hc[a] = fs[a * L + T + k];
+#pragma unroll
+        for (int s = 0; s < NF; s++) hcode[s] = ldg(d.halo_code, (size_t)(hb + k) * NF + s);
+        auto staged_or_global = [&](int l, float phi[Q]) {
+            if (l < LOCAL_LIM) {
+#pragma unroll
+                for (int a = 0; a < Q; a++) phi[a] = fs[a * L + l];
+            } else {
+                const int g = l - LOCAL_LIM;
+#pragma unroll
+                for (int a = 0; a < Q; a++) phi[a] = Storage<STORE>::load(d.src, (size_t)a * d.np + g, a, d.ref);
+            }
+        };
+        gradient<NF>(d, c, hc, hcode, staged_or_global, gx, gy);
+#pragma unroll
+        for (int a = 0; a < Q; a++) {
+            gxs[a * L + T + k] = gx[a];
+            gys[a * L + T + k] = gy[a];
+        }
+    }
+    __syncthreads();
+    if (!valid) return;
+
+    // ---- phase 3
     const Macro mi = moments(hi, d.ref);
     float hei[Q];
     heq(mi.drho, mi.rho, mi.jx, mi.jy, d.ref, hei);
-
-    float gxi[Q], gyi[Q];
-    Cell<NF, STORE>::gradient(d, i, hi, NO_CELL, hi, gxi, gyi);
-
+    const float inva = ldg(d.inva, i);
     float acc[Q];
 #pragma unroll
     for (int a = 0; a < Q; a++) acc[a] = 0.f;
-
 #pragma unroll
     for (int k = 0; k < NF; k++) {
-        const size_t s = (size_t)k * d.np + i;
-        const int j = d.nbr[s];
-        if (NF == 4 && j == NB_PAD) continue;
-        const float2 g = d.gn[s];
-        const float2 r = d.rf[s];
-        if (j >= 0) {
-            float hj[Q], gxj[Q], gyj[Q];
-#pragma unroll
-            for (int a = 0; a < Q; a++)
-                hj[a] = Storage<STORE>::load(d.src, (size_t)a * d.np + j, a, d.ref);
-            Cell<NF, STORE>::gradient(d, j, hj, i, hi, gxj, gyj);
-            const float2 q = d.rj[s];
+        if (code[k] < PAD_BELOW) continue;
+        const float2 v0 = corner<NF>(d, k, i), v1 = corner<NF>(d, k + 1, i);
+        const float2 g = scaled_normal(v0, v1, inva);
+        const float2 r = make_float2(0.5f * (v0.x + v1.x), 0.5f * (v0.y + v1.y));   // x_f - x_i
+        if (code[k] >= 0) {
+            const int l = code[k];
+            const float2 dk = ldg(d.dxy, (size_t)k * d.np + i);
+            const float2 q = make_float2(r.x - dk.x, r.y - dk.y);                    // x_f - x_j
 #pragma unroll
             for (int a = 1; a < Q; a++) {
                 const float en = EX[a] * g.x + EY[a] * g.y;
-                const float own = fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a]));
-                const float nb = fmaf(gyj[a], q.y, fmaf(gxj[a], q.x, hj[a]));
-                acc[a] = fmaf(en, en > 0.f ? own : nb, acc[a]);
+                float phi;
+                if (en > 0.f) {
+                    phi = fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a]));
+                } else {
+                    phi = fmaf(gys[a * L + l], q.y, fmaf(gxs[a * L + l], q.x, fs[a * L + l]));
+                }
+                acc[a] = fmaf(en, phi, acc[a]);
             }
         } else {
-            const GroupDev &gr = d.groups[-1 - j];
+            const GroupDev &gr = d.groups[-1 - code[k]];
             float bv[Q];
             boundary_value(gr, hi, mi, hei, g, d.ref, bv);
             const bool upwind = gr.kind == FVLBM_BC_INLET || (gr.kind == FVLBM_BC_OUTLET && gr.internal);
@@ -309,13 +419,13 @@ __global__ void __launch_bounds__(512) k_stage(const InstDesc *__restrict__ desc
                 const float en = EX[a] * g.x + EY[a] * g.y;
                 float phi;
                 if (gr.kind == FVLBM_BC_WALL) {
-                    phi = bv[a];
+                    phi = bv[a];                                                    // Eq. 18 face value
                 } else if (upwind) {
-                    phi = en > 0.f ? fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a])) : bv[a];
+                    phi = en > 0.f ? fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a])) : bv[a];   // Eqs. 23, 24
                 } else if (gr.kind == FVLBM_BC_OUTLET) {
-                    phi = hi[a];
+                    phi = hi[a];                                                    // Eq. 25
                 } else {
-                    phi = 0.5f * (hi[a] + bv[a]);
+                    phi = 0.5f * (hi[a] + bv[a]);                                   // Eq. 26
                 }
                 acc[a] = fmaf(en, phi, acc[a]);
             }
@@ -333,56 +443,70 @@ __global__ void __launch_bounds__(512) k_stage(const InstDesc *__restrict__ desc
             const float b = (d.base == d.src) ? hi[a] : Storage<STORE>::load(d.base, idx, a, d.ref);
             out = fma_exact(d.coef, rhs, b);
         } else if (d.mode == 3) {
-            static_cast<float *>(d.dst)[idx] = rhs;
+            stg(static_cast<float *>(d.dst), idx, rhs);
             continue;
         } else {
-            const float prev = (d.mode == 1) ? rhs : d.rhs_prev[idx];
+            const float prev = (d.mode == 1) ? rhs : ldg(d.rhs_prev, idx);
             out = fma_exact(0.5f * d.coef, 3.f * rhs - prev, hi[a]);
-            d.rhs_prev[idx] = rhs;
+            stg(d.rhs_prev, idx, rhs);
         }
         Storage<STORE>::store(d.dst, idx, a, out, d.ref, salt);
     }
 }
 
-template <int NF, int STORE>
-const void *stage_fn() { return reinterpret_cast<const void *>(&k_stage<NF, STORE>); }
+template <int NF, int STORE, int T>
+const void *fn() { return reinterpret_cast<const void *>(&k_tile<NF, STORE, T>); }
 
-const void *pick(int nf, int storage) {
-    if (nf == 3) {
-        if (storage == FVLBM_STORE_FP32) return stage_fn<3, FVLBM_STORE_FP32>();
-        if (storage == FVLBM_STORE_FP32_DEV) return stage_fn<3, FVLBM_STORE_FP32_DEV>();
-        return stage_fn<3, FVLBM_STORE_FP16_DEV>();
+template <int NF, int STORE>
+const void *pick_t(int T) {
+    switch (T) {
+    case 64: return fn<NF, STORE, 64>();
+    case 128: return fn<NF, STORE, 128>();
+    case 256: return fn<NF, STORE, 256>();
+    default: return fn<NF, STORE, 512>();
     }
-    if (storage == FVLBM_STORE_FP32) return stage_fn<4, FVLBM_STORE_FP32>();
-    if (storage == FVLBM_STORE_FP32_DEV) return stage_fn<4, FVLBM_STORE_FP32_DEV>();
-    return stage_fn<4, FVLBM_STORE_FP16_DEV>();
+}
+
+const void *pick(int nf, int storage, int T) {
+    if (nf == 3) {
+        if (storage == FVLBM_STORE_FP32) return pick_t<3, FVLBM_STORE_FP32>(T);
+        if (storage == FVLBM_STORE_FP32_DEV) return pick_t<3, FVLBM_STORE_FP32_DEV>(T);
+        return pick_t<3, FVLBM_STORE_FP16_DEV>(T);
+    }
+    if (storage == FVLBM_STORE_FP32) return pick_t<4, FVLBM_STORE_FP32>(T);
+    if (storage == FVLBM_STORE_FP32_DEV) return pick_t<4, FVLBM_STORE_FP32_DEV>(T);
+    return pick_t<4, FVLBM_STORE_FP16_DEV>(T);
 }
 
 }  // namespace
 
+size_t stage_lds_bytes(int T, int hmax) { return (size_t)3 * Q * (T + hmax) * sizeof(float); }
+
 hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                        int xcd_remap, hipStream_t stream) {
+                        int xcd_remap, int hmax, hipStream_t stream) {
     if (ut.n_units == 0) return hipSuccess;
     const int2 *units = ut.units;
     int n_units = ut.n_units;
-    void *args[] = {(void *)&descs_dev, (void *)&units, (void *)&n_units, (void *)&xcd_remap};
-    return hipLaunchKernel(pick(nf, storage), dim3(ut.n_units), dim3(ut.block), args, 0, stream);
+    int L = ut.block + hmax;
+    void *args[] = {(void *)&descs_dev, (void *)&units, (void *)&n_units, (void *)&xcd_remap, (void *)&L};
+    return hipLaunchKernel(pick(nf, storage, ut.block), dim3(ut.n_units), dim3(ut.block), args,
+                           stage_lds_bytes(ut.block, hmax), stream);
 }
 
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                          int xcd_remap, void **argbuf) {
-    // argbuf: caller-owned storage for the 4 argument values, alive until the graph is instantiated
-    struct Args { const InstDesc *d; const int2 *u; int n; int x; };
+                          int xcd_remap, int hmax, void **argbuf) {
+    // argbuf: caller-owned storage for the argument values, alive until the graph is instantiated
+    struct Args { const InstDesc *d; const int2 *u; int n; int x; int L; };
     Args *a = reinterpret_cast<Args *>(argbuf[0]);
-    a->d = descs_dev; a->u = ut.units; a->n = ut.n_units; a->x = xcd_remap;
+    a->d = descs_dev; a->u = ut.units; a->n = ut.n_units; a->x = xcd_remap; a->L = ut.block + hmax;
     void **kp = argbuf + 1;
-    kp[0] = &a->d; kp[1] = &a->u; kp[2] = &a->n; kp[3] = &a->x;
+    kp[0] = &a->d; kp[1] = &a->u; kp[2] = &a->n; kp[3] = &a->x; kp[4] = &a->L;
     hipKernelNodeParams p{};
-    p.func = const_cast<void *>(pick(nf, storage));
+    p.func = const_cast<void *>(pick(nf, storage, ut.block));
     p.gridDim = dim3(ut.n_units);
     p.blockDim = dim3(ut.block);
-    p.sharedMemBytes = 0;
+    p.sharedMemBytes = (unsigned)stage_lds_bytes(ut.block, hmax);
     p.kernelParams = kp;
     p.extra = nullptr;
     return hipGraphAddKernelNode(node, g, deps, ndeps, &p);

@@ -136,28 +136,37 @@ def _rect_boundary(nx, ny, side_group, periodic_x=False, periodic_y=False,
             np.asarray(shift, dtype=np.float64).reshape(-1, 2))
 
 
-def tanh_cluster(n: int, ratio: float) -> np.ndarray:
-    """n+1 points on [0,1], tanh-clustered at both ends with wall growth ratio h1/h0 = ratio."""
-    def pts(beta):
-        s = 2.0 * np.arange(n + 1) / n - 1.0
-        return 0.5 * (1.0 + np.tanh(beta * s) / np.tanh(beta))
+def _tanh_points(n: int, beta: float) -> np.ndarray:
+    s = 2.0 * np.arange(n + 1) / n - 1.0
+    p = 0.5 * (1.0 + np.tanh(beta * s) / np.tanh(beta))
+    p[0], p[-1] = 0.0, 1.0
+    return p
 
+
+def tanh_beta(n: int, ratio: float) -> float:
+    """Stretching parameter beta of x = (1 + tanh(beta (2i/n - 1))/tanh beta)/2 giving a
+    wall growth ratio h1/h0 = ratio on n cells."""
     def growth(beta):
-        p = pts(beta)
+        p = _tanh_points(n, beta)
         return (p[2] - p[1]) / (p[1] - p[0])
-
-    if ratio <= 1.0:
-        return np.linspace(0.0, 1.0, n + 1)
-    lo, hi = 1e-6, 20.0
+    lo, hi = 1e-6, 12.0
     for _ in range(200):
         mid = 0.5 * (lo + hi)
         if growth(mid) < ratio:
             lo = mid
         else:
             hi = mid
-    p = pts(0.5 * (lo + hi))
-    p[0], p[-1] = 0.0, 1.0
-    return p
+    return 0.5 * (lo + hi)
+
+
+def tanh_cluster(n: int, ratio: float, beta: Optional[float] = None) -> np.ndarray:
+    """n+1 points on [0,1], tanh-clustered at both ends: wall growth ratio h1/h0 = ratio,
+    or the given stretching parameter beta."""
+    if beta is None:
+        if ratio <= 1.0:
+            return np.linspace(0.0, 1.0, n + 1)
+        beta = tanh_beta(n, ratio)
+    return _tanh_points(n, beta)
 
 
 def solve_geometric_ratio(h0: float, n: int, length: float) -> float:
@@ -194,11 +203,12 @@ def couette(nx: int = 16, ny: int = 16, U: float = 0.1, tri: bool = False,
 
 
 def cavity(n: int = 100, ratio: float = 1.08, jitter: float = 0.2, seed: int = 0,
-           lid_u: float = 0.1, tri: bool = True) -> RawMesh:
+           lid_u: float = 0.1, tri: bool = True, beta: Optional[float] = None) -> RawMesh:
     """Lid-driven square cavity (Section 3.2): tanh wall clustering with growth ratio
-    `ratio`, quads split into triangles along the (i,j)-(i+1,j+1) diagonal, interior
-    nodes jittered by +-`jitter` x local spacing from `seed`.  Top wall moves at lid_u."""
-    xs = tanh_cluster(n, ratio); ys = xs.copy()
+    `ratio` (or stretching parameter `beta`), quads split into triangles along the
+    (i,j)-(i+1,j+1) diagonal, interior nodes jittered by +-`jitter` x local spacing
+    from `seed`.  Top wall moves at lid_u."""
+    xs = tanh_cluster(n, ratio, beta); ys = xs.copy()
     nodes = _structured_nodes(xs, ys)
     ptr, cells = _rect_cells(n, n, tri)
     rng = np.random.default_rng(seed)
@@ -455,6 +465,13 @@ def two_cylinders(nr: int = 128, nt: int = 256, spacing: float = 3.0, r0: float 
 
 def cell_count_cavity(n: int) -> int:
     return 2 * n * n
+
+
+def streaming_cavity(n: int = 2048, seed: int = 0, lid_u: float = 0.1) -> RawMesh:
+    """The 100 x 100 cavity's tanh mapping (growth 1.08 at 100 cells) refined to
+    n x n, split and jittered like it: 2 n^2 triangles, far larger than the
+    on-chip caches (the bandwidth-roofline workload)."""
+    return cavity(n=n, beta=tanh_beta(100, 1.08), jitter=0.2, seed=seed, lid_u=lid_u)
 
 
 def random_instance(rng: np.random.Generator, n_cells: int, kind: Optional[str] = None):

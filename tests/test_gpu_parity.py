@@ -203,7 +203,7 @@ def test_graph_and_direct_launches_bitwise(F):
 def test_schedules_do_not_change_results(F, scheme):
     m = mg.cavity(n=22, jitter=0.2, seed=13)
     outs = []
-    for block, x in [(256, True), (64, False), (128, True), (512, False)]:
+    for block, x in [(256, True), (64, False), (128, True), (256, False)]:
         mesh = F.Mesh(m)
         s = F.Solver(mesh, F.make_params(tau=3e-4, scheme=scheme))
         s.set_schedule(block, x)
@@ -217,13 +217,15 @@ def test_schedules_do_not_change_results(F, scheme):
 def test_checkpoint_restore_bitwise(F, scheme):
     m = mg.cavity(n=16, jitter=0.2, seed=14)
     mesh = F.Mesh(m)
-    a = F.Solver(mesh, F.make_params(tau=1e-3, scheme=scheme))
+    prm = dict(tau=0.01, dt=0.002, scheme=scheme)     # AB2 needs dt below tau (Section 3.1)
+    a = F.Solver(mesh, F.make_params(**prm))
     a.step(60)
     ref = a.f
-    b = F.Solver(mesh, F.make_params(tau=1e-3, scheme=scheme))
+    assert np.all(np.isfinite(ref))
+    b = F.Solver(mesh, F.make_params(**prm))
     b.step(25)
     ck = b.checkpoint()
-    c = F.Solver(mesh, F.make_params(tau=1e-3, scheme=scheme))
+    c = F.Solver(mesh, F.make_params(**prm))
     c.restore(ck)
     c.step(35)
     assert np.array_equal(c.f, ref)
@@ -297,7 +299,7 @@ def test_cylinder_cfg3_full_size_vs_stored_oracle(F):
 
 def test_streaming_size_mesh_invariants(F):
     """8.4M triangles (the roofline workload): rest state preserved, mass conserved."""
-    m = mg.cavity(n=2048, ratio=1.08, jitter=0.2, seed=0, lid_u=0.0)
+    m = mg.streaming_cavity(n=2048, lid_u=0.0)
     mesh = F.Mesh(m)
     s = F.Solver(mesh, F.make_params(tau=3e-5, scheme="euler", storage="fp32dev"))
     st0 = s.stats()
