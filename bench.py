@@ -1,16 +1,22 @@
 """Throughput benchmark of the FVLBM time step on one MI355X.
 
-Headline workload: lid-driven cavity, Re = 1000, U = 0.1, 20,000 jittered
-triangles from a 100 x 100 tanh-clustered grid (growth 1.08, seed 0),
-four-stage RK, FP32 storage, dt from CFL 0.5.  One step = one full RK step
-(four RHS evaluations) over all cells; the metric is M cell-updates/s.
+Headline workload (the metric's configuration): lid-driven cavity, Re = 1000,
+U = 0.1, 20,000 jittered triangles from a 100 x 100 tanh-clustered grid
+(growth 1.08, seed 0), four-stage RK, FP32 storage (deviations from the rest
+equilibrium), dt from CFL 0.5.  One step = one full RK step (four RHS
+evaluations) over all cells; the metric is M cell-updates/s.
 
-Prints one JSON line.  Extra objects:
-  roofline      the RK stage kernel against the HBM peak (algorithmic bytes per
-                launch / average launch duration, HIP events on the solver's stream)
+Prints one JSON line.  Besides the contract fields:
+  roofline      the RK stage kernel against the HBM peak: algorithmic bytes per
+                launch (see the design notes) / average launch duration, timed
+                with HIP events on the solver's stream over the timed region
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload
-  streaming     the same kernel on an 8.4M-triangle mesh that does not fit the
-                on-chip caches (honest HBM fraction), Euler and RK4
+  streaming     the same kernel on 8.4M triangles (larger than the on-chip
+                caches): the honest HBM fraction, Euler and four-stage RK
+  batched       64 seeded instances (2k-200k cells) advanced together by the
+                batched, graph-replayed, autotuned path with FP16-deviation
+                storage, next to the same instances run one at a time on the
+                plain single-instance FP32 path
 """
 from __future__ import annotations
 
@@ -26,59 +32,93 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per cell (see the design notes): state read/write + compact mesh
-MESH_BYTES = {3: 60, 4: 72}           # per RHS evaluation
-STATE_BYTES = {"euler": 18, "rk4": 99}  # x bytes per stored value, per cell-update
+# Algorithmic bytes per cell-update: the state a step must read and write plus
+# one read of a compact mesh description per RHS evaluation (60 B per
+# triangle, 72 B per quadrilateral).
+MESH_BYTES = {3: 60, 4: 72}
+STATE_VALUES = {"euler": 18, "rk4": 99}   # stored values moved per cell-update
 
 
 def alg_bytes_per_update(nf: int, scheme: str, sbytes: int) -> float:
     n_rhs = 4 if scheme == "rk4" else 1
-    return STATE_BYTES[scheme] * sbytes + n_rhs * MESH_BYTES[nf]
+    return STATE_VALUES[scheme] * sbytes + n_rhs * MESH_BYTES[nf]
 
 
-def timed_run(F, solver, steps: int, warmup: int, stream):
+def events_time(stream, fn):
     import torch
-    solver.step(warmup)
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    solver.step(steps)
-    end.record(stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    fn()
+    b.record(stream)
     torch.cuda.synchronize()
-    return start.elapsed_time(end) / 1e3
+    return a.elapsed_time(b) / 1e3
 
 
-def cpu_baseline(mesh_raw, tau, scheme, target_s=12.0):
+def cpu_baseline(inst, scheme="rk4", target_s=12.0):
     from oracle import oracle as O
-    o = O.Oracle(mesh_raw, tau=tau, cfl=0.5, u_ref=0.1, scheme=scheme)
+    o = O.Oracle(inst.mesh, tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme=scheme)
     o.init()
     t0 = time.perf_counter(); o.step(1); t1 = time.perf_counter()
-    per = max(t1 - t0, 1e-4)
-    n = max(2, int(target_s / per))
+    n = max(2, int(target_s / max(t1 - t0, 1e-4)))
     t0 = time.perf_counter(); o.step(n); t1 = time.perf_counter()
-    return dict(value=mesh_raw.n_cells * n / (t1 - t0) / 1e6, unit="M cell-updates/s", cores=1,
-                kind="oracle", sample=f"{n} {scheme} steps of the same {mesh_raw.n_cells}-cell mesh (FP64, 1 thread)")
+    return dict(value=round(inst.n_cells * n / (t1 - t0) / 1e6, 4), unit="M cell-updates/s", cores=1,
+                kind="oracle",
+                sample=f"{n} four-stage RK steps of the same {inst.n_cells}-cell cavity (FP64, one thread)")
 
 
-def streaming(F, mg, stream, schemes=("euler", "rk4"), n=2048, steps=None):
+def make_solver(F, inst, scheme, storage, reorder=None):
+    mesh = F.Mesh(inst.mesh, reorder=F.REORDER_HILBERT if reorder is None else reorder)
+    s = F.Solver(mesh, F.make_params(tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme=scheme,
+                                     storage=storage, u_dev=inst.u0),
+                 u=np.tile(np.asarray(inst.u0, float), (inst.n_cells, 1)))
+    return mesh, s
+
+
+def streaming(F, W, stream):
     out = {}
-    m = mg.streaming_cavity(n=n)
-    mesh = F.Mesh(m, reorder=F.REORDER_RCM)
+    m = W.streaming()
+    mesh = F.Mesh(m, reorder=F.REORDER_HILBERT)
     nf = mesh.info()["nf"]
-    for scheme in schemes:
-        k = steps or (20 if scheme == "euler" else 5)
+    for scheme, k in (("euler", 20), ("rk4", 5)):
         s = F.Solver(mesh, F.make_params(tau=3e-5, scheme=scheme, storage="fp32dev"))
-        el = timed_run(F, s, k, 2, stream)
+        s.autotune(4)
+        el = events_time(stream, lambda: s.step(k))
         n_launch = k * (4 if scheme == "rk4" else 1)
         t_launch = el / n_launch
         alg = alg_bytes_per_update(nf, scheme, 4) / (4 if scheme == "rk4" else 1) * m.n_cells
-        out[scheme] = dict(cells=m.n_cells, steps=k, M_cell_updates_per_s=m.n_cells * k / el / 1e6,
-                           launch_ms=t_launch * 1e3, achieved_GBs=alg / t_launch / 1e9,
-                           frac=alg / t_launch / 1e9 / HBM_PEAK_GBS)
+        out[scheme] = dict(cells=m.n_cells, steps=k, M_cell_updates_per_s=round(m.n_cells * k / el / 1e6, 1),
+                           launch_ms=round(t_launch * 1e3, 4), achieved_GBs=round(alg / t_launch / 1e9, 1),
+                           frac=round(alg / t_launch / 1e9 / HBM_PEAK_GBS, 4), schedule=s.get_schedule())
         s.close()
     mesh.close()
     return out
+
+
+def batched(F, W, stream, steps=1000, single_steps=100):
+    insts = W.batched()
+    total = sum(i.n_cells for i in insts)
+    pairs = [make_solver(F, i, "rk4", "fp16dev") for i in insts]
+    b = F.Batch([s for _, s in pairs])
+    tune_ms = b.autotune(32)
+    el = events_time(stream, lambda: b.step(steps))
+    rec = dict(instances=len(insts), cells=total, steps=steps, storage="fp16dev", scheme="rk4",
+               M_cell_updates_per_s=round(total * steps / el / 1e6, 1), ms_per_step=round(el * 1e3 / steps, 4),
+               tuned_ms_per_step=round(tune_ms, 4))
+    b.close()
+    for _, s in pairs:
+        s.close()
+    # the plain single-instance FP32 path on the same instances, one after another
+    t = 0.0
+    for inst in insts:
+        mesh, s = make_solver(F, inst, "rk4", "fp32dev")
+        s.step(8)
+        t += events_time(stream, lambda: s.step(single_steps))
+        s.close(); mesh.close()
+    rec["single_fp32_M_cell_updates_per_s"] = round(total * single_steps / t / 1e6, 1)
+    rec["speedup_vs_single_fp32"] = round(rec["M_cell_updates_per_s"] / rec["single_fp32_M_cell_updates_per_s"], 2)
+    return rec
 
 
 def main():
@@ -87,62 +127,65 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="fp32dev")
+    ap.add_argument("--only", choices=["all", "headline", "streaming", "batched"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-streaming", action="store_true")
-    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this library has no multi-GPU path; "
-              "see the design notes for how the step would shard.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
+              "the design notes describe how the step would shard.", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_1812_00390_amd import fvlbm as F
-    from paper_1812_00390_amd import meshgen as mg
+    from paper_1812_00390_amd import workloads as W
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    U, Re = 0.1, 1000.0
-    tau = 3 * U * 1.0 / Re
-    m = mg.cavity(n=100, ratio=1.08, jitter=0.2, seed=0, lid_u=U)
-    mesh = F.Mesh(m, reorder=F.REORDER_RCM)
-    nf = mesh.info()["nf"]
-    s = F.Solver(mesh, F.make_params(tau=tau, cfl=0.5, u_ref=U, scheme="rk4", storage=args.storage))
-    if args.block:
-        s.set_schedule(args.block, True)
-    el = timed_run(F, s, args.steps, args.warmup, stream)
-    n = m.n_cells
-    value = n * args.steps / el / 1e6
-    sbytes = 2 if args.storage == "fp16dev" else 4
-    t_launch = el / (4 * args.steps)
-    alg_launch = alg_bytes_per_update(nf, "rk4", sbytes) / 4 * n
-    rho, u, st = s.macros()
-    rec = {
-        "metric": "M cell-updates/s (D2Q9, FP32)",
-        "value": round(value, 3),
-        "unit": "M cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": el * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if args.storage != "fp16dev" else "f32 (fp16 storage)",
-        "data": "synthetic",
-        "config": {"workload": "lid-driven cavity Re=1000, 20000 jittered triangles (100x100 tanh 1.08, seed 0), "
-                               "RK4, CFL 0.5", "cells": n, "scheme": "rk4", "storage": args.storage,
-                   "dt": s.dt, "schedule": list(s.get_schedule())},
-        "roofline": {"bound": "hbm", "achieved": round(alg_launch / t_launch / 1e9, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(alg_launch / t_launch / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_stage<3,FP32> (one RK stage)",
-                     "alg_bytes_per_launch": alg_launch, "launch_us": t_launch * 1e6},
-        "check": {"max_u": float(np.abs(u).max()), "mass": st["mass"]},
-    }
-    if not args.no_streaming:
-        rec["streaming"] = streaming(F, mg, stream)
-    if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(m, tau, "rk4")
+    rec = {}
+    if args.only in ("all", "headline"):
+        inst = W.cavity20k()
+        mesh, s = make_solver(F, inst, "rk4", args.storage)
+        nf = mesh.info()["nf"]
+        if not args.no_autotune:
+            s.autotune(64)
+        s.step(args.warmup)
+        el = events_time(stream, lambda: s.step(args.steps))
+        n = inst.n_cells
+        sbytes = 2 if args.storage == "fp16dev" else 4
+        t_launch = el / (4 * args.steps)
+        alg_launch = alg_bytes_per_update(nf, "rk4", sbytes) / 4 * n
+        rho, u, st = s.macros()
+        rec.update({
+            "metric": "M cell-updates/s (D2Q9, FP32)",
+            "value": round(n * args.steps / el / 1e6, 3),
+            "unit": "M cell-updates/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": round(el * 1e3 / args.steps, 5),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32" if args.storage != "fp16dev" else "f32 compute, fp16 storage",
+            "data": "synthetic",
+            "config": {"workload": "lid-driven cavity Re=1000 U=0.1, 20000 jittered triangles "
+                                   "(100x100 tanh growth 1.08, seed 0), four-stage RK, CFL 0.5",
+                       "cells": n, "scheme": "rk4", "storage": args.storage, "dt": s.dt,
+                       "schedule": s.get_schedule()},
+            "roofline": {"bound": "hbm", "achieved": round(alg_launch / t_launch / 1e9, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg_launch / t_launch / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": None, "kernel": "k_tile<3> (one RK stage)",
+                         "alg_bytes_per_launch": alg_launch, "launch_us": round(t_launch * 1e6, 3)},
+            "check": {"max_u": float(np.abs(u).max()), "mass": st["mass"]},
+        })
+        s.close(); mesh.close()
+        if not args.no_cpu_baseline:
+            rec["cpu_baseline"] = cpu_baseline(inst)
+    if args.only in ("all", "streaming"):
+        rec["streaming"] = streaming(F, W, stream)
+    if args.only in ("all", "batched"):
+        rec["batched"] = batched(F, W, stream)
     print(json.dumps(rec))
 
 

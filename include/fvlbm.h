@@ -171,11 +171,26 @@ fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_b
 fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps);
 void fvlbm_batch_destroy(fvlbm_batch *b);
 
-/* Launch schedule (block size in cells, and whether block ids are spread so
- * that neighbouring tiles share an XCD's L2).  set returns FVLBM_E_ARG for an
- * unsupported block size (64, 128, 256, 512 are supported). */
-fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap);
-fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap);
+/* Launch schedule: tile size in cells (one workgroup per tile: 64, 128, 256 or
+ * 512), whether tiles are renumbered so that each XCD walks one contiguous
+ * range of tiles (neighbouring tiles then share that XCD's L2), and whether a
+ * persistent grid sized to the resident capacity walks the tile list instead
+ * of one workgroup per tile.  A schedule never changes the per-cell
+ * arithmetic: results are bitwise identical under every schedule.
+ * Errors: FVLBM_E_ARG (unsupported tile size, or tile plus halo do not fit
+ * the 64 KiB LDS of a workgroup). */
+fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap, int32_t persistent);
+fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap, int32_t *persistent);
+fvlbm_status fvlbm_batch_set_schedule(fvlbm_batch *b, int32_t block, int32_t xcd_remap, int32_t persistent);
+
+/* Autotuner: times every supported schedule for trial_steps steps (HIP
+ * events on the solver's or batch's stream), keeps the fastest, and restores
+ * the state, step counters and residual snapshots to what they were, so the
+ * solve continues exactly as without tuning.  best_ms (may be NULL) receives
+ * the chosen schedule's time per step.  Syncs the stream.
+ * Errors: FVLBM_E_ARG, FVLBM_E_NOMEM, FVLBM_E_DEVICE. */
+fvlbm_status fvlbm_autotune(fvlbm_solver *s, int32_t trial_steps, double *best_ms);
+fvlbm_status fvlbm_batch_autotune(fvlbm_batch *b, int32_t trial_steps, double *best_ms);
 
 const char *fvlbm_last_error(void);
 

@@ -89,6 +89,7 @@ struct fvlbm_batch {
     InstDesc *desc_dev = nullptr;     // [N_KINDS][n]
     UnitTable ut[2];                  // by face-slot count (3, 4)
     int hmax[2] = {0, 0};
+    int h1max[2] = {0, 0};
     int scheme = 0, storage = 0;
     hipStream_t stream = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
@@ -97,6 +98,8 @@ struct fvlbm_batch {
 
 namespace {
 
+// Callers synchronize the stream first: a graph exec, descriptor array or
+// unit table must not be destroyed while queued work may still use it.
 void free_graphs(std::map<std::pair<int, int>, hipGraphExec_t> &g) {
     for (auto &kv : g) hipGraphExecDestroy(kv.second);
     g.clear();
@@ -123,7 +126,7 @@ InstDesc base_desc(fvlbm_solver *s, const TileTables *tt) {
     const MeshDev &m = s->mesh->dev;
     InstDesc d{};
     d.vxy = m.vxy; d.dxy = m.dxy; d.inva = m.inva; d.minv = m.minv;
-    d.lnbr = tt->lnbr; d.halo_ptr = tt->halo_ptr; d.halo_idx = tt->halo_idx; d.halo_code = tt->halo_code;
+    d.lnbr = tt->lnbr; d.hdr = tt->hdr; d.halo_idx = tt->halo_idx; d.halo_code = tt->halo_code;
     d.n_cells = m.n_cells; d.np = m.np;
     d.inv_tau = (float)(1.0 / s->p.tau);
     d.ref = s->ref;
@@ -222,7 +225,7 @@ hipGraphExec_t solver_graph(fvlbm_solver *s, int cur, int nsteps) {
             ab[0] = new char[64];
             hipGraphNode_t node;
             ok = add_stage_node(g, &node, prev ? &prev : nullptr, prev ? 1 : 0, s->desc_dev + k, s->ut,
-                                s->mesh->dev.nf, s->p.storage, s->sched.xcd_remap, s->tiles->hmax, ab) == hipSuccess;
+                                s->mesh->dev.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->hmax, s->tiles->h1max, ab) == hipSuccess;
             prev = node;
             if (!ok) break;
         }
@@ -257,7 +260,7 @@ fvlbm_status enqueue_steps(fvlbm_solver *s, int64_t n) {
         }
         step_kinds(s->p.scheme, s->cur, s->have_prev, ks);
         for (int k : ks) {
-            hipError_t e = launch_stage(s->desc_dev + k, s->ut, nf, s->p.storage, s->sched.xcd_remap, s->tiles->hmax, s->stream);
+            hipError_t e = launch_stage(s->desc_dev + k, s->ut, nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->hmax, s->tiles->h1max, s->stream);
             if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("stage launch failed: ") + hipGetErrorString(e));
         }
         advance_position(s->p.scheme, s->cur, s->have_prev);
@@ -278,6 +281,7 @@ fvlbm_status upload_descs(fvlbm_solver *s) {
 }  // namespace
 
 fvlbm_solver::~fvlbm_solver() {
+    hipStreamSynchronize(stream);
     free_graphs(graphs);
     if (desc_dev) hipFree(desc_dev);
     if (ut.units) hipFree(ut.units);
@@ -332,6 +336,7 @@ double fvlbm_mesh_cfl_length(const fvlbm_mesh *mesh) { return mesh ? mesh->dev.c
 
 void fvlbm_mesh_destroy(fvlbm_mesh *mesh) {
     if (!mesh) return;
+    hipDeviceSynchronize();          // solvers on any stream may still read the mesh arrays
     free_tiles(mesh->dev);
     if (mesh->dev.block) hipFree(mesh->dev.block);
     delete mesh;
@@ -381,7 +386,7 @@ fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const doub
         std::string err;
         fvlbm_status tst = get_tiles(mesh->dev, s->sched.block, &s->tiles, err);
         if (tst != FVLBM_OK) return fail(tst, err);
-        if (stage_lds_bytes(s->sched.block, s->tiles->hmax) > 65536) {
+        if (stage_lds_bytes(s->sched.block, s->tiles->hmax, s->tiles->h1max) > 65536) {
             s->sched.block = 128;
             tst = get_tiles(mesh->dev, s->sched.block, &s->tiles, err);
             if (tst != FVLBM_OK) return fail(tst, err);
@@ -506,7 +511,7 @@ fvlbm_status fvlbm_rhs(fvlbm_solver *s, double *rhs) {
     const MeshDev &m = s->mesh->dev;
     double *out = reinterpret_cast<double *>(s->buf + s->L.out);
     int k = s->cur == 0 ? RH0 : (s->cur == 1 ? RH1 : RH2);
-    hipError_t e = launch_stage(s->desc_dev + k, s->ut, m.nf, s->p.storage, s->sched.xcd_remap, s->tiles->hmax, s->stream);
+    hipError_t e = launch_stage(s->desc_dev + k, s->ut, m.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->hmax, s->tiles->h1max, s->stream);
     if (e == hipSuccess) e = launch_rhs_out(reinterpret_cast<float *>(s->buf + s->L.r32), m.n_cells, m.np, m.perm_dev, out, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(rhs, out, (size_t)Q * m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -558,15 +563,17 @@ fvlbm_status fvlbm_restore(fvlbm_solver *s, const void *host_buf, size_t bytes) 
     return FVLBM_OK;
 }
 
-fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap) {
+fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap, int32_t persistent) {
     if (!s || (block != 64 && block != 128 && block != 256 && block != 512)) return fail(FVLBM_E_ARG, "unsupported block size");
     const TileTables *tt = nullptr;
     std::string err;
     fvlbm_status st = get_tiles(s->mesh->dev, block, &tt, err);
     if (st != FVLBM_OK) return fail(st, err);
-    if (stage_lds_bytes(block, tt->hmax) > 65536) return fail(FVLBM_E_ARG, "tile and halo do not fit the LDS at this block size");
+    if (stage_lds_bytes(block, tt->hmax, tt->h1max) > 65536) return fail(FVLBM_E_ARG, "tile and halo do not fit the LDS at this block size");
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "stream synchronize failed");
     s->sched.block = block;
     s->sched.xcd_remap = xcd_remap ? 1 : 0;
+    s->sched.persistent = persistent ? 1 : 0;
     s->tiles = tt;
     free_graphs(s->graphs);
     st = make_units({{0, s->mesh->dev.n_cells}}, block, s->ut);
@@ -574,14 +581,56 @@ fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_rema
     return upload_descs(s);
 }
 
-fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap) {
-    if (!s || !block || !xcd_remap) return fail(FVLBM_E_ARG, "null argument");
+fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap, int32_t *persistent) {
+    if (!s || !block || !xcd_remap || !persistent) return fail(FVLBM_E_ARG, "null argument");
     *block = s->sched.block;
     *xcd_remap = s->sched.xcd_remap;
+    *persistent = s->sched.persistent;
     return FVLBM_OK;
 }
 
 // ------------------------------------------------------------------ batch
+
+namespace {
+// (Re)build a batch's descriptors and unit tables for its schedule.
+fvlbm_status batch_build(fvlbm_batch *b) {
+    const int n = (int)b->members.size();
+    std::vector<InstDesc> all((size_t)N_KINDS * n);
+    int hmax[2] = {0, 0}, h1max[2] = {0, 0};
+    for (int i = 0; i < n; i++) {
+        fvlbm_solver *s = b->members[i];
+        const TileTables *tt = nullptr;
+        std::string err;
+        fvlbm_status st = get_tiles(s->mesh->dev, b->sched.block, &tt, err);
+        if (st != FVLBM_OK) return fail(st, err);
+        int t = s->mesh->dev.nf - 3;
+        hmax[t] = std::max(hmax[t], tt->hmax);
+        h1max[t] = std::max(h1max[t], tt->h1max);
+        InstDesc d[N_KINDS];
+        fill_descs(s, tt, d);
+        for (int k = 0; k < N_KINDS; k++) all[(size_t)k * n + i] = d[k];
+    }
+    for (int t = 0; t < 2; t++)
+        if (stage_lds_bytes(b->sched.block, hmax[t], h1max[t]) > 65536)
+            return fail(FVLBM_E_ARG, "batch tiles do not fit the LDS at this block size");
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "stream synchronize failed");
+    free_graphs(b->graphs);
+    if (b->desc_dev) { hipFree(b->desc_dev); b->desc_dev = nullptr; }
+    if (hipMalloc(&b->desc_dev, all.size() * sizeof(InstDesc)) != hipSuccess) return fail(FVLBM_E_NOMEM, "batch descriptor allocation failed");
+    if (hipMemcpy(b->desc_dev, all.data(), all.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FVLBM_E_DEVICE, "batch descriptor upload failed");
+    for (int t = 0; t < 2; t++) {
+        b->hmax[t] = hmax[t];
+        b->h1max[t] = h1max[t];
+        std::vector<std::pair<int, int>> inst;
+        for (int i = 0; i < n; i++)
+            if (b->members[i]->mesh->dev.nf == 3 + t) inst.push_back({i, b->members[i]->mesh->dev.n_cells});
+        fvlbm_status st = make_units(inst, b->sched.block, b->ut[t]);
+        if (st != FVLBM_OK) return st;
+    }
+    return FVLBM_OK;
+}
+}  // namespace
 
 fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_batch **out) {
     if (!solvers || n <= 0 || !out) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_batch_create");
@@ -600,33 +649,31 @@ fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_b
         if (s->p.scheme == FVLBM_SCHEME_AB2 && !s->have_prev) return fail(FVLBM_E_PARAM, "AB2 members must have taken their first step");
         b->members.push_back(s);
     }
-    std::vector<InstDesc> all((size_t)N_KINDS * n);
-    for (int i = 0; i < n; i++) {
-        fvlbm_solver *s = b->members[i];
-        const TileTables *tt = nullptr;
-        std::string err;
-        fvlbm_status st = get_tiles(s->mesh->dev, b->sched.block, &tt, err);
-        if (st != FVLBM_OK) return fail(st, err);
-        int t = s->mesh->dev.nf - 3;
-        b->hmax[t] = std::max(b->hmax[t], tt->hmax);
-        InstDesc d[N_KINDS];
-        fill_descs(s, tt, d);
-        for (int k = 0; k < N_KINDS; k++) all[(size_t)k * n + i] = d[k];
+    // the first member's tile size, or the largest smaller one whose tiles fit the LDS
+    fvlbm_status st = FVLBM_E_ARG;
+    for (int T : {b->sched.block, 256, 128, 64}) {
+        if (T > b->sched.block) continue;
+        b->sched.block = T;
+        st = batch_build(b.get());
+        if (st != FVLBM_E_ARG) break;
     }
-    for (int t = 0; t < 2; t++)
-        if (stage_lds_bytes(b->sched.block, b->hmax[t]) > 65536) return fail(FVLBM_E_PARAM, "batch tiles do not fit the LDS");
-    if (hipMalloc(&b->desc_dev, all.size() * sizeof(InstDesc)) != hipSuccess) return fail(FVLBM_E_NOMEM, "batch descriptor allocation failed");
-    if (hipMemcpy(b->desc_dev, all.data(), all.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess)
-        return fail(FVLBM_E_DEVICE, "batch descriptor upload failed");
-    for (int t = 0; t < 2; t++) {
-        std::vector<std::pair<int, int>> inst;
-        for (int i = 0; i < n; i++)
-            if (b->members[i]->mesh->dev.nf == 3 + t) inst.push_back({i, b->members[i]->mesh->dev.n_cells});
-        fvlbm_status st = make_units(inst, b->sched.block, b->ut[t]);
-        if (st != FVLBM_OK) return st;
-    }
+    if (st != FVLBM_OK) return st;
     *out = b.release();
     return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_batch_set_schedule(fvlbm_batch *b, int32_t block, int32_t xcd_remap, int32_t persistent) {
+    if (!b || (block != 64 && block != 128 && block != 256 && block != 512)) return fail(FVLBM_E_ARG, "unsupported block size");
+    Schedule old = b->sched;
+    b->sched.block = block;
+    b->sched.xcd_remap = xcd_remap ? 1 : 0;
+    b->sched.persistent = persistent ? 1 : 0;
+    fvlbm_status st = batch_build(b);
+    if (st != FVLBM_OK) {
+        b->sched = old;
+        batch_build(b);
+    }
+    return st;
 }
 
 namespace {
@@ -654,7 +701,7 @@ hipGraphExec_t batch_graph(fvlbm_batch *b, int cur, int nsteps) {
                 hipGraphNode_t node;
                 ok = add_stage_node(g, &node, prev.empty() ? nullptr : prev.data(), (int)prev.size(),
                                     b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
-                                    b->sched.xcd_remap, b->hmax[t], ab) == hipSuccess;
+                                    b->sched.xcd_remap, b->sched.persistent, b->hmax[t], b->h1max[t], ab) == hipSuccess;
                 now.push_back(node);
             }
             prev = now;
@@ -670,8 +717,10 @@ hipGraphExec_t batch_graph(fvlbm_batch *b, int cur, int nsteps) {
 }
 }  // namespace
 
-fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps) {
-    if (!b || n_steps < 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_batch_step");
+}  // extern "C"
+
+namespace {
+fvlbm_status batch_enqueue(fvlbm_batch *b, int64_t n_steps, bool snapshots) {
     const int n = (int)b->members.size();
     int64_t left = n_steps;
     std::vector<int> ks;
@@ -690,7 +739,7 @@ fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps) {
                 for (int k : ks)
                     for (int t = 0; t < 2; t++) {
                         hipError_t e = launch_stage(b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
-                                                    b->sched.xcd_remap, b->hmax[t], b->stream);
+                                                    b->sched.xcd_remap, b->sched.persistent, b->hmax[t], b->h1max[t], b->stream);
                         if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
                     }
                 advance_position(b->scheme, c, hp);
@@ -701,7 +750,7 @@ fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps) {
             for (int64_t k = 0; k < chunk; k++) advance_position(s->p.scheme, s->cur, s->have_prev);
             s->steps += chunk;
             // snapshot when a lag boundary is crossed exactly at the chunk end
-            if (s->steps / s->lag != before / s->lag && s->steps % s->lag == 0) {
+            if (snapshots && s->steps / s->lag != before / s->lag && s->steps % s->lag == 0) {
                 if (take_snapshot(s) != hipSuccess) return fail(FVLBM_E_DEVICE, "snapshot failed");
             }
         }
@@ -710,8 +759,126 @@ fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps) {
     return FVLBM_OK;
 }
 
+// Device copy of what a step reads and writes (the current distributions and
+// the AB2 history) plus the host-side position, for the autotuner.
+struct Saved {
+    fvlbm_solver *s = nullptr;
+    char *dev = nullptr;
+    size_t fb = 0, rb = 0;
+    int cur = 0;
+    int64_t steps = 0;
+    bool have_prev = false;
+};
+
+fvlbm_status save_state(fvlbm_solver *s, Saved &sv) {
+    const MeshDev &m = s->mesh->dev;
+    sv.s = s;
+    sv.fb = (size_t)Q * m.np * storage_bytes(s->p.storage);
+    sv.rb = s->p.scheme == FVLBM_SCHEME_AB2 ? (size_t)Q * m.np * sizeof(float) : 0;
+    if (hipMalloc(&sv.dev, sv.fb + sv.rb) != hipSuccess) return fail(FVLBM_E_NOMEM, "autotune state copy allocation failed");
+    hipError_t e = hipMemcpyAsync(sv.dev, fptr(s, s->cur), sv.fb, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && sv.rb) e = hipMemcpyAsync(sv.dev + sv.fb, s->buf + s->L.r32, sv.rb, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, "autotune state copy failed");
+    sv.cur = s->cur;
+    sv.steps = s->steps;
+    sv.have_prev = s->have_prev;
+    return FVLBM_OK;
+}
+
+fvlbm_status restore_state(Saved &sv) {
+    fvlbm_solver *s = sv.s;
+    hipError_t e = hipMemcpyAsync(fptr(s, sv.cur), sv.dev, sv.fb, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && sv.rb) e = hipMemcpyAsync(s->buf + s->L.r32, sv.dev + sv.fb, sv.rb, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    hipFree(sv.dev);
+    sv.dev = nullptr;
+    s->cur = sv.cur;
+    s->steps = sv.steps;
+    s->have_prev = sv.have_prev;
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, "autotune state restore failed");
+    return FVLBM_OK;
+}
+
+// Times `steps` steps of `run` on `stream` with HIP events (after a warm-up
+// that also builds the step graphs); returns ms per step or -1.
+template <class Run>
+double time_steps(hipStream_t stream, int steps, Run run) {
+    if (run(GRAPH_CHUNK) != FVLBM_OK) return -1;
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    hipEventRecord(a, stream);
+    fvlbm_status st = run(steps);
+    hipEventRecord(b, stream);
+    hipEventSynchronize(b);
+    float ms = 0;
+    hipEventElapsedTime(&ms, a, b);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return st == FVLBM_OK ? ms / steps : -1;
+}
+
+const int TUNE_BLOCKS[] = {64, 128, 256, 512};
+}  // namespace
+
+extern "C" {
+
+fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps) {
+    if (!b || n_steps < 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_batch_step");
+    return batch_enqueue(b, n_steps, true);
+}
+
+fvlbm_status fvlbm_autotune(fvlbm_solver *s, int32_t trial_steps, double *best_ms) {
+    if (!s || trial_steps <= 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_autotune");
+    if (s->failed) return fail(FVLBM_E_STATE, "solver is in an error state");
+    if (s->p.scheme == FVLBM_SCHEME_AB2 && !s->have_prev) return fail(FVLBM_E_STATE, "take the first AB2 step before tuning");
+    Saved sv;
+    fvlbm_status st = save_state(s, sv);
+    if (st != FVLBM_OK) return st;
+    Schedule best = s->sched;
+    double best_t = 1e300;
+    for (int T : TUNE_BLOCKS)
+        for (int x = 0; x < 2; x++)
+            for (int ps = 0; ps < 2; ps++) {
+                if (fvlbm_set_schedule(s, T, x, ps) != FVLBM_OK) continue;
+                double t = time_steps(s->stream, trial_steps, [&](int n) { return enqueue_steps(s, n); });
+                if (t > 0 && t < best_t) { best_t = t; best = s->sched; }
+            }
+    fvlbm_set_schedule(s, best.block, best.xcd_remap, best.persistent);
+    st = restore_state(sv);
+    if (best_ms) *best_ms = best_t;
+    return st;
+}
+
+fvlbm_status fvlbm_batch_autotune(fvlbm_batch *b, int32_t trial_steps, double *best_ms) {
+    if (!b || trial_steps <= 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_batch_autotune");
+    std::vector<Saved> saved(b->members.size());
+    for (size_t i = 0; i < b->members.size(); i++) {
+        fvlbm_status st = save_state(b->members[i], saved[i]);
+        if (st != FVLBM_OK) return st;
+    }
+    Schedule best = b->sched;
+    double best_t = 1e300;
+    for (int T : TUNE_BLOCKS)
+        for (int x = 0; x < 2; x++)
+            for (int ps = 0; ps < 2; ps++) {
+                if (fvlbm_batch_set_schedule(b, T, x, ps) != FVLBM_OK) continue;
+                double t = time_steps(b->stream, trial_steps, [&](int n) { return batch_enqueue(b, n, false); });
+                if (t > 0 && t < best_t) { best_t = t; best = b->sched; }
+            }
+    fvlbm_batch_set_schedule(b, best.block, best.xcd_remap, best.persistent);
+    fvlbm_status res = FVLBM_OK;
+    for (auto &sv : saved) {
+        fvlbm_status st = restore_state(sv);
+        if (st != FVLBM_OK) res = st;
+    }
+    if (best_ms) *best_ms = best_t;
+    return res;
+}
+
 void fvlbm_batch_destroy(fvlbm_batch *b) {
     if (!b) return;
+    hipStreamSynchronize(b->stream);
     free_graphs(b->graphs);
     if (b->desc_dev) hipFree(b->desc_dev);
     for (auto &u : b->ut) if (u.units) hipFree(u.units);

@@ -53,21 +53,22 @@ struct GroupDev {
     float rho;           // rho_inf
 };
 
-// Per tile size T: cells [t*T, t*T+T) form tile t; its halo is the set of
-// face neighbours outside the tile.  Local indices: tile cell i -> i - t*T,
-// halo entry k -> T + k.
+// Per tile size T: cells [t*T, t*T+T) form tile t; ring 1 is the set of face
+// neighbours outside the tile, ring 2 the face neighbours of ring 1 outside
+// tile and ring 1.  Local indices: tile cell i -> i - t*T, ring-1 entry k ->
+// T + k, ring-2 entry k -> T + n1 + k.
 struct TileTables {
     int T = 0;
     int n_tiles = 0;
-    int hmax = 0;                // largest halo
+    int hmax = 0;                // largest n1 + n2
+    int h1max = 0;               // largest n1
     uint2 *lnbr = nullptr;       // [np] four int16 slot codes per tile cell: local index, -1-g, or LN_PAD
-    int *halo_ptr = nullptr;     // [n_tiles+1]
-    int *halo_idx = nullptr;     // cell of each halo entry
-    int *halo_code = nullptr;    // [entries][nf]: local index (< LOCAL_LIM), LOCAL_LIM + cell, -1-g, NB_PAD
+    int4 *hdr = nullptr;         // [n_tiles] {first entry in halo_idx, n1, n2, first ring-1 code}
+    int *halo_idx = nullptr;     // cells of ring 1 then ring 2, per tile
+    int *halo_code = nullptr;    // [ring-1 entries][nf]: local index, -1-g, or NB_PAD
     size_t bytes = 0;
     void *block = nullptr;
 };
-constexpr int LOCAL_LIM = 1 << 16;
 constexpr int LN_PAD = -32768;
 
 struct MeshDev {
@@ -113,9 +114,9 @@ RefDev make_ref(double rho0, double ux, double uy, double scale);
 
 // Host form of the tile tables (see TileTables).
 struct HostTiles {
-    int T = 0, n_tiles = 0, hmax = 0;
+    int T = 0, n_tiles = 0, hmax = 0, h1max = 0;
     std::vector<uint16_t> lnbr;      // [np][4]
-    std::vector<int> halo_ptr, halo_idx, halo_code;
+    std::vector<int> hdr, halo_idx, halo_code;   // hdr: [n_tiles][4]
 };
 void build_tile_tables_host(const std::vector<int> &nbr, int n, int nf, int np, int T, HostTiles &out);
 
@@ -128,7 +129,8 @@ struct InstDesc {
     const float2 *vxy, *dxy;
     const float *inva, *minv;
     const uint2 *lnbr;
-    const int *halo_ptr, *halo_idx, *halo_code;
+    const int4 *hdr;
+    const int *halo_idx, *halo_code;
     const void *src;      // state the RHS is evaluated at
     const void *base;     // f(0) of the update (== src for Euler / AB2)
     void *dst;
@@ -145,6 +147,7 @@ struct InstDesc {
 struct Schedule {
     int block = 256;
     int xcd_remap = 1;
+    int persistent = 0;
 };
 
 // Work units: (instance, tile index) per block; built for a schedule.
@@ -157,12 +160,12 @@ struct UnitTable {
 // Launch one RHS-evaluation stage over all units (one unit = one tile of
 // ut.block cells).  nf: 3 or 4; storage FVLBM_STORE_*; hmax: largest halo.
 hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                        int xcd_remap, int hmax, hipStream_t stream);
-size_t stage_lds_bytes(int T, int hmax);
+                        int xcd_remap, int persistent, int hmax, int h1max, hipStream_t stream);
+size_t stage_lds_bytes(int T, int hmax, int h1max);
 // Same as a kernel node for a graph.
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                          int xcd_remap, int hmax, void **argbuf);
+                          int xcd_remap, int persistent, int hmax, int h1max, void **argbuf);
 
 // Step 0 and conversions (FP64 host data in input order <-> device storage).
 hipError_t launch_init_eq(void *dst, int storage, int n, int np, const RefDev &ref,

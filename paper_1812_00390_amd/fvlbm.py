@@ -71,8 +71,11 @@ SIGNATURES = {
     "fvlbm_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(_vp)]),
     "fvlbm_batch_step": (C.c_int, [_vp, C.c_int64]),
     "fvlbm_batch_destroy": (None, [_vp]),
-    "fvlbm_set_schedule": (C.c_int, [_vp, C.c_int32, C.c_int32]),
-    "fvlbm_get_schedule": (C.c_int, [_vp, _ip, _ip]),
+    "fvlbm_set_schedule": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
+    "fvlbm_get_schedule": (C.c_int, [_vp, _ip, _ip, _ip]),
+    "fvlbm_batch_set_schedule": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
+    "fvlbm_autotune": (C.c_int, [_vp, C.c_int32, _dp]),
+    "fvlbm_batch_autotune": (C.c_int, [_vp, C.c_int32, _dp]),
     "fvlbm_last_error": (C.c_char_p, []),
 }
 
@@ -259,13 +262,19 @@ class Solver:
         buf = C.create_string_buffer(data, len(data))
         _check(lib().fvlbm_restore(self.h, buf, len(data)))
 
-    def set_schedule(self, block: int, xcd_remap: bool = True):
-        _check(lib().fvlbm_set_schedule(self.h, int(block), int(bool(xcd_remap))))
+    def set_schedule(self, block: int, xcd_remap: bool = True, persistent: bool = False):
+        _check(lib().fvlbm_set_schedule(self.h, int(block), int(bool(xcd_remap)), int(bool(persistent))))
 
     def get_schedule(self):
-        b, x = C.c_int32(), C.c_int32()
-        _check(lib().fvlbm_get_schedule(self.h, C.byref(b), C.byref(x)))
-        return b.value, bool(x.value)
+        b, x, p = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().fvlbm_get_schedule(self.h, C.byref(b), C.byref(x), C.byref(p)))
+        return dict(block=b.value, xcd_remap=bool(x.value), persistent=bool(p.value))
+
+    def autotune(self, trial_steps: int = 64) -> float:
+        """Pick the fastest launch schedule (state restored afterwards); returns ms per step."""
+        ms = C.c_double()
+        _check(lib().fvlbm_autotune(self.h, int(trial_steps), C.byref(ms)))
+        return ms.value
 
     def close(self):
         if getattr(self, "h", None):
@@ -291,6 +300,15 @@ class Batch:
 
     def step(self, n: int):
         _check(lib().fvlbm_batch_step(self.h, int(n)))
+
+    def set_schedule(self, block: int, xcd_remap: bool = True, persistent: bool = False):
+        _check(lib().fvlbm_batch_set_schedule(self.h, int(block), int(bool(xcd_remap)), int(bool(persistent))))
+
+    def autotune(self, trial_steps: int = 64) -> float:
+        """Pick the fastest launch schedule for the whole batch (states restored); ms per step."""
+        ms = C.c_double()
+        _check(lib().fvlbm_batch_autotune(self.h, int(trial_steps), C.byref(ms)))
+        return ms.value
 
     def close(self):
         if getattr(self, "h", None):

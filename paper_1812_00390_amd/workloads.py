@@ -1,0 +1,87 @@
+"""Seeded workload definitions (meshes plus solver parameters) for the
+benchmark and the serving loop.  Only configuration lives here; every step of
+the method runs in the HIP library.
+
+  cavity20k   lid-driven cavity, Re 1000, U 0.1, 100x100 tanh grid (growth 1.08)
+              split into 20,000 jittered triangles (seed 0); four-stage RK
+  cylinder98k O-grid 256 x 384 quads around a cylinder, h0 = 0.005 D to 30 D,
+              Re 100, u_inf 0.1; four-stage RK, free-stream storage reference
+  batched64   64 instances, cells log-uniform in [2e3, 2e5] (seed 1), half
+              jittered-triangle cavities, half O-grid cylinders, Re uniform in
+              [100, 3000], tau = 3 U L / Re per instance; four-stage RK,
+              FP16-deviation storage
+  streaming   the cavity20k tanh mapping refined to 2048 x 2048 quads, split:
+              8.4M triangles, far larger than the on-chip caches
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+from . import meshgen as mg
+
+U_REF = 0.1
+
+
+@dataclasses.dataclass
+class Instance:
+    mesh: mg.RawMesh
+    tau: float
+    u_ref: float             # CFL velocity scale
+    u0: tuple                # initial (and storage-reference) velocity
+    kind: str
+    re: float
+
+    @property
+    def n_cells(self) -> int:
+        return self.mesh.n_cells
+
+
+def cavity_instance(n: int, re: float, seed: int = 0, ratio: float = 1.08) -> Instance:
+    m = mg.cavity(n=n, ratio=ratio if n >= 20 else 1.0, jitter=0.2, seed=seed, lid_u=U_REF)
+    return Instance(m, 3.0 * U_REF * 1.0 / re, U_REF, (0.0, 0.0), "cavity", re)
+
+
+def cylinder_instance(nr: int, nt: int, re: float, h0: float = 0.005, R: float = 30.0) -> Instance:
+    h0 = min(h0, 0.5 * (R - 0.5) / nr)
+    m = mg.cylinder(nr=nr, nt=nt, R=R, h0=h0, u_inf=(U_REF, 0.0))
+    return Instance(m, 3.0 * U_REF * 1.0 / re, 2 * U_REF, (U_REF, 0.0), "cylinder", re)
+
+
+def two_cylinder_instance(nr: int, nt: int, re: float) -> Instance:
+    m = mg.two_cylinders(nr=nr, nt=nt, u_inf=(U_REF, 0.0), h0=min(0.005, 0.4 * 25.0 / nr))
+    return Instance(m, 3.0 * U_REF * 1.0 / re, 2 * U_REF, (U_REF, 0.0), "two_cylinders", re)
+
+
+def cavity20k() -> Instance:
+    return cavity_instance(100, 1000.0, seed=0)
+
+
+def cylinder98k() -> Instance:
+    return cylinder_instance(256, 384, 100.0)
+
+
+def random_instance(rng: np.random.Generator, n_cells: float, kinds=("cavity", "cylinder")) -> Instance:
+    kind = kinds[int(rng.integers(len(kinds)))]
+    re = float(rng.uniform(100.0, 3000.0))
+    if kind == "cavity":
+        n = max(6, int(round(math.sqrt(n_cells / 2.0))))
+        return cavity_instance(n, re, seed=int(rng.integers(1 << 30)))
+    if kind == "cylinder":
+        nr = max(6, int(round(math.sqrt(n_cells / 1.5))))
+        return cylinder_instance(nr, int(round(1.5 * nr)), re)
+    nr = max(6, int(round(math.sqrt(n_cells / 4.0))))
+    return two_cylinder_instance(nr, 2 * nr, float(rng.uniform(100.0, 200.0)))
+
+
+def batched(n: int = 64, seed: int = 1, lo: float = 2e3, hi: float = 2e5) -> List[Instance]:
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(lo), math.log(hi), size=n))
+    return [random_instance(rng, float(c)) for c in sizes]
+
+
+def streaming() -> mg.RawMesh:
+    return mg.streaming_cavity(2048)
