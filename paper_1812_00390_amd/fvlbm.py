@@ -303,6 +303,11 @@ class Batch:
 
     def set_schedule(self, block: int, xcd_remap: bool = True, persistent: bool = False):
         _check(lib().fvlbm_batch_set_schedule(self.h, int(block), int(bool(xcd_remap)), int(bool(persistent))))
+        self._schedule = dict(block=int(block), xcd_remap=bool(xcd_remap), persistent=bool(persistent))
+
+    def get_schedule(self) -> dict:
+        return dict(self._schedule) if getattr(self, "_schedule", None) else \
+            dict(block=self.solvers[0].get_schedule()["block"], xcd_remap=True, persistent=False)
 
     def autotune(self, trial_steps: int = 64) -> float:
         """Pick the fastest launch schedule for the whole batch (states restored); ms per step."""
