@@ -44,6 +44,25 @@ def alg_bytes_per_update(nf: int, scheme: str, sbytes: int) -> float:
     return STATE_VALUES[scheme] * sbytes + n_rhs * MESH_BYTES[nf]
 
 
+def measured_traffic(schedule):
+    """HBM bytes per launch of the stage kernel from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain copy of
+    known size), or None when the kernel sources changed since they were taken
+    or the timed schedule is not the one they were taken with."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_tile_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    sched = [schedule["block"], int(schedule["xcd_remap"]), int(schedule["persistent"])]
+    if h.hexdigest() != rec["source_sha256"] or sched != rec["schedule"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def events_time(stream, fn):
     import torch
     torch.cuda.synchronize()
@@ -127,7 +146,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="fp32dev")
-    ap.add_argument("--only", choices=["all", "headline", "streaming", "batched"], default="all")
+    ap.add_argument("--only", choices=["all", "headline", "streaming", "batched", "copy"], default="all")
+    ap.add_argument("--schedule", default="", help="force a launch schedule 'block,xcd,persistent' instead of tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
@@ -147,7 +167,10 @@ def main():
         inst = W.cavity20k()
         mesh, s = make_solver(F, inst, "rk4", args.storage)
         nf = mesh.info()["nf"]
-        if not args.no_autotune:
+        if args.schedule:
+            b, x, p = (int(v) for v in args.schedule.split(","))
+            s.set_schedule(b, bool(x), bool(p))
+        elif not args.no_autotune:
             s.autotune(64)
         s.step(args.warmup)
         el = events_time(stream, lambda: s.step(args.steps))
@@ -175,13 +198,21 @@ def main():
                        "schedule": s.get_schedule()},
             "roofline": {"bound": "hbm", "achieved": round(alg_launch / t_launch / 1e9, 2), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(alg_launch / t_launch / 1e9 / HBM_PEAK_GBS, 4),
-                         "traffic": None, "kernel": "k_tile<3> (one RK stage)",
+                         "traffic": measured_traffic(s.get_schedule()) if args.storage == "fp32dev" else None,
+                         "kernel": "k_tile<3> (one RK stage)",
                          "alg_bytes_per_launch": alg_launch, "launch_us": round(t_launch * 1e6, 3)},
             "check": {"max_u": float(np.abs(u).max()), "mass": st["mass"]},
         })
         s.close(); mesh.close()
         if not args.no_cpu_baseline:
             rec["cpu_baseline"] = cpu_baseline(inst)
+    if args.only == "copy":
+        # calibration of the HBM byte counters: a plain device copy of a known size
+        n = 1 << 28                       # 1 GiB of FP32 each way
+        src = torch.ones(n, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        el = events_time(stream, lambda: [dst.copy_(src) for _ in range(5)])
+        rec["copy"] = dict(bytes_each_way=4 * n, launches=5, GBs=round(2 * 4 * n * 5 / el / 1e9, 1))
     if args.only in ("all", "streaming"):
         rec["streaming"] = streaming(F, W, stream)
     if args.only in ("all", "batched"):

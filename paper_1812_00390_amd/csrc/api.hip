@@ -72,6 +72,7 @@ struct fvlbm_solver {
     int64_t steps = 0;
     int snap_cur = -1;         // buffer of the newest snapshot, -1 none
     int64_t snap_step = -1;
+    bool res_valid = false;    // the residual scalar holds the change between the last two snapshots
     bool have_prev = false;    // AB2 history valid
     int lag = 1000;
     bool failed = false;
@@ -201,6 +202,7 @@ hipError_t take_snapshot(fvlbm_solver *s) {
     if (e == hipSuccess && snap_old) e = launch_finish_sums(partial, reduce_blocks(m.n_cells), scal, 1, s->stream);
     s->snap_cur = nxt;
     s->snap_step = s->steps;
+    s->res_valid = snap_old != nullptr;
     return e;
 }
 
@@ -468,7 +470,7 @@ fvlbm_status fvlbm_macros(fvlbm_solver *s, double *rho, double *u, double *stats
     if (e == hipSuccess && u) e = hipMemcpyAsync(u, out + m.n_cells, (size_t)2 * m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) { s->failed = true; return fail(FVLBM_E_DEVICE, std::string("macros failed: ") + hipGetErrorString(e)); }
-    bool have_res = s->snap_cur >= 0 && s->snap_step >= s->lag;
+    bool have_res = s->res_valid;
     if (stats) {
         stats[0] = sc[0];
         stats[1] = have_res ? sc[1] : -1.0;
@@ -501,6 +503,7 @@ fvlbm_status fvlbm_set_f(fvlbm_solver *s, const double *f) {
     s->have_prev = false;
     s->snap_cur = -1;
     s->snap_step = -1;
+    s->res_valid = false;
     return FVLBM_OK;
 }
 
@@ -559,6 +562,7 @@ fvlbm_status fvlbm_restore(fvlbm_solver *s, const void *host_buf, size_t bytes) 
     s->have_prev = hdr[5] != 0;
     s->snap_cur = -1;
     s->snap_step = -1;
+    s->res_valid = false;
     s->failed = false;
     return FVLBM_OK;
 }
@@ -724,6 +728,11 @@ fvlbm_status batch_enqueue(fvlbm_batch *b, int64_t n_steps, bool snapshots) {
     const int n = (int)b->members.size();
     int64_t left = n_steps;
     std::vector<int> ks;
+    // as fvlbm_step(): a member on a lag boundary without a snapshot takes one first
+    if (snapshots && n_steps > 0)
+        for (fvlbm_solver *s : b->members)
+            if (s->snap_cur < 0 && s->steps % s->lag == 0 && take_snapshot(s) != hipSuccess)
+                return fail(FVLBM_E_DEVICE, "snapshot failed");
     while (left > 0) {
         fvlbm_solver *s0 = b->members[0];
         int64_t chunk = std::min<int64_t>(left, GRAPH_CHUNK);

@@ -196,6 +196,31 @@ def test_batched_equals_single_bitwise(F):
         assert np.array_equal(a.f, x.f)
 
 
+def test_batch_residual_matches_single(F):
+    # the residual (velocity change over the lag) is available only after two
+    # snapshots, and the batch reports the same value as the solver alone
+    meshes = [mg.cavity(n=12, jitter=0.2, seed=20), mg.cylinder(nr=8, nt=12, R=6.0, h0=0.05)]
+    alone, mixed = [], []
+    for m in meshes:
+        for dst in (alone, mixed):
+            mesh = F.Mesh(m)
+            dst.append((mesh, F.Solver(mesh, F.make_params(tau=2e-3, scheme="rk4", storage="fp32dev", u_ref=0.2,
+                                                          residual_lag=40))))
+    b = F.Batch([s for _, s in mixed])
+    b.step(40)
+    for (_, a), (_, x) in zip(alone, mixed):
+        a.step(40)
+        assert a.stats()["residual"] > 0 and x.stats()["residual"] > 0
+    b.step(40)
+    for (_, a), (_, x) in zip(alone, mixed):
+        a.step(40)
+        assert a.stats()["residual"] == x.stats()["residual"] > 0
+    # a restored state has no residual until a full lag has passed again
+    ck = mixed[0][1].checkpoint()
+    mixed[0][1].restore(ck)
+    assert mixed[0][1].stats()["residual"] == -1.0
+
+
 def test_autotune_keeps_results_bitwise(F):
     m = mg.cavity(n=30, jitter=0.2, seed=15)
     ref_mesh = F.Mesh(m)
