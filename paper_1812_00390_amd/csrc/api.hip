@@ -89,7 +89,7 @@ struct fvlbm_batch {
     std::vector<fvlbm_solver *> members;
     InstDesc *desc_dev = nullptr;     // [N_KINDS][n]
     UnitTable ut[2];                  // by face-slot count (3, 4)
-    int hmax[2] = {0, 0};
+    int h2max[2] = {0, 0};
     int h1max[2] = {0, 0};
     int scheme = 0, storage = 0;
     hipStream_t stream = nullptr;
@@ -127,7 +127,8 @@ InstDesc base_desc(fvlbm_solver *s, const TileTables *tt) {
     const MeshDev &m = s->mesh->dev;
     InstDesc d{};
     d.vxy = m.vxy; d.dxy = m.dxy; d.inva = m.inva; d.minv = m.minv;
-    d.lnbr = tt->lnbr; d.hdr = tt->hdr; d.halo_idx = tt->halo_idx; d.halo_code = tt->halo_code;
+    d.lnbr = tt->lnbr; d.halo_idx = tt->halo_idx; d.halo_code = tt->halo_code;
+    d.h1s = tt->h1max; d.h2s = tt->h2max;
     d.n_cells = m.n_cells; d.np = m.np;
     d.inv_tau = (float)(1.0 / s->p.tau);
     d.ref = s->ref;
@@ -227,7 +228,7 @@ hipGraphExec_t solver_graph(fvlbm_solver *s, int cur, int nsteps) {
             ab[0] = new char[64];
             hipGraphNode_t node;
             ok = add_stage_node(g, &node, prev ? &prev : nullptr, prev ? 1 : 0, s->desc_dev + k, s->ut,
-                                s->mesh->dev.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->hmax, s->tiles->h1max, ab) == hipSuccess;
+                                s->mesh->dev.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->h2max, s->tiles->h1max, ab) == hipSuccess;
             prev = node;
             if (!ok) break;
         }
@@ -262,7 +263,7 @@ fvlbm_status enqueue_steps(fvlbm_solver *s, int64_t n) {
         }
         step_kinds(s->p.scheme, s->cur, s->have_prev, ks);
         for (int k : ks) {
-            hipError_t e = launch_stage(s->desc_dev + k, s->ut, nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->hmax, s->tiles->h1max, s->stream);
+            hipError_t e = launch_stage(s->desc_dev + k, s->ut, nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->h2max, s->tiles->h1max, s->stream);
             if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("stage launch failed: ") + hipGetErrorString(e));
         }
         advance_position(s->p.scheme, s->cur, s->have_prev);
@@ -388,7 +389,7 @@ fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const doub
         std::string err;
         fvlbm_status tst = get_tiles(mesh->dev, s->sched.block, &s->tiles, err);
         if (tst != FVLBM_OK) return fail(tst, err);
-        if (stage_lds_bytes(s->sched.block, s->tiles->hmax, s->tiles->h1max) > 65536) {
+        if (stage_lds_bytes(s->sched.block, s->tiles->h2max, s->tiles->h1max) > 65536) {
             s->sched.block = 128;
             tst = get_tiles(mesh->dev, s->sched.block, &s->tiles, err);
             if (tst != FVLBM_OK) return fail(tst, err);
@@ -514,7 +515,7 @@ fvlbm_status fvlbm_rhs(fvlbm_solver *s, double *rhs) {
     const MeshDev &m = s->mesh->dev;
     double *out = reinterpret_cast<double *>(s->buf + s->L.out);
     int k = s->cur == 0 ? RH0 : (s->cur == 1 ? RH1 : RH2);
-    hipError_t e = launch_stage(s->desc_dev + k, s->ut, m.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->hmax, s->tiles->h1max, s->stream);
+    hipError_t e = launch_stage(s->desc_dev + k, s->ut, m.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->h2max, s->tiles->h1max, s->stream);
     if (e == hipSuccess) e = launch_rhs_out(reinterpret_cast<float *>(s->buf + s->L.r32), m.n_cells, m.np, m.perm_dev, out, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(rhs, out, (size_t)Q * m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -573,7 +574,7 @@ fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_rema
     std::string err;
     fvlbm_status st = get_tiles(s->mesh->dev, block, &tt, err);
     if (st != FVLBM_OK) return fail(st, err);
-    if (stage_lds_bytes(block, tt->hmax, tt->h1max) > 65536) return fail(FVLBM_E_ARG, "tile and halo do not fit the LDS at this block size");
+    if (stage_lds_bytes(block, tt->h2max, tt->h1max) > 65536) return fail(FVLBM_E_ARG, "tile and halo do not fit the LDS at this block size");
     if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "stream synchronize failed");
     s->sched.block = block;
     s->sched.xcd_remap = xcd_remap ? 1 : 0;
@@ -600,7 +601,7 @@ namespace {
 fvlbm_status batch_build(fvlbm_batch *b) {
     const int n = (int)b->members.size();
     std::vector<InstDesc> all((size_t)N_KINDS * n);
-    int hmax[2] = {0, 0}, h1max[2] = {0, 0};
+    int h2max[2] = {0, 0}, h1max[2] = {0, 0};
     for (int i = 0; i < n; i++) {
         fvlbm_solver *s = b->members[i];
         const TileTables *tt = nullptr;
@@ -608,14 +609,14 @@ fvlbm_status batch_build(fvlbm_batch *b) {
         fvlbm_status st = get_tiles(s->mesh->dev, b->sched.block, &tt, err);
         if (st != FVLBM_OK) return fail(st, err);
         int t = s->mesh->dev.nf - 3;
-        hmax[t] = std::max(hmax[t], tt->hmax);
+        h2max[t] = std::max(h2max[t], tt->h2max);
         h1max[t] = std::max(h1max[t], tt->h1max);
         InstDesc d[N_KINDS];
         fill_descs(s, tt, d);
         for (int k = 0; k < N_KINDS; k++) all[(size_t)k * n + i] = d[k];
     }
     for (int t = 0; t < 2; t++)
-        if (stage_lds_bytes(b->sched.block, hmax[t], h1max[t]) > 65536)
+        if (stage_lds_bytes(b->sched.block, h2max[t], h1max[t]) > 65536)
             return fail(FVLBM_E_ARG, "batch tiles do not fit the LDS at this block size");
     if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "stream synchronize failed");
     free_graphs(b->graphs);
@@ -624,7 +625,7 @@ fvlbm_status batch_build(fvlbm_batch *b) {
     if (hipMemcpy(b->desc_dev, all.data(), all.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess)
         return fail(FVLBM_E_DEVICE, "batch descriptor upload failed");
     for (int t = 0; t < 2; t++) {
-        b->hmax[t] = hmax[t];
+        b->h2max[t] = h2max[t];
         b->h1max[t] = h1max[t];
         std::vector<std::pair<int, int>> inst;
         for (int i = 0; i < n; i++)
@@ -705,7 +706,7 @@ hipGraphExec_t batch_graph(fvlbm_batch *b, int cur, int nsteps) {
                 hipGraphNode_t node;
                 ok = add_stage_node(g, &node, prev.empty() ? nullptr : prev.data(), (int)prev.size(),
                                     b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
-                                    b->sched.xcd_remap, b->sched.persistent, b->hmax[t], b->h1max[t], ab) == hipSuccess;
+                                    b->sched.xcd_remap, b->sched.persistent, b->h2max[t], b->h1max[t], ab) == hipSuccess;
                 now.push_back(node);
             }
             prev = now;
@@ -748,7 +749,7 @@ fvlbm_status batch_enqueue(fvlbm_batch *b, int64_t n_steps, bool snapshots) {
                 for (int k : ks)
                     for (int t = 0; t < 2; t++) {
                         hipError_t e = launch_stage(b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
-                                                    b->sched.xcd_remap, b->sched.persistent, b->hmax[t], b->h1max[t], b->stream);
+                                                    b->sched.xcd_remap, b->sched.persistent, b->h2max[t], b->h1max[t], b->stream);
                         if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
                     }
                 advance_position(b->scheme, c, hp);

@@ -55,17 +55,18 @@ struct GroupDev {
 
 // Per tile size T: cells [t*T, t*T+T) form tile t; ring 1 is the set of face
 // neighbours outside the tile, ring 2 the face neighbours of ring 1 outside
-// tile and ring 1.  Local indices: tile cell i -> i - t*T, ring-1 entry k ->
-// T + k, ring-2 entry k -> T + n1 + k.
+// tile and ring 1.  Every tile has h1max ring-1 slots and h2max ring-2 slots
+// (the largest counts over tiles; unused slots hold -1), so a thread finds its
+// halo cell at a fixed position without a per-tile header.  Local indices:
+// tile cell i -> i - t*T, ring-1 slot k -> T + k, ring-2 slot k -> T + h1max + k.
 struct TileTables {
     int T = 0;
     int n_tiles = 0;
-    int hmax = 0;                // largest n1 + n2
-    int h1max = 0;               // largest n1
+    int h1max = 0;               // ring-1 slots per tile (largest n1)
+    int h2max = 0;               // ring-2 slots per tile (largest n2)
     uint2 *lnbr = nullptr;       // [np] four int16 slot codes per tile cell: local index, -1-g, or LN_PAD
-    int4 *hdr = nullptr;         // [n_tiles] {first entry in halo_idx, n1, n2, first ring-1 code}
-    int *halo_idx = nullptr;     // cells of ring 1 then ring 2, per tile
-    int *halo_code = nullptr;    // [ring-1 entries][nf]: local index, -1-g, or NB_PAD
+    int *halo_idx = nullptr;     // [n_tiles][h1max + h2max] cells of the ring-1 then ring-2 slots, -1 if unused
+    uint2 *halo_code = nullptr;  // [n_tiles][h1max] four int16 slot codes per ring-1 slot (as lnbr)
     size_t bytes = 0;
     void *block = nullptr;
 };
@@ -114,9 +115,10 @@ RefDev make_ref(double rho0, double ux, double uy, double scale);
 
 // Host form of the tile tables (see TileTables).
 struct HostTiles {
-    int T = 0, n_tiles = 0, hmax = 0, h1max = 0;
-    std::vector<uint16_t> lnbr;      // [np][4]
-    std::vector<int> hdr, halo_idx, halo_code;   // hdr: [n_tiles][4]
+    int T = 0, n_tiles = 0, h1max = 0, h2max = 0;
+    std::vector<uint16_t> lnbr;        // [np][4]
+    std::vector<int> halo_idx;         // [n_tiles][h1max + h2max]
+    std::vector<uint16_t> halo_code;   // [n_tiles][h1max][4]
 };
 void build_tile_tables_host(const std::vector<int> &nbr, int n, int nf, int np, int T, HostTiles &out);
 
@@ -129,8 +131,9 @@ struct InstDesc {
     const float2 *vxy, *dxy;
     const float *inva, *minv;
     const uint2 *lnbr;
-    const int4 *hdr;
-    const int *halo_idx, *halo_code;
+    const int *halo_idx;
+    const uint2 *halo_code;
+    int h1s, h2s;         // ring-1 / ring-2 slots per tile of this instance's tables
     const void *src;      // state the RHS is evaluated at
     const void *base;     // f(0) of the update (== src for Euler / AB2)
     void *dst;
@@ -158,14 +161,15 @@ struct UnitTable {
 };
 
 // Launch one RHS-evaluation stage over all units (one unit = one tile of
-// ut.block cells).  nf: 3 or 4; storage FVLBM_STORE_*; hmax: largest halo.
+// ut.block cells).  nf: 3 or 4; storage FVLBM_STORE_*; h2max, h1max: the
+// largest ring-2 and ring-1 slot counts over the launch's instances (LDS size).
 hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                        int xcd_remap, int persistent, int hmax, int h1max, hipStream_t stream);
-size_t stage_lds_bytes(int T, int hmax, int h1max);
+                        int xcd_remap, int persistent, int h2max, int h1max, hipStream_t stream);
+size_t stage_lds_bytes(int T, int h2max, int h1max);
 // Same as a kernel node for a graph.
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                          int xcd_remap, int persistent, int hmax, int h1max, void **argbuf);
+                          int xcd_remap, int persistent, int h2max, int h1max, void **argbuf);
 
 // Step 0 and conversions (FP64 host data in input order <-> device storage).
 hipError_t launch_init_eq(void *dst, int storage, int n, int np, const RefDev &ref,

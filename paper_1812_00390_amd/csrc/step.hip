@@ -17,6 +17,11 @@
 // Everything is computed on deviations h = f - f_eq(rho0, u_dev) in FP32,
 // so the constant part of f never enters a flux difference; storage is FP32
 // f, FP32 h, or FP16 h/(w S).
+//
+// Only directions 1..8 move (e_0 = 0), so a staged record holds h_1..h_8 and
+// their gradients; a cell's h_0 stays in its own thread's registers.
+// Interior faces are handled in fully unrolled loops; the rare boundary slots
+// go through one rolled loop per phase, which keeps the kernel small.
 #include "fvlbm_internal.h"
 
 // No implicit contraction: every fused multiply-add below is written as fmaf,
@@ -39,7 +44,9 @@ __device__ constexpr float WT[Q] = {4.f / 9, 1.f / 9, 1.f / 9, 1.f / 9, 1.f / 9,
 // The descriptor's pointers are read from memory, so the compiler cannot
 // infer their address space and would emit FLAT instructions (which also
 // count against the LDS wait counter).  Every device-memory access goes
-// through these global-address-space accessors instead.
+// through these global-address-space accessors instead.  Plane accesses take
+// a uniform plane base (scalar registers) plus a 32-bit byte offset, which
+// maps onto the scalar-base form of the global load and store instructions.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define FVLBM_GLOBAL_AS __attribute__((address_space(1)))   // the device pass only; the host pass never runs these
 #else
@@ -50,100 +57,81 @@ __device__ inline T ldg(const T *p, size_t i) {
     return ((const FVLBM_GLOBAL_AS T *)p)[i];
 }
 template <class T>
-__device__ inline void stg(T *p, size_t i, T v) {
-    ((FVLBM_GLOBAL_AS T *)p)[i] = v;
+__device__ inline T ldo(const void *base, uint32_t off) {
+    return *(const FVLBM_GLOBAL_AS T *)((const FVLBM_GLOBAL_AS char *)base + off);
+}
+template <class T>
+__device__ inline void sto(void *base, uint32_t off, T v) {
+    *(FVLBM_GLOBAL_AS T *)((FVLBM_GLOBAL_AS char *)base + off) = v;
+}
+__device__ inline const void *plane(const void *p, size_t plane_bytes, int a) {
+    return static_cast<const char *>(p) + plane_bytes * (size_t)a;
+}
+__device__ inline void *plane(void *p, size_t plane_bytes, int a) {
+    return static_cast<char *>(p) + plane_bytes * (size_t)a;
 }
 
 __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------- rounding
 //
-// Every state store rounds without bias: the new value's residual is carried
-// (Fast2Sum), and the stored neighbour is picked with probability
-// proportional to the distance, driven by a multiplicative hash of the
-// value's own bits and the slot index.  Round-to-nearest would drop every increment
-// smaller than half an ulp, so a run can freeze short of its steady state
-// (FP32) or drift (FP16); unbiased rounding keeps the expected increment.
-// The hash makes the rounding a pure function of (value, cell, direction):
-// results do not depend on launch order, schedule, batching or graphs.
+// Every state store rounds without bias.  Round-to-nearest drops every
+// increment smaller than half an ulp, so a run can freeze short of its steady
+// state (FP32) or drift (FP16).  Instead a dither uniform over one unit in the
+// last place (centred) is added before rounding, so the expected stored value
+// is the exact one.  The dither is a hash of the increment's bits and of
+// (cell, direction): results do not depend on launch order, schedule,
+// batching or graphs.
 
-struct Exact {
-    float s, e;   // value = s + e, |e| <= ulp(s)/2 (approximately)
-};
+// 24 well-mixed bits (the top of a 24-bit product, full-rate multiply)
+__device__ inline uint32_t mix(uint32_t x) { return __umul24(x ^ (x >> 15), 0x9e3779u); }
 
-// b + c * r with its residual: the increment p = c r is rounded once (its
-// error is far below an ulp of the sum), then Fast2Sum; when |p| > |b| the
-// residual is only approximate, which leaves the rounding nearly unbiased.
-__device__ inline Exact fma_exact(float c, float r, float b) {
-#pragma clang fp contract(off)
-    const float p = c * r;
-    const float s = b + p;
-    return {s, p - (s - b)};
-}
-
-// a + x with its residual (x carries its own residual)
-__device__ inline Exact add_exact(float a, Exact x) {
-#pragma clang fp contract(off)
-    const float s = a + x.s;
-    const float bb = s - a;
-    const float e = (a - (s - bb)) + (x.s - bb);
-    return {s, e + x.e};
-}
-
-__device__ inline float unit_random(uint32_t h) { return (float)(h >> 8) * (1.0f / 16777216.0f); }
-
-// unbiased rounding of s + e to FP32
-__device__ inline float round_fp32(Exact v, uint32_t salt) {
-    if (v.e == 0.f) return v.s;
-    // neighbour of s in the direction of e (s is finite and, as |e| <= ulp(s)/2, nonzero)
-    const uint32_t bs = __float_as_uint(v.s);
-    const bool up_mag = (v.e > 0.f) == (v.s > 0.f);
-    const float nb = __uint_as_float(up_mag ? bs + 1u : bs - 1u);
-    const float gap = fabsf(nb - v.s);
-    uint32_t h = (__float_as_uint(v.e) ^ (__float_as_uint(v.s) * 0x9e3779b1u) ^ salt) * 0x85ebca6bu;
-    h ^= h >> 15;
-    return unit_random(h) * gap < fabsf(v.e) ? nb : v.s;
+// b + p rounded to FP32 with a centred dither of one ulp of b
+__device__ inline float add_sr(float b, float p, uint32_t key) {
+    const float g = __uint_as_float(__float_as_uint(b) & 0x7f800000u) * 0x1p-47f;   // ulp(b) / 2^24; 0 for b = 0
+    const int32_t r = (int32_t)mix(__float_as_uint(p) ^ key) >> 8;                 // uniform in [-2^23, 2^23)
+    return b + fmaf((float)r, g, p);
 }
 
 // unbiased rounding of a float to FP16: add 13 random bits below the FP16
 // mantissa, then truncate (exact for FP16 normals)
-__device__ inline __half round_fp16(float v, uint32_t salt) {
+__device__ inline __half round_fp16(float v, uint32_t key) {
     const uint32_t b = __float_as_uint(v);
-    uint32_t h = (b ^ (salt * 0x9e3779b1u)) * 0x85ebca6bu;
-    h ^= h >> 15;
-    const uint32_t mag = (b & 0x7fffffffu) + (h & 0x1fffu);
+    const uint32_t mag = (b & 0x7fffffffu) + (mix(b ^ key) >> 19);
     return __float2half_rz(__uint_as_float((b & 0x80000000u) | mag));
 }
 
+// A storage format: load(plane base, byte offset, direction) returns the
+// deviation h; store(.., b, inc, ..) writes b + inc (b a deviation).
 template <int STORE>
 struct Storage;
 
 template <>
 struct Storage<FVLBM_STORE_FP32> {
-    __device__ static float load(const void *p, size_t idx, int a, const RefDev &r) {
-        return ldg(static_cast<const float *>(p), idx) - r.fref[a];
+    static constexpr uint32_t SZ = 4;
+    __device__ static float load(const void *p, uint32_t off, int a, const RefDev &r) {
+        return ldo<float>(p, off) - r.fref[a];
     }
-    __device__ static void store(void *p, size_t idx, int a, Exact h, const RefDev &r, uint32_t salt) {
-        stg(static_cast<float *>(p), idx, round_fp32(add_exact(r.fref[a], h), salt));
+    __device__ static void store(void *p, uint32_t off, int a, float b, float inc, const RefDev &r, uint32_t key) {
+        sto<float>(p, off, add_sr(b + r.fref[a], inc, key));   // b + fref is the stored f (b came from it by Sterbenz)
     }
 };
 template <>
 struct Storage<FVLBM_STORE_FP32_DEV> {
-    __device__ static float load(const void *p, size_t idx, int, const RefDev &) {
-        return ldg(static_cast<const float *>(p), idx);
-    }
-    __device__ static void store(void *p, size_t idx, int, Exact h, const RefDev &, uint32_t salt) {
-        stg(static_cast<float *>(p), idx, round_fp32(h, salt));
+    static constexpr uint32_t SZ = 4;
+    __device__ static float load(const void *p, uint32_t off, int, const RefDev &) { return ldo<float>(p, off); }
+    __device__ static void store(void *p, uint32_t off, int, float b, float inc, const RefDev &, uint32_t key) {
+        sto<float>(p, off, add_sr(b, inc, key));
     }
 };
 template <>
 struct Storage<FVLBM_STORE_FP16_DEV> {
-    __device__ static float load(const void *p, size_t idx, int a, const RefDev &r) {
-        const __half v = ldg(static_cast<const __half *>(p), idx);
-        return __half2float(v) * (WT[a] * r.scale);
+    static constexpr uint32_t SZ = 2;
+    __device__ static float load(const void *p, uint32_t off, int a, const RefDev &r) {
+        return __half2float(ldo<__half>(p, off)) * (WT[a] * r.scale);
     }
-    __device__ static void store(void *p, size_t idx, int a, Exact h, const RefDev &r, uint32_t salt) {
-        stg(static_cast<__half *>(p), idx, round_fp16((h.s + h.e) * r.inv_unit[a], salt));
+    __device__ static void store(void *p, uint32_t off, int a, float b, float inc, const RefDev &r, uint32_t key) {
+        sto<__half>(p, off, round_fp16((b + inc) * r.inv_unit[a], key));
     }
 };
 
@@ -241,7 +229,6 @@ __device__ inline void boundary_value(const GroupDev &g, const float h[Q], const
     }
 }
 
-constexpr int PAD_BELOW = -MAX_GROUPS;   // slot codes below this are padded slots
 
 // Least-squares coefficient of slot k of cell c: M^-1 w_k d_k (Eq. 12).
 __device__ inline float2 lsq_coef(float2 dk, float m11, float m12, float m22) {
@@ -254,10 +241,7 @@ __device__ inline float2 scaled_normal(float2 v0, float2 v1, float inva) {
     return make_float2((v1.y - v0.y) * inva, -(v1.x - v0.x) * inva);
 }
 
-template <int NF>
-__device__ inline float2 corner(const InstDesc &d, int k, int c) {
-    return ldg(d.vxy, (size_t)(k % NF) * d.np + c);
-}
+constexpr int PAD_BELOW = -MAX_GROUPS;   // slot codes below this are padded slots
 
 __device__ inline int remap_block(int b, int nb, int xcd_remap) {
     // Blocks are dispatched round-robin over the 8 XCDs; renumber them so that
@@ -271,88 +255,89 @@ __device__ inline int remap_block(int b, int nb, int xcd_remap) {
 
 __device__ inline int unpack16(uint32_t w, int hi) { return (int)(int16_t)(hi ? (w >> 16) : (w & 0xffffu)); }
 
-// Geometry of one cell held in registers: stencil offsets, least-squares
-// inverse, corner offsets and 1/A.
+
+// corner k of cell c (offset from the centroid)
+__device__ inline float2 corner(const InstDesc &d, int k, int c) {
+    return ldo<float2>(plane(d.vxy, (size_t)d.np * 8, k), (uint32_t)c * 8u);
+}
+
+// Least-squares data of one cell held in registers: stencil offsets and the
+// inverse least-squares matrix.
 template <int NF>
 struct CellGeo {
     float2 dk[NF];
     float m11, m12, m22;
     __device__ void load(const InstDesc &d, int c) {
+        const uint32_t o8 = (uint32_t)c * 8u, o4 = (uint32_t)c * 4u;
 #pragma unroll
-        for (int k = 0; k < NF; k++) dk[k] = ldg(d.dxy, (size_t)k * d.np + c);
-        m11 = ldg(d.minv, c);
-        m12 = ldg(d.minv, (size_t)d.np + c);
-        m22 = ldg(d.minv, 2 * (size_t)d.np + c);
+        for (int k = 0; k < NF; k++) dk[k] = ldo<float2>(plane(d.dxy, (size_t)d.np * 8, k), o8);
+        m11 = ldo<float>(d.minv, o4);
+        m12 = ldo<float>(plane(d.minv, (size_t)d.np * 4, 1), o4);
+        m22 = ldo<float>(plane(d.minv, (size_t)d.np * 4, 2), o4);
     }
 };
 
-// LDS records.  Region A holds tile and ring-1 cells, 28 floats each:
-// f0..f8, pad, (gx0,gy0)..(gx8,gy8); region B holds ring-2 cells, 12 floats
-// each: f0..f8, pad.  Records are 16-byte aligned, so a cell's values are
-// read with 128-bit LDS loads.
-constexpr int RA = 7;   // float4 per region-A record
-constexpr int RB = 3;   // float4 per region-B record
+// Face data of one tile cell: corner offsets and 1/A.
+template <int NF>
+struct CellFaces {
+    float2 v[NF];
+    float inva;
+    __device__ void load(const InstDesc &d, int c) {
+#pragma unroll
+        for (int k = 0; k < NF; k++) v[k] = corner(d, k, c);
+        inva = ldo<float>(d.inva, (uint32_t)c * 4u);
+    }
+};
+
+// LDS records.  Region A holds tile and ring-1 cells, 24 floats each:
+// h1..h8, (gx1,gy1)..(gx8,gy8); region B holds ring-2 cells, 8 floats each:
+// h1..h8.  Records are 16-byte aligned and read with 128-bit LDS loads.
+constexpr int RA = 6;   // float4 per region-A record
+constexpr int RB = 2;   // float4 per region-B record
 
 __device__ inline void rd_f(const float4 *rec, float f[Q]) {
     const float4 x = rec[0], y = rec[1];
-    f[0] = x.x; f[1] = x.y; f[2] = x.z; f[3] = x.w;
-    f[4] = y.x; f[5] = y.y; f[6] = y.z; f[7] = y.w;
-    f[8] = reinterpret_cast<const float *>(rec)[8];
+    f[1] = x.x; f[2] = x.y; f[3] = x.z; f[4] = x.w;
+    f[5] = y.x; f[6] = y.y; f[7] = y.z; f[8] = y.w;
 }
 __device__ inline void wr_f(float4 *rec, const float f[Q]) {
-    rec[0] = make_float4(f[0], f[1], f[2], f[3]);
-    rec[1] = make_float4(f[4], f[5], f[6], f[7]);
-    reinterpret_cast<float *>(rec)[8] = f[8];
+    rec[0] = make_float4(f[1], f[2], f[3], f[4]);
+    rec[1] = make_float4(f[5], f[6], f[7], f[8]);
 }
 __device__ inline void rd_g(const float4 *rec, float gx[Q], float gy[Q]) {
-    const float2 p = reinterpret_cast<const float2 *>(rec)[5];
-    const float4 a = rec[3], b = rec[4], c = rec[5], d = rec[6];
-    gx[0] = p.x; gy[0] = p.y;
+    const float4 a = rec[2], b = rec[3], c = rec[4], d = rec[5];
     gx[1] = a.x; gy[1] = a.y; gx[2] = a.z; gy[2] = a.w;
     gx[3] = b.x; gy[3] = b.y; gx[4] = b.z; gy[4] = b.w;
     gx[5] = c.x; gy[5] = c.y; gx[6] = c.z; gy[6] = c.w;
     gx[7] = d.x; gy[7] = d.y; gx[8] = d.z; gy[8] = d.w;
 }
 __device__ inline void wr_g(float4 *rec, const float gx[Q], const float gy[Q]) {
-    reinterpret_cast<float2 *>(rec)[5] = make_float2(gx[0], gy[0]);
-    rec[3] = make_float4(gx[1], gy[1], gx[2], gy[2]);
-    rec[4] = make_float4(gx[3], gy[3], gx[4], gy[4]);
-    rec[5] = make_float4(gx[5], gy[5], gx[6], gy[6]);
-    rec[6] = make_float4(gx[7], gy[7], gx[8], gy[8]);
+    rec[2] = make_float4(gx[1], gy[1], gx[2], gy[2]);
+    rec[3] = make_float4(gx[3], gy[3], gx[4], gy[4]);
+    rec[4] = make_float4(gx[5], gy[5], gx[6], gy[6]);
+    rec[5] = make_float4(gx[7], gy[7], gx[8], gy[8]);
 }
 
-// Gradient of cell c (Eq. 12) from staged values: sum_k M^-1 w_k d_k (phi_k - f_c),
-// phi_k = the staged value of local cell code[k], or the wall / ghost value of
-// a boundary slot (Eqs. 18-22) formed from the cell's own state.  Local
-// indices below `a_end` are region-A records, the rest region B.
+// Boundary-slot terms of the gradient of cell c: phi_k is the wall / ghost
+// value (Eqs. 18-22) formed from the cell's own state.
 template <int NF>
-__device__ inline void gradient_staged(const InstDesc &d, int c, const CellGeo<NF> &geo, const float hc[Q],
-                                       const int code[NF], const float4 *A, const float4 *B, int a_end,
-                                       float gx[Q], float gy[Q]) {
-#pragma unroll
-    for (int a = 0; a < Q; a++) { gx[a] = 0.f; gy[a] = 0.f; }
-    bool have_m = false;
-    Macro m;
+__device__ inline void boundary_gradient_body(const InstDesc &d, int c, const CellGeo<NF> &geo, const float hc[Q],
+                                              uint2 packed, float gx[Q], float gy[Q]) {
+    const Macro m = moments(hc, d.ref);
     float he[Q];
-#pragma unroll
+    heq(m.drho, m.rho, m.jx, m.jy, d.ref, he);
+    const float inva = ldo<float>(d.inva, (uint32_t)c * 4u);
+#pragma unroll 1
     for (int k = 0; k < NF; k++) {
-        if (code[k] < PAD_BELOW) continue;
-        const float2 w = lsq_coef(geo.dk[k], geo.m11, geo.m12, geo.m22);
+        const int ck = unpack16(k < 2 ? packed.x : packed.y, k & 1);
+        if (ck >= 0 || ck < PAD_BELOW) continue;
+        const float2 dk = ldo<float2>(plane(d.dxy, (size_t)d.np * 8, k), (uint32_t)c * 8u);
+        const float2 w = lsq_coef(dk, geo.m11, geo.m12, geo.m22);
+        const float2 gn = scaled_normal(corner(d, k, c), corner(d, k + 1 == NF ? 0 : k + 1, c), inva);
         float phi[Q];
-        if (code[k] >= 0) {
-            const int l = code[k];
-            rd_f(l < a_end ? A + l * RA : B + (l - a_end) * RB, phi);
-        } else {
-            if (!have_m) {
-                m = moments(hc, d.ref);
-                heq(m.drho, m.rho, m.jx, m.jy, d.ref, he);
-                have_m = true;
-            }
-            const float2 gn = scaled_normal(corner<NF>(d, k, c), corner<NF>(d, k + 1, c), ldg(d.inva, c));
-            boundary_value(d.groups[-1 - code[k]], hc, m, he, gn, d.ref, phi);
-        }
+        boundary_value(d.groups[-1 - ck], hc, m, he, gn, d.ref, phi);
 #pragma unroll
-        for (int a = 0; a < Q; a++) {
+        for (int a = 1; a < Q; a++) {
             const float df = phi[a] - hc[a];
             gx[a] = fmaf(w.x, df, gx[a]);
             gy[a] = fmaf(w.y, df, gy[a]);
@@ -360,132 +345,219 @@ __device__ inline void gradient_staged(const InstDesc &d, int c, const CellGeo<N
     }
 }
 
+// Gradient of cell c (Eq. 12) from staged values: sum_k M^-1 w_k d_k (phi_k - h_c),
+// phi_k the staged value of local cell code[k] (interior slots first, then
+// boundary slots).  Local indices below `a_end` are region-A records, the rest
+// region B.
+template <int NF>
+__device__ inline void gradient_staged(const InstDesc &d, int c, const CellGeo<NF> &geo, const float hc[Q],
+                                       const int (&code)[NF], uint2 packed, const float4 *A, const float4 *B, int a_end,
+                                       float gx[Q], float gy[Q]) {
+#pragma unroll
+    for (int a = 1; a < Q; a++) { gx[a] = 0.f; gy[a] = 0.f; }
+    bool bnd = false;
+#pragma unroll
+    for (int k = 0; k < NF; k++) {
+        if (code[k] < 0) {
+            bnd = bnd || code[k] >= PAD_BELOW;
+            continue;
+        }
+        const float2 w = lsq_coef(geo.dk[k], geo.m11, geo.m12, geo.m22);
+        const int l = code[k];
+        float phi[Q];
+        rd_f(l < a_end ? A + l * RA : B + (l - a_end) * RB, phi);
+#pragma unroll
+        for (int a = 1; a < Q; a++) {
+            const float df = phi[a] - hc[a];
+            gx[a] = fmaf(w.x, df, gx[a]);
+            gy[a] = fmaf(w.y, df, gy[a]);
+        }
+    }
+    if (bnd) boundary_gradient_body<NF>(d, c, geo, hc, packed, gx, gy);
+}
+
+// Boundary-face terms of the flux sum of tile cell i (Eqs. 18, 23-26).
+template <int NF>
+__device__ inline void boundary_flux(const InstDesc &d, int i, const float hi[Q], const float gxi[Q], const float gyi[Q],
+                                     const Macro &mi, const float hei[Q], uint2 packed, float inva, float acc[Q]) {
+#pragma unroll 1
+    for (int k = 0; k < NF; k++) {
+        const int ck = unpack16(k < 2 ? packed.x : packed.y, k & 1);
+        if (ck >= 0 || ck < PAD_BELOW) continue;
+        const float2 v0 = corner(d, k, i), v1 = corner(d, k + 1 == NF ? 0 : k + 1, i);
+        const float2 g = scaled_normal(v0, v1, inva);
+        const float2 r = make_float2(0.5f * (v0.x + v1.x), 0.5f * (v0.y + v1.y));   // x_f - x_i
+        const GroupDev &gr = d.groups[-1 - ck];
+        float bv[Q];
+        boundary_value(gr, hi, mi, hei, g, d.ref, bv);
+        const int kind = gr.kind;
+        const bool upwind = kind == FVLBM_BC_INLET || (kind == FVLBM_BC_OUTLET && gr.internal);
+#pragma unroll
+        for (int a = 1; a < Q; a++) {
+            const float en = edot(a, g.x, g.y);
+            float phi;
+            if (kind == FVLBM_BC_WALL) {
+                phi = bv[a];                                                    // Eq. 18 face value
+            } else if (upwind) {
+                phi = en > 0.f ? fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a])) : bv[a];   // Eqs. 23, 24
+            } else if (kind == FVLBM_BC_OUTLET) {
+                phi = hi[a];                                                    // Eq. 25
+            } else {
+                phi = 0.5f * (hi[a] + bv[a]);                                   // Eq. 26
+            }
+            acc[a] = fmaf(en, phi, acc[a]);
+        }
+    }
+}
+
 // Phase 3 for one tile cell: face values, flux sum, BGK source, update, store.
+// base[] holds f(0) of the update when it is not the evaluated state.
 template <int NF, int STORE>
-__device__ __forceinline__ void tile_update(const InstDesc &d, int i, const int code[NF], const CellGeo<NF> &geo,
+__device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, const float base[Q], bool sep_base,
+                                            const int (&code)[NF], uint2 packed, const CellGeo<NF> &geo, const CellFaces<NF> &cf,
                                             const float4 *own, const float4 *A) {
     float hi[Q], gxi[Q], gyi[Q];
+    hi[0] = h0;
     rd_f(own, hi);
     rd_g(own, gxi, gyi);
     const Macro mi = moments(hi, d.ref);
     float hei[Q];
     heq(mi.drho, mi.rho, mi.jx, mi.jy, d.ref, hei);
-    const float inva = ldg(d.inva, i);
     float acc[Q];
 #pragma unroll
     for (int a = 0; a < Q; a++) acc[a] = 0.f;
+    bool bnd = false;
 #pragma unroll
     for (int k = 0; k < NF; k++) {
-        if (code[k] < PAD_BELOW) continue;
-        const float2 v0 = corner<NF>(d, k, i), v1 = corner<NF>(d, k + 1, i);
-        const float2 g = scaled_normal(v0, v1, inva);
+        if (code[k] < 0) {
+            bnd = bnd || code[k] >= PAD_BELOW;
+            continue;
+        }
+        const float2 v0 = cf.v[k], v1 = cf.v[k + 1 == NF ? 0 : k + 1];
+        const float2 g = scaled_normal(v0, v1, cf.inva);
         const float2 r = make_float2(0.5f * (v0.x + v1.x), 0.5f * (v0.y + v1.y));   // x_f - x_i
-        if (code[k] >= 0) {
-            const float4 *rec = A + code[k] * RA;                                     // neighbours are in region A
-            const float2 q = make_float2(r.x - geo.dk[k].x, r.y - geo.dk[k].y);       // x_f - x_j
-            float hj[Q], gxj[Q], gyj[Q];
-            rd_f(rec, hj);
-            rd_g(rec, gxj, gyj);
+        const float2 q = make_float2(r.x - geo.dk[k].x, r.y - geo.dk[k].y);       // x_f - x_j
+        const float4 *rec = A + code[k] * RA;                                     // neighbours are in region A
+        float hj[Q], gxj[Q], gyj[Q];
+        rd_f(rec, hj);
+        rd_g(rec, gxj, gyj);
 #pragma unroll
-            for (int a = 1; a < Q; a++) {
-                const float en = edot(a, g.x, g.y);
-                const float own = fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a]));
-                const float nb = fmaf(gyj[a], q.y, fmaf(gxj[a], q.x, hj[a]));
-                acc[a] = fmaf(en, en > 0.f ? own : nb, acc[a]);
-            }
-        } else {
-            const GroupDev &gr = d.groups[-1 - code[k]];
-            float bv[Q];
-            boundary_value(gr, hi, mi, hei, g, d.ref, bv);
-            const bool upwind = gr.kind == FVLBM_BC_INLET || (gr.kind == FVLBM_BC_OUTLET && gr.internal);
-#pragma unroll
-            for (int a = 1; a < Q; a++) {
-                const float en = edot(a, g.x, g.y);
-                float phi;
-                if (gr.kind == FVLBM_BC_WALL) {
-                    phi = bv[a];                                                    // Eq. 18 face value
-                } else if (upwind) {
-                    phi = en > 0.f ? fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a])) : bv[a];   // Eqs. 23, 24
-                } else if (gr.kind == FVLBM_BC_OUTLET) {
-                    phi = hi[a];                                                    // Eq. 25
-                } else {
-                    phi = 0.5f * (hi[a] + bv[a]);                                   // Eq. 26
-                }
-                acc[a] = fmaf(en, phi, acc[a]);
-            }
+        for (int a = 1; a < Q; a++) {
+            const float en = edot(a, g.x, g.y);
+            const float own_v = fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a]));
+            const float nb_v = fmaf(gyj[a], q.y, fmaf(gxj[a], q.x, hj[a]));
+            acc[a] = fmaf(en, en > 0.f ? own_v : nb_v, acc[a]);
         }
     }
+    if (bnd) boundary_flux<NF>(d, i, hi, gxi, gyi, mi, hei, packed, cf.inva, acc);
 
     // RHS = -sum (e.n dl/A) phi - (f - f_eq)/tau  (Eq. 10), then the update.
+    const uint32_t os = (uint32_t)i * Storage<STORE>::SZ, o4 = (uint32_t)i * 4u;
+    const size_t pb = (size_t)d.np * Storage<STORE>::SZ, pb4 = (size_t)d.np * 4;
+    const uint32_t key0 = (uint32_t)i * 9u;
 #pragma unroll
     for (int a = 0; a < Q; a++) {
         const float rhs = fmaf(hei[a] - hi[a], d.inv_tau, -acc[a]);
-        const size_t idx = (size_t)a * d.np + i;
-        const uint32_t salt = (uint32_t)i * 9u + (uint32_t)a;
-        Exact out;
+        float b, inc;
         if (d.mode == 0) {
-            const float b = (d.base == d.src) ? hi[a] : Storage<STORE>::load(d.base, idx, a, d.ref);
-            out = fma_exact(d.coef, rhs, b);
+            b = sep_base ? base[a] : hi[a];
+            inc = d.coef * rhs;
         } else if (d.mode == 3) {
-            stg(static_cast<float *>(d.dst), idx, rhs);
+            sto<float>(plane(d.dst, pb4, a), o4, rhs);
             continue;
         } else {
-            const float prev = (d.mode == 1) ? rhs : ldg(d.rhs_prev, idx);
-            out = fma_exact(0.5f * d.coef, 3.f * rhs - prev, hi[a]);
-            stg(d.rhs_prev, idx, rhs);
+            const float prev = (d.mode == 1) ? rhs : ldo<float>(plane(d.rhs_prev, pb4, a), o4);
+            b = hi[a];
+            inc = (0.5f * d.coef) * (3.f * rhs - prev);
+            sto<float>(plane(d.rhs_prev, pb4, a), o4, rhs);
         }
-        Storage<STORE>::store(d.dst, idx, a, out, d.ref, salt);
+        Storage<STORE>::store(plane(d.dst, pb, a), os, a, b, inc, d.ref, key0 + (uint32_t)a);
     }
 }
 
 // One RHS evaluation and update for one tile of T cells.
-//   Phase 1  one round of independent device loads: the tile's values, both
-//            halo rings' values (to LDS), this thread's cell geometry and its
-//            ring-1 cell's geometry (to registers);
+//   Phase 1  one round of loads: the tile's values, both halo rings' values
+//            (to LDS), this thread's cell geometry and faces, its ring-1
+//            slot's geometry and the update base (to registers); halo slots
+//            sit at fixed positions, so only the halo values wait on an index;
 //   Phase 2  gradients of tile and ring-1 cells into LDS (each computed once);
 //   Phase 3  per tile cell: face values (own gradient outgoing, staged
 //            neighbour value and gradient incoming), flux sum, BGK source,
 //            update, store.
-// Dynamic LDS: nA = T + h1max region-A records, then region-B records for
-// up to hmax ring-2 cells (sized by the launcher).
+// Dynamic LDS: nA = T + (largest ring-1 slot count) region-A records, then
+// region-B records for the largest ring-2 slot count (sized by the launcher).
 template <int NF, int STORE, int T>
 __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, int2 u, float4 *A, float4 *B) {
+    using S = Storage<STORE>;
     const InstDesc &d = descs[u.x];
     const int tile = u.y;
     const int tid = threadIdx.x;
     const int i = tile * T + tid;
     const bool valid = i < d.n_cells;
-    const int4 hd = ldg(d.hdr, tile);              // {first entry, n1, n2, first ring-1 code}
-    const int n1 = hd.y, nh = hd.y + hd.z;
-    const int a_end = T + n1;                      // local indices below this are region A
+    const int h1s = d.h1s, h2s = d.h2s;
+    const int a_end = T + h1s;                     // local indices below this are region A
+    const int *hidx = d.halo_idx + (size_t)tile * (size_t)(h1s + h2s);
+    const size_t pb = (size_t)d.np * S::SZ;
+    const bool sep_base = d.mode == 0 && d.base != d.src;
 
     // ---- phase 1
+    float h0 = 0.f, base[Q];
     int code[NF];
+    uint2 ln = make_uint2(0, 0), hl = make_uint2(0, 0);
     CellGeo<NF> geo;
+    CellFaces<NF> cf;
     if (valid) {
+        const uint32_t os = (uint32_t)i * S::SZ;
         float f[Q];
 #pragma unroll
-        for (int a = 0; a < Q; a++) f[a] = Storage<STORE>::load(d.src, (size_t)a * d.np + i, a, d.ref);
+        for (int a = 0; a < Q; a++) f[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
+        h0 = f[0];
         wr_f(A + tid * RA, f);
-        const uint2 ln = ldg(d.lnbr, i);
+        ln = ldo<uint2>(d.lnbr, (uint32_t)i * 8u);
 #pragma unroll
         for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
         geo.load(d, i);
-    }
-    int hcell = -1, hcode[NF];
-    CellGeo<NF> hgeo;
-    if (tid < n1) {
-        hcell = ldg(d.halo_idx, hd.x + tid);
+        cf.load(d, i);
+        if (sep_base) {
 #pragma unroll
-        for (int s = 0; s < NF; s++) hcode[s] = ldg(d.halo_code, (size_t)hd.w + (size_t)tid * NF + s);
-        hgeo.load(d, hcell);
+            for (int a = 0; a < Q; a++) base[a] = S::load(plane(d.base, pb, a), os, a, d.ref);
+        }
     }
-    for (int k = tid; k < nh; k += T) {
-        const int c = ldg(d.halo_idx, hd.x + k);
+    int c1 = -1, hcode[NF];
+    float hf0 = 0.f;
+    CellGeo<NF> hgeo;
+    if (tid < h1s) {
+        c1 = ldg(hidx, tid);
+        if (c1 >= 0) {
+            hl = ldg(d.halo_code, (size_t)tile * h1s + tid);
+#pragma unroll
+            for (int k = 0; k < NF; k++) hcode[k] = unpack16(k < 2 ? hl.x : hl.y, k & 1);
+            hgeo.load(d, c1);
+            const uint32_t os = (uint32_t)c1 * S::SZ;
+            float f[Q];
+#pragma unroll
+            for (int a = 0; a < Q; a++) f[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
+            hf0 = f[0];
+            wr_f(A + (T + tid) * RA, f);
+        }
+    }
+    for (int k = tid + T; k < h1s; k += T) {        // ring 1 larger than the tile
+        const int c = ldg(hidx, k);
+        if (c < 0) continue;
+        const uint32_t os = (uint32_t)c * S::SZ;
         float f[Q];
 #pragma unroll
-        for (int a = 0; a < Q; a++) f[a] = Storage<STORE>::load(d.src, (size_t)a * d.np + c, a, d.ref);
-        wr_f(k < n1 ? A + (T + k) * RA : B + (k - n1) * RB, f);
+        for (int a = 1; a < Q; a++) f[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
+        wr_f(A + (T + k) * RA, f);
+    }
+    for (int k = tid; k < h2s; k += T) {
+        const int c = ldg(hidx, h1s + k);
+        if (c < 0) continue;
+        const uint32_t os = (uint32_t)c * S::SZ;
+        float f[Q];
+#pragma unroll
+        for (int a = 1; a < Q; a++) f[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
+        wr_f(B + k * RB, f);
     }
     __syncthreads();
 
@@ -493,29 +565,34 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     {
         float hc[Q], gx[Q], gy[Q];
         if (valid) {
+            hc[0] = h0;
             rd_f(A + tid * RA, hc);
-            gradient_staged<NF>(d, i, geo, hc, code, A, B, a_end, gx, gy);
+            gradient_staged<NF>(d, i, geo, hc, code, ln, A, B, a_end, gx, gy);
             wr_g(A + tid * RA, gx, gy);
         }
-        if (hcell >= 0) {
+        if (c1 >= 0) {
+            hc[0] = hf0;
             rd_f(A + (T + tid) * RA, hc);
-            gradient_staged<NF>(d, hcell, hgeo, hc, hcode, A, B, a_end, gx, gy);
+            gradient_staged<NF>(d, c1, hgeo, hc, hcode, hl, A, B, a_end, gx, gy);
             wr_g(A + (T + tid) * RA, gx, gy);
         }
-        for (int k = tid + T; k < n1; k += T) {       // ring 1 larger than the tile: geometry loaded here
-            const int c = ldg(d.halo_idx, hd.x + k);
+        for (int k = tid + T; k < h1s; k += T) {
+            const int c = ldg(hidx, k);
+            if (c < 0) continue;
+            const uint2 hl2 = ldg(d.halo_code, (size_t)tile * h1s + k);
             int cc[NF];
 #pragma unroll
-            for (int s = 0; s < NF; s++) cc[s] = ldg(d.halo_code, (size_t)hd.w + (size_t)k * NF + s);
+            for (int s = 0; s < NF; s++) cc[s] = unpack16(s < 2 ? hl2.x : hl2.y, s & 1);
             CellGeo<NF> g2;
             g2.load(d, c);
+            hc[0] = S::load(d.src, (uint32_t)c * S::SZ, 0, d.ref);
             rd_f(A + (T + k) * RA, hc);
-            gradient_staged<NF>(d, c, g2, hc, cc, A, B, a_end, gx, gy);
+            gradient_staged<NF>(d, c, g2, hc, cc, hl2, A, B, a_end, gx, gy);
             wr_g(A + (T + k) * RA, gx, gy);
         }
     }
     __syncthreads();
-    if (valid) tile_update<NF, STORE>(d, i, code, geo, A + tid * RA, A);
+    if (valid) tile_update<NF, STORE>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A);
 }
 
 template <int NF, int STORE, int T>
@@ -581,17 +658,17 @@ int grid_blocks(const UnitTable &ut, int persistent, int nf, int storage, size_t
 
 }  // namespace
 
-size_t stage_lds_bytes(int T, int hmax, int h1max) {
-    return ((size_t)(T + h1max) * RA + (size_t)(hmax > h1max ? hmax : h1max) * RB) * sizeof(float4);
+size_t stage_lds_bytes(int T, int h2max, int h1max) {
+    return ((size_t)(T + h1max) * RA + (size_t)h2max * RB) * sizeof(float4);
 }
 
 hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                        int xcd_remap, int persistent, int hmax, int h1max, hipStream_t stream) {
+                        int xcd_remap, int persistent, int h2max, int h1max, hipStream_t stream) {
     if (ut.n_units == 0) return hipSuccess;
     const int2 *units = ut.units;
     int n_units = ut.n_units;
     int nA = ut.block + h1max;
-    const size_t lds = stage_lds_bytes(ut.block, hmax, h1max);
+    const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
     void *args[] = {(void *)&descs_dev, (void *)&units, (void *)&n_units, (void *)&xcd_remap, (void *)&nA};
     return hipLaunchKernel(pick(nf, storage, ut.block, persistent), dim3(grid_blocks(ut, persistent, nf, storage, lds)),
                            dim3(ut.block), args, lds, stream);
@@ -599,7 +676,7 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
 
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                          int xcd_remap, int persistent, int hmax, int h1max, void **argbuf) {
+                          int xcd_remap, int persistent, int h2max, int h1max, void **argbuf) {
     // argbuf: caller-owned storage for the argument values, alive until the graph is instantiated
     struct Args { const InstDesc *d; const int2 *u; int n; int x; int nA; };
     Args *a = reinterpret_cast<Args *>(argbuf[0]);
@@ -607,7 +684,7 @@ hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode
     void **kp = argbuf + 1;
     kp[0] = &a->d; kp[1] = &a->u; kp[2] = &a->n; kp[3] = &a->x; kp[4] = &a->nA;
     hipKernelNodeParams p{};
-    const size_t lds = stage_lds_bytes(ut.block, hmax, h1max);
+    const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
     p.func = const_cast<void *>(pick(nf, storage, ut.block, persistent));
     p.gridDim = dim3(grid_blocks(ut, persistent, nf, storage, lds));
     p.blockDim = dim3(ut.block);
