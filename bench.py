@@ -88,7 +88,7 @@ def cpu_baseline(inst, scheme="rk4", target_s=12.0):
 
 
 def make_solver(F, inst, scheme, storage, reorder=None):
-    mesh = F.Mesh(inst.mesh, reorder=F.REORDER_HILBERT if reorder is None else reorder)
+    mesh = F.Mesh(inst.mesh, reorder=F.REORDER_BISECT if reorder is None else reorder)
     s = F.Solver(mesh, F.make_params(tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme=scheme,
                                      storage=storage, u_dev=inst.u0),
                  u=np.tile(np.asarray(inst.u0, float), (inst.n_cells, 1)))
@@ -98,7 +98,7 @@ def make_solver(F, inst, scheme, storage, reorder=None):
 def streaming(F, W, stream):
     out = {}
     m = W.streaming()
-    mesh = F.Mesh(m, reorder=F.REORDER_HILBERT)
+    mesh = F.Mesh(m, reorder=F.REORDER_BISECT)
     nf = mesh.info()["nf"]
     for scheme, k in (("euler", 20), ("rk4", 5)):
         s = F.Solver(mesh, F.make_params(tau=3e-5, scheme=scheme, storage="fp32dev"))

@@ -61,7 +61,7 @@ typedef struct {
 
 enum { FVLBM_SCHEME_EULER = 0, FVLBM_SCHEME_RK4 = 1, FVLBM_SCHEME_AB2 = 2 };
 enum { FVLBM_STORE_FP32 = 0, FVLBM_STORE_FP32_DEV = 1, FVLBM_STORE_FP16_DEV = 2 };
-enum { FVLBM_REORDER_NONE = 0, FVLBM_REORDER_RCM = 1, FVLBM_REORDER_HILBERT = 2 };
+enum { FVLBM_REORDER_NONE = 0, FVLBM_REORDER_RCM = 1, FVLBM_REORDER_HILBERT = 2, FVLBM_REORDER_BISECT = 3 };
 enum { FVLBM_FLAG_FORCE_DT = 1 };
 
 typedef struct {
@@ -92,7 +92,9 @@ typedef struct fvlbm_batch fvlbm_batch;      /* opaque; a set of solvers advance
  *   groups        [n_groups]   boundary-condition groups
  *   periodic_pairs[2*n_periodic] boundary-edge indices (a, b) joined by periodicity
  *   periodic_shift[2*n_periodic] vector added to positions on b's side to bring them next to a
- *   reorder       FVLBM_REORDER_*; internal cell order for locality (outputs stay in input order)
+ *   reorder       FVLBM_REORDER_*; internal cell order for locality (outputs stay in input order).
+ *                 FVLBM_REORDER_BISECT (recursive graph bisection) gives the step kernel's
+ *                 tiles the shortest halos on meshes of any cell aspect ratio
  * Geometry and least-squares coefficients are computed on the device in FP64
  * (Eq. 12 with w = 1/|x_n - x_i|^2; f at the area centroid) and stored as FP32.
  * Errors: FVLBM_E_ARG, FVLBM_E_MESH, FVLBM_E_NOMEM, FVLBM_E_DEVICE.  Syncs hip_stream.

@@ -1,6 +1,7 @@
 // Host-side mesh topology: edge matching, boundary groups, periodic pairs,
-// validation, and cell reordering (reverse Cuthill-McKee or Hilbert curve)
-// so that a wavefront's neighbour gathers stay within a few cache lines.
+// validation, and cell reordering (reverse Cuthill-McKee, Hilbert curve or
+// recursive graph bisection) so that a wavefront's neighbour gathers stay
+// within a few cache lines and a tile of consecutive cells has a short halo.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -55,6 +56,90 @@ std::vector<int> order_hilbert(const std::vector<double> &cx, const std::vector<
     return perm;
 }
 
+// Recursive graph bisection over the cell adjacency (CSR).  A part is split
+// by the graph distances d1, d2 to the two ends p1, p2 of a pseudo-diameter:
+// cells with smaller d1 - d2 (closer to p1) form the first half.  The cut is
+// a level set of a graph coordinate, so both halves stay compact in graph
+// distance whatever the cell aspect ratios, and every aligned block of 512
+// (at the top levels) or 64 cells (below) is one compact part: tiles of
+// consecutive cells get short halos.
+class Bisector {
+  public:
+    Bisector(int n, const std::vector<int> &ptr, const std::vector<int> &adj)
+        : n_(n), ptr_(ptr), adj_(adj), part_(n, -1), d1_(n, -1), d2_(n, -1) {}
+
+    std::vector<int> order() {
+        std::vector<int> cells(n_);
+        std::iota(cells.begin(), cells.end(), 0);
+        out_.reserve(n_);
+        split(cells, 0);
+        return out_;
+    }
+
+  private:
+    // BFS distances from s within the current part; returns a farthest reached cell.
+    int bfs(int s, int tag, std::vector<int> &dist, const std::vector<int> &cells) {
+        for (int c : cells) dist[c] = -1;
+        q_.clear();
+        q_.push_back(s);
+        dist[s] = 0;
+        int last = s;
+        for (size_t h = 0; h < q_.size(); h++) {
+            const int c = q_[h];
+            last = c;
+            for (int e = ptr_[c]; e < ptr_[c + 1]; e++) {
+                const int j = adj_[e];
+                if (part_[j] == tag && dist[j] < 0) { dist[j] = dist[c] + 1; q_.push_back(j); }
+            }
+        }
+        return last;
+    }
+
+    static int split_size(size_t m) {
+        const size_t blk = m >= 1024 ? 512 : 64;
+        size_t left = (m / 2 + blk / 2) / blk * blk;
+        if (left < blk) left = blk;
+        if (left >= m) left = m - 1;
+        return (int)left;
+    }
+
+    void split(std::vector<int> &cells, int depth) {
+        const int tag = ++tag_;
+        for (int c : cells) part_[c] = tag;
+        if (cells.size() > 1) {
+            const int p1 = bfs(bfs(cells[0], tag, d1_, cells), tag, d1_, cells);
+            int p2 = p1, far = -1;
+            for (int c : cells)
+                if (d1_[c] > far) { far = d1_[c]; p2 = c; }
+            bfs(p2, tag, d2_, cells);
+            // key: reached cells by d1 - d2, cells of other components last
+            const long span = (long)n_ + 1;
+            auto key = [&](int c) -> long {
+                if (d1_[c] < 0 || d2_[c] < 0) return (2 * span + 1) * span + c;
+                return ((long)(d1_[c] - d2_[c]) + span) * span + c;
+            };
+            if (cells.size() <= 64) {
+                std::sort(cells.begin(), cells.end(), [&](int a, int b) { return key(a) < key(b); });
+            } else {
+                const int left = split_size(cells.size());
+                std::nth_element(cells.begin(), cells.begin() + left, cells.end(),
+                                 [&](int a, int b) { return key(a) < key(b); });
+                std::vector<int> a(cells.begin(), cells.begin() + left), b(cells.begin() + left, cells.end());
+                std::vector<int>().swap(cells);
+                split(a, depth + 1);
+                split(b, depth + 1);
+                return;
+            }
+        }
+        out_.insert(out_.end(), cells.begin(), cells.end());
+    }
+
+    int n_;
+    const std::vector<int> &ptr_, &adj_;
+    std::vector<int> part_, d1_, d2_, q_, out_;
+    int tag_ = 0;
+};
+
 // Reverse Cuthill-McKee over the cell adjacency (CSR).
 std::vector<int> order_rcm(int n, const std::vector<int> &adj_ptr, const std::vector<int> &adj) {
     std::vector<int> deg(n);
@@ -108,7 +193,7 @@ fvlbm_status build_topology(int32_t n_nodes, const double *xy, int32_t n_cells,
     if (n_nodes <= 0 || !xy || n_cells <= 0 || !cell_ptr || !cell_nodes || n_bfaces < 0 ||
         (n_bfaces > 0 && (!bface_nodes || !bface_group)) || n_groups < 0 || n_groups > MAX_GROUPS ||
         (n_groups > 0 && !groups) || n_periodic < 0 ||
-        (n_periodic > 0 && (!periodic_pairs || !periodic_shift)) || reorder < 0 || reorder > 2) {
+        (n_periodic > 0 && (!periodic_pairs || !periodic_shift)) || reorder < 0 || reorder > 3) {
         err = "bad arguments to fvlbm_create_mesh";
         return FVLBM_E_ARG;
     }
@@ -196,7 +281,7 @@ fvlbm_status build_topology(int32_t n_nodes, const double *xy, int32_t n_cells,
     // reorder
     std::vector<int> perm(n_cells);
     std::iota(perm.begin(), perm.end(), 0);
-    if (reorder == FVLBM_REORDER_RCM) {
+    if (reorder == FVLBM_REORDER_RCM || reorder == FVLBM_REORDER_BISECT) {
         std::vector<int> ptr(n_cells + 1, 0), adj;
         adj.reserve((size_t)n_cells * 4);
         for (int c = 0; c < n_cells; c++) {
@@ -206,7 +291,8 @@ fvlbm_status build_topology(int32_t n_nodes, const double *xy, int32_t n_cells,
             }
             ptr[c + 1] = (int)adj.size();
         }
-        perm = order_rcm(n_cells, ptr, adj);
+        if (reorder == FVLBM_REORDER_RCM) perm = order_rcm(n_cells, ptr, adj);
+        else perm = Bisector(n_cells, ptr, adj).order();
     } else if (reorder == FVLBM_REORDER_HILBERT) {
         std::vector<double> cx(n_cells), cy(n_cells);
         for (int c = 0; c < n_cells; c++) {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfvlbm.so")
 
 EULER, RK4, AB2 = 0, 1, 2
 FP32, FP32_DEV, FP16_DEV = 0, 1, 2
-REORDER_NONE, REORDER_RCM, REORDER_HILBERT = 0, 1, 2
+REORDER_NONE, REORDER_RCM, REORDER_HILBERT, REORDER_BISECT = 0, 1, 2, 3
 SCHEMES = {"euler": EULER, "rk4": RK4, "ab2": AB2}
 STORAGES = {"fp32": FP32, "fp32dev": FP32_DEV, "fp16dev": FP16_DEV}
 FLAG_FORCE_DT = 1
@@ -127,7 +127,7 @@ def _stream_handle(stream=None):
 class Mesh:
     """A mesh resident on the device (fvlbm_create_mesh)."""
 
-    def __init__(self, raw, reorder: int = REORDER_RCM, stream=None):
+    def __init__(self, raw, reorder: int = REORDER_BISECT, stream=None):
         L = lib()
         self.raw = raw
         self.n_cells = raw.n_cells

@@ -79,7 +79,7 @@ class GpuBackend:
 
     def create(self, inst):
         F = self.F
-        mesh = F.Mesh(inst.mesh, reorder=F.REORDER_HILBERT)
+        mesh = F.Mesh(inst.mesh, reorder=F.REORDER_BISECT)
         p = F.make_params(tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme=self.scheme, storage=self.storage,
                           u_dev=inst.u0, residual_lag=self.chunk)
         s = F.Solver(mesh, p, u=np.tile(np.asarray(inst.u0, float), (inst.n_cells, 1)))

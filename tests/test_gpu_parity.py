@@ -75,7 +75,7 @@ RHS_MESHES = {
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp32dev"])
-@pytest.mark.parametrize("reorder", [0, 1, 2])
+@pytest.mark.parametrize("reorder", [0, 1, 2, 3])
 @pytest.mark.parametrize("name", list(RHS_MESHES))
 def test_rhs_matches_oracle(F, O, name, reorder, storage):
     make, tau = RHS_MESHES[name]
