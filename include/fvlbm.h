@@ -180,7 +180,7 @@ void fvlbm_batch_destroy(fvlbm_batch *b);
  * of one workgroup per tile.  A schedule never changes the per-cell
  * arithmetic: results are bitwise identical under every schedule.
  * Errors: FVLBM_E_ARG (unsupported tile size, or tile plus halo do not fit
- * the 64 KiB LDS of a workgroup). */
+ * the LDS a workgroup may use: 160 KiB on gfx950). */
 fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap, int32_t persistent);
 fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap, int32_t *persistent);
 fvlbm_status fvlbm_batch_set_schedule(fvlbm_batch *b, int32_t block, int32_t xcd_remap, int32_t persistent);

@@ -389,7 +389,7 @@ fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const doub
         std::string err;
         fvlbm_status tst = get_tiles(mesh->dev, s->sched.block, &s->tiles, err);
         if (tst != FVLBM_OK) return fail(tst, err);
-        if (stage_lds_bytes(s->sched.block, s->tiles->h2max, s->tiles->h1max) > 65536) {
+        if (stage_lds_bytes(s->sched.block, s->tiles->h2max, s->tiles->h1max) > stage_lds_limit()) {
             s->sched.block = 128;
             tst = get_tiles(mesh->dev, s->sched.block, &s->tiles, err);
             if (tst != FVLBM_OK) return fail(tst, err);
@@ -574,7 +574,7 @@ fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_rema
     std::string err;
     fvlbm_status st = get_tiles(s->mesh->dev, block, &tt, err);
     if (st != FVLBM_OK) return fail(st, err);
-    if (stage_lds_bytes(block, tt->h2max, tt->h1max) > 65536) return fail(FVLBM_E_ARG, "tile and halo do not fit the LDS at this block size");
+    if (stage_lds_bytes(block, tt->h2max, tt->h1max) > stage_lds_limit()) return fail(FVLBM_E_ARG, "tile and halo do not fit the LDS at this block size");
     if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "stream synchronize failed");
     s->sched.block = block;
     s->sched.xcd_remap = xcd_remap ? 1 : 0;
@@ -616,7 +616,7 @@ fvlbm_status batch_build(fvlbm_batch *b) {
         for (int k = 0; k < N_KINDS; k++) all[(size_t)k * n + i] = d[k];
     }
     for (int t = 0; t < 2; t++)
-        if (stage_lds_bytes(b->sched.block, h2max[t], h1max[t]) > 65536)
+        if (stage_lds_bytes(b->sched.block, h2max[t], h1max[t]) > stage_lds_limit())
             return fail(FVLBM_E_ARG, "batch tiles do not fit the LDS at this block size");
     if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "stream synchronize failed");
     free_graphs(b->graphs);

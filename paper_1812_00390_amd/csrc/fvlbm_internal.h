@@ -166,6 +166,8 @@ struct UnitTable {
 hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
                         int xcd_remap, int persistent, int h2max, int h1max, hipStream_t stream);
 size_t stage_lds_bytes(int T, int h2max, int h1max);
+// LDS a workgroup may use on the current device (160 KiB on gfx950).
+size_t stage_lds_limit();
 // Same as a kernel node for a graph.
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,

@@ -83,21 +83,28 @@ __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // (cell, direction): results do not depend on launch order, schedule,
 // batching or graphs.
 
-// 24 well-mixed bits (the top of a 24-bit product, full-rate multiply)
-__device__ inline uint32_t mix(uint32_t x) { return __umul24(x ^ (x >> 15), 0x9e3779u); }
+// A hash with avalanche in every input bit (full-rate 24-bit multiplies and
+// shifts): a small change of the input changes the output unpredictably.
+__device__ inline uint32_t mix(uint32_t x) {
+    x = __umul24(x ^ (x >> 15), 0x9e3779u);
+    x = __umul24(x ^ (x >> 13), 0x85ebcau);
+    return x ^ (x >> 16);
+}
 
-// b + p rounded to FP32 with a centred dither of one ulp of b
+// b + p rounded to FP32 with a centred dither of one ulp of b.  The dither is
+// drawn from the increment's bits, never from the bits being rounded away.
 __device__ inline float add_sr(float b, float p, uint32_t key) {
     const float g = __uint_as_float(__float_as_uint(b) & 0x7f800000u) * 0x1p-47f;   // ulp(b) / 2^24; 0 for b = 0
     const int32_t r = (int32_t)mix(__float_as_uint(p) ^ key) >> 8;                 // uniform in [-2^23, 2^23)
     return b + fmaf((float)r, g, p);
 }
 
-// unbiased rounding of a float to FP16: add 13 random bits below the FP16
-// mantissa, then truncate (exact for FP16 normals)
-__device__ inline __half round_fp16(float v, uint32_t key) {
+// unbiased rounding of v = (b + p) / unit to FP16: 13 random bits (from the
+// increment p) are added below the FP16 mantissa, then truncated (exact for
+// FP16 normals)
+__device__ inline __half round_fp16(float v, float p, uint32_t key) {
     const uint32_t b = __float_as_uint(v);
-    const uint32_t mag = (b & 0x7fffffffu) + (mix(b ^ key) >> 19);
+    const uint32_t mag = (b & 0x7fffffffu) + (mix(__float_as_uint(p) ^ key) >> 19);
     return __float2half_rz(__uint_as_float((b & 0x80000000u) | mag));
 }
 
@@ -131,7 +138,7 @@ struct Storage<FVLBM_STORE_FP16_DEV> {
         return __half2float(ldo<__half>(p, off)) * (WT[a] * r.scale);
     }
     __device__ static void store(void *p, uint32_t off, int a, float b, float inc, const RefDev &r, uint32_t key) {
-        sto<__half>(p, off, round_fp16((b + inc) * r.inv_unit[a], key));
+        sto<__half>(p, off, round_fp16((b + inc) * r.inv_unit[a], inc, key));
     }
 };
 
@@ -261,31 +268,58 @@ __device__ inline float2 corner(const InstDesc &d, int k, int c) {
     return ldo<float2>(plane(d.vxy, (size_t)d.np * 8, k), (uint32_t)c * 8u);
 }
 
-// Least-squares data of one cell held in registers: stencil offsets and the
-// inverse least-squares matrix.
+// Least-squares data of one cell held in registers: the stencil offsets and
+// the inverse of M = sum_k w_k d_k d_k^T, w_k = 1/|d_k|^2 (Eq. 12), formed
+// here from the offsets (M is dimensionless and well scaled, so FP32 is
+// ample) instead of being read from memory.
 template <int NF>
 struct CellGeo {
     float2 dk[NF];
     float m11, m12, m22;
     __device__ void load(const InstDesc &d, int c) {
-        const uint32_t o8 = (uint32_t)c * 8u, o4 = (uint32_t)c * 4u;
+        const uint32_t o8 = (uint32_t)c * 8u;
 #pragma unroll
         for (int k = 0; k < NF; k++) dk[k] = ldo<float2>(plane(d.dxy, (size_t)d.np * 8, k), o8);
-        m11 = ldo<float>(d.minv, o4);
-        m12 = ldo<float>(plane(d.minv, (size_t)d.np * 4, 1), o4);
-        m22 = ldo<float>(plane(d.minv, (size_t)d.np * 4, 2), o4);
+    }
+    // padded slots (no face) do not enter M
+    __device__ void invert(const int (&code)[NF]) {
+        float a = 0.f, b = 0.f, e = 0.f;
+#pragma unroll
+        for (int k = 0; k < NF; k++) {
+            if (code[k] < PAD_BELOW) continue;
+            const float w = frcp(fmaf(dk[k].x, dk[k].x, dk[k].y * dk[k].y));
+            const float wx = w * dk[k].x, wy = w * dk[k].y;
+            a = fmaf(wx, dk[k].x, a);
+            b = fmaf(wx, dk[k].y, b);
+            e = fmaf(wy, dk[k].y, e);
+        }
+        const float idet = frcp(fmaf(a, e, -(b * b)));
+        m11 = e * idet;
+        m12 = -b * idet;
+        m22 = a * idet;
     }
 };
 
-// Face data of one tile cell: corner offsets and 1/A.
+// Face data of one tile cell: corner offsets from the centroid and 1/A.  A
+// triangle's centroid is its vertex mean, so its third offset is minus the sum
+// of the other two and is not read.
 template <int NF>
 struct CellFaces {
     float2 v[NF];
     float inva;
     __device__ void load(const InstDesc &d, int c) {
 #pragma unroll
-        for (int k = 0; k < NF; k++) v[k] = corner(d, k, c);
-        inva = ldo<float>(d.inva, (uint32_t)c * 4u);
+        for (int k = 0; k < (NF == 3 ? 2 : NF); k++) v[k] = corner(d, k, c);
+    }
+    __device__ void finish() {
+        if (NF == 3) v[2] = make_float2(-(v[0].x + v[1].x), -(v[0].y + v[1].y));
+        float twice_a = 0.f;                    // shoelace over the corner offsets
+#pragma unroll
+        for (int k = 0; k < NF; k++) {
+            const float2 p = v[k], q = v[k + 1 == NF ? 0 : k + 1];
+            twice_a = fmaf(p.x, q.y, fmaf(-p.y, q.x, twice_a));
+        }
+        inva = 2.f * frcp(twice_a);
     }
 };
 
@@ -326,14 +360,14 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, int c, const Ce
     const Macro m = moments(hc, d.ref);
     float he[Q];
     heq(m.drho, m.rho, m.jx, m.jy, d.ref, he);
-    const float inva = ldo<float>(d.inva, (uint32_t)c * 4u);
 #pragma unroll 1
     for (int k = 0; k < NF; k++) {
         const int ck = unpack16(k < 2 ? packed.x : packed.y, k & 1);
         if (ck >= 0 || ck < PAD_BELOW) continue;
         const float2 dk = ldo<float2>(plane(d.dxy, (size_t)d.np * 8, k), (uint32_t)c * 8u);
         const float2 w = lsq_coef(dk, geo.m11, geo.m12, geo.m22);
-        const float2 gn = scaled_normal(corner(d, k, c), corner(d, k + 1 == NF ? 0 : k + 1, c), inva);
+        // an outward normal of face k (only its direction enters the ghost values)
+        const float2 gn = scaled_normal(corner(d, k, c), corner(d, k + 1 == NF ? 0 : k + 1, c), 1.f);
         float phi[Q];
         boundary_value(d.groups[-1 - ck], hc, m, he, gn, d.ref, phi);
 #pragma unroll
@@ -384,7 +418,16 @@ __device__ inline void boundary_flux(const InstDesc &d, int i, const float hi[Q]
     for (int k = 0; k < NF; k++) {
         const int ck = unpack16(k < 2 ? packed.x : packed.y, k & 1);
         if (ck >= 0 || ck < PAD_BELOW) continue;
-        const float2 v0 = corner(d, k, i), v1 = corner(d, k + 1 == NF ? 0 : k + 1, i);
+        float2 v0, v1;
+        if (NF == 3) {                          // the same corner offsets as the interior faces use
+            const float2 c0 = corner(d, 0, i), c1 = corner(d, 1, i);
+            const float2 c2 = make_float2(-(c0.x + c1.x), -(c0.y + c1.y));
+            v0 = k == 0 ? c0 : (k == 1 ? c1 : c2);
+            v1 = k == 0 ? c1 : (k == 1 ? c2 : c0);
+        } else {
+            v0 = corner(d, k, i);
+            v1 = corner(d, k + 1 == NF ? 0 : k + 1, i);
+        }
         const float2 g = scaled_normal(v0, v1, inva);
         const float2 r = make_float2(0.5f * (v0.x + v1.x), 0.5f * (v0.y + v1.y));   // x_f - x_i
         const GroupDev &gr = d.groups[-1 - ck];
@@ -501,63 +544,75 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     const bool sep_base = d.mode == 0 && d.base != d.src;
 
     // ---- phase 1
-    float h0 = 0.f, base[Q];
+    // Straight-line loads (indices clamped into range instead of branching, so
+    // the compiler can wait on each load precisely): halo slot indices first,
+    // then the own cell's data, then the halo values as soon as their indices
+    // return, then the update base.
+    const int hs = h1s + h2s;
+    const int hraw1 = ldg(hidx, tid < hs ? tid : 0);
+    const int hraw2 = ldg(hidx, h1s + tid < hs ? h1s + tid : 0);
+    const uint2 hl = ldg(d.halo_code, (size_t)tile * h1s + (tid < h1s ? tid : 0));
+    const int c1 = tid < h1s ? hraw1 : -1;
+    const int c2 = tid < h2s ? hraw2 : -1;
+
+    float h0 = 0.f, base[Q], f[Q];
     int code[NF];
-    uint2 ln = make_uint2(0, 0), hl = make_uint2(0, 0);
     CellGeo<NF> geo;
     CellFaces<NF> cf;
-    if (valid) {
-        const uint32_t os = (uint32_t)i * S::SZ;
-        float f[Q];
+    const int ic = valid ? i : 0;
+    const uint32_t os = (uint32_t)ic * S::SZ;
 #pragma unroll
-        for (int a = 0; a < Q; a++) f[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
-        h0 = f[0];
-        wr_f(A + tid * RA, f);
-        ln = ldo<uint2>(d.lnbr, (uint32_t)i * 8u);
-#pragma unroll
-        for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
-        geo.load(d, i);
-        cf.load(d, i);
-        if (sep_base) {
-#pragma unroll
-            for (int a = 0; a < Q; a++) base[a] = S::load(plane(d.base, pb, a), os, a, d.ref);
-        }
-    }
-    int c1 = -1, hcode[NF];
-    float hf0 = 0.f;
+    for (int a = 0; a < Q; a++) f[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
+    const uint2 ln = ldo<uint2>(d.lnbr, (uint32_t)ic * 8u);
+    geo.load(d, ic);
+    cf.load(d, ic);
+    int hcode[NF];
+    float hf0 = 0.f, f1[Q], f2[Q];
     CellGeo<NF> hgeo;
-    if (tid < h1s) {
-        c1 = ldg(hidx, tid);
-        if (c1 >= 0) {
-            hl = ldg(d.halo_code, (size_t)tile * h1s + tid);
+    {
+        const uint32_t os1 = (uint32_t)(c1 >= 0 ? c1 : 0) * S::SZ;
 #pragma unroll
-            for (int k = 0; k < NF; k++) hcode[k] = unpack16(k < 2 ? hl.x : hl.y, k & 1);
-            hgeo.load(d, c1);
-            const uint32_t os = (uint32_t)c1 * S::SZ;
-            float f[Q];
+        for (int a = 0; a < Q; a++) f1[a] = S::load(plane(d.src, pb, a), os1, a, d.ref);
+        hgeo.load(d, c1 >= 0 ? c1 : 0);
+        const uint32_t os2 = (uint32_t)(c2 >= 0 ? c2 : 0) * S::SZ;
 #pragma unroll
-            for (int a = 0; a < Q; a++) f[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
-            hf0 = f[0];
-            wr_f(A + (T + tid) * RA, f);
-        }
+        for (int a = 1; a < Q; a++) f2[a] = S::load(plane(d.src, pb, a), os2, a, d.ref);
     }
+    if (sep_base) {
+#pragma unroll
+        for (int a = 0; a < Q; a++) base[a] = S::load(plane(d.base, pb, a), os, a, d.ref);
+    }
+    h0 = f[0];
+#pragma unroll
+    for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
+    geo.invert(code);
+    cf.finish();
+    if (valid) wr_f(A + tid * RA, f);
+    if (c1 >= 0) {
+        hf0 = f1[0];
+        wr_f(A + (T + tid) * RA, f1);
+#pragma unroll
+        for (int k = 0; k < NF; k++) hcode[k] = unpack16(k < 2 ? hl.x : hl.y, k & 1);
+        hgeo.invert(hcode);
+    }
+    if (c2 >= 0) wr_f(B + tid * RB, f2);
     for (int k = tid + T; k < h1s; k += T) {        // ring 1 larger than the tile
         const int c = ldg(hidx, k);
         if (c < 0) continue;
         const uint32_t os = (uint32_t)c * S::SZ;
-        float f[Q];
+        float g[Q];
 #pragma unroll
-        for (int a = 1; a < Q; a++) f[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
-        wr_f(A + (T + k) * RA, f);
+        for (int a = 1; a < Q; a++) g[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
+        wr_f(A + (T + k) * RA, g);
     }
-    for (int k = tid; k < h2s; k += T) {
+    for (int k = tid + T; k < h2s; k += T) {        // ring 2 larger than the tile
         const int c = ldg(hidx, h1s + k);
         if (c < 0) continue;
         const uint32_t os = (uint32_t)c * S::SZ;
-        float f[Q];
+        float g[Q];
 #pragma unroll
-        for (int a = 1; a < Q; a++) f[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
-        wr_f(B + k * RB, f);
+        for (int a = 1; a < Q; a++) g[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
+        wr_f(B + k * RB, g);
     }
     __syncthreads();
 
@@ -585,6 +640,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
             for (int s = 0; s < NF; s++) cc[s] = unpack16(s < 2 ? hl2.x : hl2.y, s & 1);
             CellGeo<NF> g2;
             g2.load(d, c);
+            g2.invert(cc);
             hc[0] = S::load(d.src, (uint32_t)c * S::SZ, 0, d.ref);
             rd_f(A + (T + k) * RA, hc);
             gradient_staged<NF>(d, c, g2, hc, cc, hl2, A, B, a_end, gx, gy);
@@ -658,6 +714,13 @@ int grid_blocks(const UnitTable &ut, int persistent, int nf, int storage, size_t
 
 }  // namespace
 
+size_t stage_lds_limit() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 65536;
+    return (size_t)v;
+}
+
 size_t stage_lds_bytes(int T, int h2max, int h1max) {
     return ((size_t)(T + h1max) * RA + (size_t)h2max * RB) * sizeof(float4);
 }
@@ -670,8 +733,12 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
     int nA = ut.block + h1max;
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
     void *args[] = {(void *)&descs_dev, (void *)&units, (void *)&n_units, (void *)&xcd_remap, (void *)&nA};
-    return hipLaunchKernel(pick(nf, storage, ut.block, persistent), dim3(grid_blocks(ut, persistent, nf, storage, lds)),
-                           dim3(ut.block), args, lds, stream);
+    const void *fn_ptr = pick(nf, storage, ut.block, persistent);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn_ptr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipLaunchKernel(fn_ptr, dim3(grid_blocks(ut, persistent, nf, storage, lds)), dim3(ut.block), args, lds, stream);
 }
 
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
@@ -686,6 +753,10 @@ hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode
     hipKernelNodeParams p{};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
     p.func = const_cast<void *>(pick(nf, storage, ut.block, persistent));
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(p.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     p.gridDim = dim3(grid_blocks(ut, persistent, nf, storage, lds));
     p.blockDim = dim3(ut.block);
     p.sharedMemBytes = (unsigned)lds;
