@@ -114,7 +114,8 @@ fvlbm_status make_units(const std::vector<std::pair<int, int>> &inst, int block,
     if (ut.units) { hipFree(ut.units); ut.units = nullptr; }
     ut.n_units = (int)units.size();
     ut.block = block;
-    if (units.empty()) return FVLBM_OK;
+    ut.direct = inst.size() == 1 && inst[0].first == 0;   // unit b is (instance 0, tile b): no table lookup
+    if (units.empty() || ut.direct) return FVLBM_OK;
     if (hipMalloc(&ut.units, units.size() * sizeof(int2)) != hipSuccess) return fail(FVLBM_E_NOMEM, "unit table allocation failed");
     if (hipMemcpy(ut.units, units.data(), units.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
         return fail(FVLBM_E_DEVICE, "unit table copy failed");

@@ -155,9 +155,10 @@ struct Schedule {
 
 // Work units: (instance, tile index) per block; built for a schedule.
 struct UnitTable {
-    int2 *units = nullptr;   // device
+    int2 *units = nullptr;   // device; null when direct
     int n_units = 0;
     int block = 0;
+    bool direct = false;     // one instance: unit b is (0, b), the kernel needs no table
 };
 
 // Launch one RHS-evaluation stage over all units (one unit = one tile of

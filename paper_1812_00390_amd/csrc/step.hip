@@ -656,9 +656,11 @@ __global__ void __launch_bounds__(T) k_tile(const InstDesc *__restrict__ descs,
                                             const int2 *__restrict__ units, int n_units,
                                             int xcd_remap, int nA) {
     extern __shared__ float4 lds4[];
-    tile_body<NF, STORE, T>(descs, units[remap_block(blockIdx.x, n_units, xcd_remap)], lds4, lds4 + nA * RA);
+    const int ub = remap_block(blockIdx.x, n_units, xcd_remap);
+    tile_body<NF, STORE, T>(descs, units ? units[ub] : make_int2(0, ub), lds4, lds4 + nA * RA);
 }
 
+// (units null: a single instance whose unit b is tile b.)
 // Persistent form: a grid sized to the resident capacity walks the unit list
 // (a multiple of 8 blocks, so each block stays on one XCD's range of tiles).
 template <int NF, int STORE, int T>
@@ -666,8 +668,9 @@ __global__ void __launch_bounds__(T) k_tile_persistent(const InstDesc *__restric
                                                        const int2 *__restrict__ units, int n_units,
                                                        int xcd_remap, int nA) {
     extern __shared__ float4 lds4[];
-    for (int ub = blockIdx.x; ub < n_units; ub += gridDim.x) {
-        tile_body<NF, STORE, T>(descs, units[remap_block(ub, n_units, xcd_remap)], lds4, lds4 + nA * RA);
+    for (int b = blockIdx.x; b < n_units; b += gridDim.x) {
+        const int ub = remap_block(b, n_units, xcd_remap);
+        tile_body<NF, STORE, T>(descs, units ? units[ub] : make_int2(0, ub), lds4, lds4 + nA * RA);
         __syncthreads();             // the next unit reuses the LDS records
     }
 }
