@@ -60,7 +60,7 @@ typedef struct {
 } fvlbm_bc;
 
 enum { FVLBM_SCHEME_EULER = 0, FVLBM_SCHEME_RK4 = 1, FVLBM_SCHEME_AB2 = 2 };
-enum { FVLBM_STORE_FP32 = 0, FVLBM_STORE_FP32_DEV = 1, FVLBM_STORE_FP16_DEV = 2 };
+enum { FVLBM_STORE_FP32 = 0, FVLBM_STORE_FP32_DEV = 1, FVLBM_STORE_FP16_DEV = 2, FVLBM_STORE_I16_DEV = 3 };
 enum { FVLBM_REORDER_NONE = 0, FVLBM_REORDER_RCM = 1, FVLBM_REORDER_HILBERT = 2, FVLBM_REORDER_BISECT = 3 };
 enum { FVLBM_FLAG_FORCE_DT = 1 };
 
@@ -70,7 +70,9 @@ typedef struct {
     double cfl;            /* CFL number used when dt == 0 */
     double u_ref;          /* |U|max of Eq. 14, used when dt == 0 */
     int32_t scheme;        /* FVLBM_SCHEME_* */
-    int32_t storage;       /* FVLBM_STORE_*: f as FP32, h = f - f_eq(rho0, u_dev) as FP32, or h/(w S) as FP16 */
+    int32_t storage;       /* FVLBM_STORE_*: f as FP32, h = f - f_eq(rho0, u_dev) as FP32, h/(w S) as FP16,
+                              or h as 16-bit block-scaled values (per cell nine int16 mantissas and one
+                              exponent byte: 19 bytes per cell, 15 bits for the largest deviation) */
     double rho0;           /* reference density of the deviation storage (and of Step 0 when no field is given) */
     double fp16_scale;     /* S of the FP16 deviation storage; 0 = 3 |u_ref| (or 0.3 if u_ref = 0) */
     int32_t residual_lag;  /* steps between velocity snapshots for the residual (Eq. 32); 0 = 1000 */

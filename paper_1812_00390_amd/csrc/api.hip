@@ -24,7 +24,11 @@ fvlbm_status fail(fvlbm_status st, const std::string &msg) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int storage_bytes(int storage) { return storage == FVLBM_STORE_FP16_DEV ? 2 : 4; }
+// bytes of one copy of the distributions (np cells)
+size_t state_copy_bytes(int storage, int np) {
+    if (storage == FVLBM_STORE_I16_DEV) return (size_t)np * (Q * 2 + 1);   // nine int16 planes + exponent plane
+    return (size_t)Q * np * (storage == FVLBM_STORE_FP16_DEV ? 2 : 4);
+}
 int n_fbufs(int scheme) { return scheme == FVLBM_SCHEME_RK4 ? 3 : 2; }
 
 // RK4 coefficients of Eq. 17, read as f(k+1) = f(0) + beta_(k+1) dt RHS(f(k))
@@ -38,7 +42,7 @@ Layout layout(int n, int np, const fvlbm_params &p) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t b) { size_t o = off; off = align256(off + b); return o; };
-    size_t fb = (size_t)Q * np * storage_bytes(p.storage);
+    size_t fb = state_copy_bytes(p.storage, np);
     for (int k = 0; k < 3; k++) L.fbuf[k] = k < n_fbufs(p.scheme) ? take(fb) : 0;
     L.r32 = take((size_t)Q * np * sizeof(float));
     L.snap[0] = take((size_t)2 * n * sizeof(double));
@@ -347,7 +351,7 @@ void fvlbm_mesh_destroy(fvlbm_mesh *mesh) {
 }
 
 size_t fvlbm_state_bytes(const fvlbm_mesh *mesh, const fvlbm_params *p) {
-    if (!mesh || !p || p->scheme < 0 || p->scheme > 2 || p->storage < 0 || p->storage > 2) return 0;
+    if (!mesh || !p || p->scheme < 0 || p->scheme > 2 || p->storage < 0 || p->storage > 3) return 0;
     return layout(mesh->dev.n_cells, mesh->dev.np, *p).total;
 }
 
@@ -359,7 +363,7 @@ fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const doub
     const fvlbm_params &p = *params;
     if (!(p.tau > 0)) return fail(FVLBM_E_PARAM, "tau must be positive");
     if (p.scheme < 0 || p.scheme > 2) return fail(FVLBM_E_PARAM, "unknown scheme");
-    if (p.storage < 0 || p.storage > 2) return fail(FVLBM_E_PARAM, "unknown storage");
+    if (p.storage < 0 || p.storage > 3) return fail(FVLBM_E_PARAM, "unknown storage");
     if (!(p.rho0 > 0)) return fail(FVLBM_E_PARAM, "rho0 must be positive");
     if (((uintptr_t)device_buf & 255) != 0) return fail(FVLBM_E_ARG, "device buffer must be 256-byte aligned");
     const MeshDev &m = mesh->dev;
@@ -527,7 +531,7 @@ fvlbm_status fvlbm_rhs(fvlbm_solver *s, double *rhs) {
 size_t fvlbm_checkpoint_bytes(const fvlbm_solver *s) {
     if (!s) return 0;
     const MeshDev &m = s->mesh->dev;
-    size_t fb = (size_t)Q * m.np * storage_bytes(s->p.storage);
+    size_t fb = state_copy_bytes(s->p.storage, m.np);
     size_t extra = s->p.scheme == FVLBM_SCHEME_AB2 ? (size_t)Q * m.np * sizeof(float) : 0;
     return 64 + fb + extra;
 }
@@ -535,7 +539,7 @@ size_t fvlbm_checkpoint_bytes(const fvlbm_solver *s) {
 fvlbm_status fvlbm_checkpoint(fvlbm_solver *s, void *host_buf, size_t bytes) {
     if (!s || !host_buf || bytes < fvlbm_checkpoint_bytes(s)) return fail(FVLBM_E_ARG, "bad checkpoint buffer");
     const MeshDev &m = s->mesh->dev;
-    size_t fb = (size_t)Q * m.np * storage_bytes(s->p.storage);
+    size_t fb = state_copy_bytes(s->p.storage, m.np);
     int64_t hdr[8] = {0x46564c424d31LL, s->steps, s->p.storage, s->p.scheme, m.n_cells, s->have_prev, 0, 0};
     std::memcpy(host_buf, hdr, 64);
     hipError_t e = hipMemcpyAsync((char *)host_buf + 64, fptr(s, s->cur), fb, hipMemcpyDeviceToHost, s->stream);
@@ -553,7 +557,7 @@ fvlbm_status fvlbm_restore(fvlbm_solver *s, const void *host_buf, size_t bytes) 
     std::memcpy(hdr, host_buf, 64);
     if (hdr[0] != 0x46564c424d31LL || hdr[2] != s->p.storage || hdr[3] != s->p.scheme || hdr[4] != m.n_cells)
         return fail(FVLBM_E_ARG, "checkpoint does not match this solver");
-    size_t fb = (size_t)Q * m.np * storage_bytes(s->p.storage);
+    size_t fb = state_copy_bytes(s->p.storage, m.np);
     s->cur = 0;
     hipError_t e = hipMemcpyAsync(fptr(s, 0), (const char *)host_buf + 64, fb, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess && s->p.scheme == FVLBM_SCHEME_AB2)
@@ -784,7 +788,7 @@ struct Saved {
 fvlbm_status save_state(fvlbm_solver *s, Saved &sv) {
     const MeshDev &m = s->mesh->dev;
     sv.s = s;
-    sv.fb = (size_t)Q * m.np * storage_bytes(s->p.storage);
+    sv.fb = state_copy_bytes(s->p.storage, m.np);
     sv.rb = s->p.scheme == FVLBM_SCHEME_AB2 ? (size_t)Q * m.np * sizeof(float) : 0;
     if (hipMalloc(&sv.dev, sv.fb + sv.rb) != hipSuccess) return fail(FVLBM_E_NOMEM, "autotune state copy allocation failed");
     hipError_t e = hipMemcpyAsync(sv.dev, fptr(s, s->cur), sv.fb, hipMemcpyDeviceToDevice, s->stream);

@@ -19,20 +19,42 @@ constexpr int RB = 256;   // reduction block
 // the reference equilibrium f_eq(rho0, u_dev) as the step kernels see it (FP32)
 __device__ inline double wref(int a, const RefDev &r) { return (double)r.fref[a]; }
 
-// exact widening of a stored value to the FP64 deviation h = f - f_ref
-__device__ inline double load_dev(const void *p, int storage, size_t idx, int a, const RefDev &r) {
-    if (storage == FVLBM_STORE_FP32) return (double)static_cast<const float *>(p)[idx] - wref(a, r);
-    if (storage == FVLBM_STORE_FP32_DEV) return (double)static_cast<const float *>(p)[idx];
-    return (double)__half2float(static_cast<const __half *>(p)[idx]) * (double)(WF[a] * r.scale);
+// exact widening of cell i's stored values to the FP64 deviations h = f - f_ref
+__device__ inline void load_cell_dev(const void *p, int storage, int np, int i, const RefDev &r, double h[Q]) {
+    if (storage == FVLBM_STORE_I16_DEV) {             // h_a = q_a 2^(s - 142)
+        const int sb = static_cast<const uint8_t *>(p)[(size_t)np * 18 + i];
+        for (int a = 0; a < Q; a++)
+            h[a] = sb ? ldexp((double)static_cast<const int16_t *>(p)[(size_t)a * np + i], sb - 142) : 0.0;
+        return;
+    }
+    for (int a = 0; a < Q; a++) {
+        const size_t idx = (size_t)a * np + i;
+        if (storage == FVLBM_STORE_FP32) h[a] = (double)static_cast<const float *>(p)[idx] - wref(a, r);
+        else if (storage == FVLBM_STORE_FP32_DEV) h[a] = (double)static_cast<const float *>(p)[idx];
+        else h[a] = (double)__half2float(static_cast<const __half *>(p)[idx]) * (double)(WF[a] * r.scale);
+    }
 }
 
-__device__ inline void store_dev(void *p, int storage, size_t idx, int a, double h, const RefDev &r) {
-    if (storage == FVLBM_STORE_FP32) {
-        static_cast<float *>(p)[idx] = (float)(wref(a, r) + h);
-    } else if (storage == FVLBM_STORE_FP32_DEV) {
-        static_cast<float *>(p)[idx] = (float)h;
-    } else {
-        static_cast<__half *>(p)[idx] = __float2half_rn((float)(h / (double)(WF[a] * r.scale)));
+// round-to-nearest narrowing of FP64 deviations into cell i's storage
+__device__ inline void store_cell_dev(void *p, int storage, int np, int i, const double h[Q], const RefDev &r) {
+    if (storage == FVLBM_STORE_I16_DEV) {
+        double m = 0.0;
+        for (int a = 0; a < Q; a++) m = fmax(m, fabs(h[a]));
+        // 2^(s - 127) just above m (taken from m as a float; one bit of headroom if that rounds up)
+        const int sb = m > 0.0 ? min((int)((__float_as_uint((float)m) >> 23) & 0xffu) + 1, 254) : 0;
+        for (int a = 0; a < Q; a++) {
+            const double x = sb ? ldexp(h[a], 142 - sb) : 0.0;
+            const int q = max(-32767, min(32767, (int)rint(x)));
+            static_cast<int16_t *>(p)[(size_t)a * np + i] = (int16_t)q;
+        }
+        static_cast<uint8_t *>(p)[(size_t)np * 18 + i] = (uint8_t)sb;
+        return;
+    }
+    for (int a = 0; a < Q; a++) {
+        const size_t idx = (size_t)a * np + i;
+        if (storage == FVLBM_STORE_FP32) static_cast<float *>(p)[idx] = (float)(wref(a, r) + h[a]);
+        else if (storage == FVLBM_STORE_FP32_DEV) static_cast<float *>(p)[idx] = (float)h[a];
+        else static_cast<__half *>(p)[idx] = __float2half_rn((float)(h[a] / (double)(WF[a] * r.scale)));
     }
 }
 
@@ -45,11 +67,13 @@ __global__ void k_init_eq(void *dst, int storage, int n, int np, RefDev ref,
     double r = rho ? rho[c] : rho_u;
     double ux = u ? u[2 * c] : 0.0, uy = u ? u[2 * c + 1] : 0.0;
     double uu = ux * ux + uy * uy;
+    double h[Q];
     for (int a = 0; a < Q; a++) {
         double eu = EXd[a] * ux + EYd[a] * uy;
         double feq = WD[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        store_dev(dst, storage, (size_t)a * np + i, a, feq - wref(a, ref), ref);
+        h[a] = feq - wref(a, ref);
     }
+    store_cell_dev(dst, storage, np, i, h, ref);
 }
 
 __global__ void k_get_f(const void *src, int storage, int n, int np, RefDev ref,
@@ -57,8 +81,9 @@ __global__ void k_get_f(const void *src, int storage, int n, int np, RefDev ref,
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int c = perm[i];
-    for (int a = 0; a < Q; a++)
-        f[(size_t)c * Q + a] = wref(a, ref) + load_dev(src, storage, (size_t)a * np + i, a, ref);
+    double h[Q];
+    load_cell_dev(src, storage, np, i, ref, h);
+    for (int a = 0; a < Q; a++) f[(size_t)c * Q + a] = wref(a, ref) + h[a];
 }
 
 __global__ void k_set_f(void *dst, int storage, int n, int np, RefDev ref,
@@ -66,8 +91,9 @@ __global__ void k_set_f(void *dst, int storage, int n, int np, RefDev ref,
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int c = perm[i];
-    for (int a = 0; a < Q; a++)
-        store_dev(dst, storage, (size_t)a * np + i, a, f[(size_t)c * Q + a] - wref(a, ref), ref);
+    double h[Q];
+    for (int a = 0; a < Q; a++) h[a] = f[(size_t)c * Q + a] - wref(a, ref);
+    store_cell_dev(dst, storage, np, i, h, ref);
 }
 
 __global__ void k_rhs_out(const float *rhs, int n, int np, const int *perm, double *out) {
@@ -96,9 +122,10 @@ __global__ void k_macros(const void *src, int storage, int n, int np, RefDev ref
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     double mass = 0.0;
     if (i < n) {
-        double r = 0, mx = 0, my = 0;
+        double r = 0, mx = 0, my = 0, h[Q];
+        load_cell_dev(src, storage, np, i, ref, h);
         for (int a = 0; a < Q; a++) {
-            double f = wref(a, ref) + load_dev(src, storage, (size_t)a * np + i, a, ref);
+            double f = wref(a, ref) + h[a];
             r += f;
             mx += EXd[a] * f;
             my += EYd[a] * f;
@@ -119,9 +146,10 @@ __global__ void k_snapshot(const void *src, int storage, int n, int np, RefDev r
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     double num = 0, den = 0;
     if (i < n) {
-        double r = 0, mx = 0, my = 0;
+        double r = 0, mx = 0, my = 0, h[Q];
+        load_cell_dev(src, storage, np, i, ref, h);
         for (int a = 0; a < Q; a++) {
-            double f = wref(a, ref) + load_dev(src, storage, (size_t)a * np + i, a, ref);
+            double f = wref(a, ref) + h[a];
             r += f; mx += EXd[a] * f; my += EYd[a] * f;
         }
         double ux = mx / r, uy = my / r;

@@ -16,7 +16,8 @@
 //             four-stage scheme), or the AB2 combination.
 // Everything is computed on deviations h = f - f_eq(rho0, u_dev) in FP32,
 // so the constant part of f never enters a flux difference; storage is FP32
-// f, FP32 h, or FP16 h/(w S).
+// f, FP32 h, FP16 h/(w S), or 16-bit block-scaled h (int16 mantissas with a
+// per-cell power-of-two scale).
 //
 // Only directions 1..8 move (e_0 = 0), so a staged record holds h_1..h_8 and
 // their gradients; a cell's h_0 stays in its own thread's registers.
@@ -141,6 +142,69 @@ struct Storage<FVLBM_STORE_FP16_DEV> {
         sto<__half>(p, off, round_fp16((b + inc) * r.inv_unit[a], inc, key));
     }
 };
+
+// 16-bit block-scaled deviations: per cell nine int16 mantissas and one
+// exponent byte s, h_a = q_a 2^(s - 142), with 2^(s - 127) just above the
+// cell's largest |h_a|.  The largest deviation keeps 15 bits where FP16 keeps
+// 11.  Planes: nine int16 planes, then the exponent plane (np bytes).
+struct BlockI16 {
+    __device__ static float scale(const void *buf, size_t np, int c) {
+        const uint32_t sb = ldo<uint8_t>(static_cast<const char *>(buf) + np * 18, (uint32_t)c);
+        return __uint_as_float(sb << 23) * 0x1p-15f;                      // 0 when s = 0
+    }
+    __device__ static float load(const void *buf, size_t np, int c, int a, float sc) {
+        return (float)ldo<int16_t>(plane(buf, np * 2, a), (uint32_t)c * 2u) * sc;
+    }
+    // v[a] = b[a] + inc[a]; unbiased rounding of each mantissa (dither from the increment)
+    __device__ static void store(void *buf, size_t np, int c, const float b[Q], const float inc[Q], uint32_t key0) {
+        float v[Q], m = 0.f;
+#pragma unroll
+        for (int a = 0; a < Q; a++) {
+            v[a] = b[a] + inc[a];
+            m = fmaxf(m, fabsf(v[a]));
+        }
+        const uint32_t sb = m > 0.f ? min(((__float_as_uint(m) >> 23) & 0xffu) + 1u, 254u) : 0u;
+        const int sh = 142 - (int)sb;
+#pragma unroll
+        for (int a = 0; a < Q; a++) {
+            const float x = sb ? ldexpf(v[a], sh) : 0.f;                     // |x| < 2^15, exact scaling
+            const float fl = floorf(x);
+            const float u = (float)(mix(__float_as_uint(inc[a]) ^ (key0 + (uint32_t)a)) >> 8) * 0x1p-24f;
+            int q = (int)fl + (u < x - fl ? 1 : 0);
+            q = max(-32767, min(32767, q));
+            sto<int16_t>(plane(buf, np * 2, a), (uint32_t)c * 2u, (int16_t)q);
+        }
+        sto<uint8_t>(static_cast<char *>(buf) + np * 18, (uint32_t)c, (uint8_t)sb);
+    }
+};
+
+// Per-cell access for every storage mode.  load_cell fills f[a0..8] with the
+// deviations of cell c; store_cell writes b + inc.
+template <int STORE>
+__device__ inline void load_cell(const void *buf, size_t np, int c, float f[Q], const RefDev &r, int a0 = 0) {
+    if constexpr (STORE == FVLBM_STORE_I16_DEV) {
+        const float sc = BlockI16::scale(buf, np, c);
+#pragma unroll
+        for (int a = a0; a < Q; a++) f[a] = BlockI16::load(buf, np, c, a, sc);
+    } else {
+        using S = Storage<STORE>;
+        const uint32_t off = (uint32_t)c * S::SZ;
+#pragma unroll
+        for (int a = a0; a < Q; a++) f[a] = S::load(plane(buf, np * S::SZ, a), off, a, r);
+    }
+}
+template <int STORE>
+__device__ inline void store_cell(void *buf, size_t np, int c, const float b[Q], const float inc[Q], const RefDev &r,
+                                  uint32_t key0) {
+    if constexpr (STORE == FVLBM_STORE_I16_DEV) {
+        BlockI16::store(buf, np, c, b, inc, key0);
+    } else {
+        using S = Storage<STORE>;
+        const uint32_t off = (uint32_t)c * S::SZ;
+#pragma unroll
+        for (int a = 0; a < Q; a++) S::store(plane(buf, np * S::SZ, a), off, a, b[a], inc[a], r, key0 + (uint32_t)a);
+    }
+}
 
 // e_a . (x, y) for the D2Q9 velocities, folded per direction (no products by 0)
 __device__ __forceinline__ float edot(int a, float x, float y) {
@@ -495,27 +559,25 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
     if (bnd) boundary_flux<NF>(d, i, hi, gxi, gyi, mi, hei, packed, cf.inva, acc);
 
     // RHS = -sum (e.n dl/A) phi - (f - f_eq)/tau  (Eq. 10), then the update.
-    const uint32_t os = (uint32_t)i * Storage<STORE>::SZ, o4 = (uint32_t)i * 4u;
-    const size_t pb = (size_t)d.np * Storage<STORE>::SZ, pb4 = (size_t)d.np * 4;
-    const uint32_t key0 = (uint32_t)i * 9u;
+    const uint32_t o4 = (uint32_t)i * 4u;
+    const size_t pb4 = (size_t)d.np * 4;
+    float bv[Q], inc[Q];
 #pragma unroll
     for (int a = 0; a < Q; a++) {
         const float rhs = fmaf(hei[a] - hi[a], d.inv_tau, -acc[a]);
-        float b, inc;
         if (d.mode == 0) {
-            b = sep_base ? base[a] : hi[a];
-            inc = d.coef * rhs;
+            bv[a] = sep_base ? base[a] : hi[a];
+            inc[a] = d.coef * rhs;
         } else if (d.mode == 3) {
             sto<float>(plane(d.dst, pb4, a), o4, rhs);
-            continue;
         } else {
             const float prev = (d.mode == 1) ? rhs : ldo<float>(plane(d.rhs_prev, pb4, a), o4);
-            b = hi[a];
-            inc = (0.5f * d.coef) * (3.f * rhs - prev);
+            bv[a] = hi[a];
+            inc[a] = (0.5f * d.coef) * (3.f * rhs - prev);
             sto<float>(plane(d.rhs_prev, pb4, a), o4, rhs);
         }
-        Storage<STORE>::store(plane(d.dst, pb, a), os, a, b, inc, d.ref, key0 + (uint32_t)a);
     }
+    if (d.mode != 3) store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i * 9u);
 }
 
 // One RHS evaluation and update for one tile of T cells.
@@ -531,7 +593,6 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
 // region-B records for the largest ring-2 slot count (sized by the launcher).
 template <int NF, int STORE, int T>
 __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, int2 u, float4 *A, float4 *B) {
-    using S = Storage<STORE>;
     const InstDesc &d = descs[u.x];
     const int tile = u.y;
     const int tid = threadIdx.x;
@@ -540,7 +601,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     const int h1s = d.h1s, h2s = d.h2s;
     const int a_end = T + h1s;                     // local indices below this are region A
     const int *hidx = d.halo_idx + (size_t)tile * (size_t)(h1s + h2s);
-    const size_t pb = (size_t)d.np * S::SZ;
+    const size_t np = (size_t)d.np;
     const bool sep_base = d.mode == 0 && d.base != d.src;
 
     // ---- phase 1
@@ -560,9 +621,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     CellGeo<NF> geo;
     CellFaces<NF> cf;
     const int ic = valid ? i : 0;
-    const uint32_t os = (uint32_t)ic * S::SZ;
-#pragma unroll
-    for (int a = 0; a < Q; a++) f[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
+    load_cell<STORE>(d.src, np, ic, f, d.ref);
     const uint2 ln = ldo<uint2>(d.lnbr, (uint32_t)ic * 8u);
     geo.load(d, ic);
     cf.load(d, ic);
@@ -570,18 +629,11 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     float hf0 = 0.f, f1[Q], f2[Q];
     CellGeo<NF> hgeo;
     {
-        const uint32_t os1 = (uint32_t)(c1 >= 0 ? c1 : 0) * S::SZ;
-#pragma unroll
-        for (int a = 0; a < Q; a++) f1[a] = S::load(plane(d.src, pb, a), os1, a, d.ref);
+        load_cell<STORE>(d.src, np, c1 >= 0 ? c1 : 0, f1, d.ref);
         hgeo.load(d, c1 >= 0 ? c1 : 0);
-        const uint32_t os2 = (uint32_t)(c2 >= 0 ? c2 : 0) * S::SZ;
-#pragma unroll
-        for (int a = 1; a < Q; a++) f2[a] = S::load(plane(d.src, pb, a), os2, a, d.ref);
+        load_cell<STORE>(d.src, np, c2 >= 0 ? c2 : 0, f2, d.ref, 1);
     }
-    if (sep_base) {
-#pragma unroll
-        for (int a = 0; a < Q; a++) base[a] = S::load(plane(d.base, pb, a), os, a, d.ref);
-    }
+    if (sep_base) load_cell<STORE>(d.base, np, ic, base, d.ref);
     h0 = f[0];
 #pragma unroll
     for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
@@ -599,19 +651,15 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     for (int k = tid + T; k < h1s; k += T) {        // ring 1 larger than the tile
         const int c = ldg(hidx, k);
         if (c < 0) continue;
-        const uint32_t os = (uint32_t)c * S::SZ;
         float g[Q];
-#pragma unroll
-        for (int a = 1; a < Q; a++) g[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
+        load_cell<STORE>(d.src, np, c, g, d.ref, 1);
         wr_f(A + (T + k) * RA, g);
     }
     for (int k = tid + T; k < h2s; k += T) {        // ring 2 larger than the tile
         const int c = ldg(hidx, h1s + k);
         if (c < 0) continue;
-        const uint32_t os = (uint32_t)c * S::SZ;
         float g[Q];
-#pragma unroll
-        for (int a = 1; a < Q; a++) g[a] = S::load(plane(d.src, pb, a), os, a, d.ref);
+        load_cell<STORE>(d.src, np, c, g, d.ref, 1);
         wr_f(B + k * RB, g);
     }
     __syncthreads();
@@ -641,7 +689,11 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
             CellGeo<NF> g2;
             g2.load(d, c);
             g2.invert(cc);
-            hc[0] = S::load(d.src, (uint32_t)c * S::SZ, 0, d.ref);
+            {
+                float t[Q];
+                load_cell<STORE>(d.src, np, c, t, d.ref);
+                hc[0] = t[0];
+            }
             rd_f(A + (T + k) * RA, hc);
             gradient_staged<NF>(d, c, g2, hc, cc, hl2, A, B, a_end, gx, gy);
             wr_g(A + (T + k) * RA, gx, gy);
@@ -695,10 +747,12 @@ const void *pick(int nf, int storage, int T, bool persistent) {
     if (nf == 3) {
         if (storage == FVLBM_STORE_FP32) return pick_t<3, FVLBM_STORE_FP32>(T, persistent);
         if (storage == FVLBM_STORE_FP32_DEV) return pick_t<3, FVLBM_STORE_FP32_DEV>(T, persistent);
+        if (storage == FVLBM_STORE_I16_DEV) return pick_t<3, FVLBM_STORE_I16_DEV>(T, persistent);
         return pick_t<3, FVLBM_STORE_FP16_DEV>(T, persistent);
     }
     if (storage == FVLBM_STORE_FP32) return pick_t<4, FVLBM_STORE_FP32>(T, persistent);
     if (storage == FVLBM_STORE_FP32_DEV) return pick_t<4, FVLBM_STORE_FP32_DEV>(T, persistent);
+    if (storage == FVLBM_STORE_I16_DEV) return pick_t<4, FVLBM_STORE_I16_DEV>(T, persistent);
     return pick_t<4, FVLBM_STORE_FP16_DEV>(T, persistent);
 }
 

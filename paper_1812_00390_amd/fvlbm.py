@@ -17,10 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfvlbm.so")
 
 EULER, RK4, AB2 = 0, 1, 2
-FP32, FP32_DEV, FP16_DEV = 0, 1, 2
+FP32, FP32_DEV, FP16_DEV, I16_DEV = 0, 1, 2, 3
 REORDER_NONE, REORDER_RCM, REORDER_HILBERT, REORDER_BISECT = 0, 1, 2, 3
 SCHEMES = {"euler": EULER, "rk4": RK4, "ab2": AB2}
-STORAGES = {"fp32": FP32, "fp32dev": FP32_DEV, "fp16dev": FP16_DEV}
+STORAGES = {"fp32": FP32, "fp32dev": FP32_DEV, "fp16dev": FP16_DEV, "i16dev": I16_DEV}
 FLAG_FORCE_DT = 1
 
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_MESH", -3: "E_PARAM", -4: "E_NOMEM", -5: "E_DEVICE",

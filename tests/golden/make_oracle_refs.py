@@ -11,6 +11,8 @@ velocity at seeded sample cells after a fixed number of steps:
   oracle_cylinder256_rk4_100.npz  O-grid 256 x 384 quads around a cylinder,
                                   h0 = 0.005 D to 30 D, Re = 100, U = 0.1,
                                   four-stage RK, CFL 0.5, u_ref 0.2, 100 steps
+  oracle_cylinder256_rk4_20000.npz  the same cylinder after 20,000 steps (the
+                                  full start-up run; about 20 minutes)
 
 Run: python tests/golden/make_oracle_refs.py   (a few minutes, one core)
 """
@@ -31,6 +33,8 @@ CASES = {
                                           u0=(0.0, 0.0)),
     "oracle_cylinder256_rk4_100.npz": dict(mesh=lambda: mg.cylinder(nr=256, nt=384), tau=3 * 0.1 * 1.0 / 100,
                                            cfl=0.5, u_ref=0.2, steps=100, u0=(0.1, 0.0)),
+    "oracle_cylinder256_rk4_20000.npz": dict(mesh=lambda: mg.cylinder(nr=256, nt=384), tau=3 * 0.1 * 1.0 / 100,
+                                             cfl=0.5, u_ref=0.2, steps=20000, u0=(0.1, 0.0)),
 }
 
 
