@@ -17,6 +17,9 @@ Prints one JSON line.  Besides the contract fields:
                 batched, graph-replayed, autotuned path with FP16-deviation
                 storage, next to the same instances run one at a time on the
                 plain single-instance FP32 path
+  precision     each storage mode's velocity error against stored FP64 oracle runs
+  served        Poisson-arrival serving at 0.5 and 1.0 x the measured capacity:
+                p50/p99 latency and aggregate throughput
 """
 from __future__ import annotations
 
@@ -37,6 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # triangle, 72 B per quadrilateral).
 MESH_BYTES = {3: 60, 4: 72}
 STATE_VALUES = {"euler": 18, "rk4": 99}   # stored values moved per cell-update
+# bytes per stored value: the 16-bit block-scaled format adds one exponent byte per nine values
+STORE_BYTES = {"fp32": 4.0, "fp32dev": 4.0, "fp16dev": 2.0, "i16dev": 19.0 / 9.0}
 
 
 def alg_bytes_per_update(nf: int, scheme: str, sbytes: int) -> float:
@@ -100,19 +105,63 @@ def streaming(F, W, stream):
     m = W.streaming()
     mesh = F.Mesh(m, reorder=F.REORDER_BISECT)
     nf = mesh.info()["nf"]
-    for scheme, k in (("euler", 20), ("rk4", 5)):
-        s = F.Solver(mesh, F.make_params(tau=3e-5, scheme=scheme, storage="fp32dev"))
+    for scheme, storage, k in (("euler", "fp32dev", 20), ("rk4", "fp32dev", 5), ("rk4", "i16dev", 5)):
+        s = F.Solver(mesh, F.make_params(tau=3e-5, scheme=scheme, storage=storage))
         s.autotune(4)
         el = events_time(stream, lambda: s.step(k))
         n_launch = k * (4 if scheme == "rk4" else 1)
         t_launch = el / n_launch
-        alg = alg_bytes_per_update(nf, scheme, 4) / (4 if scheme == "rk4" else 1) * m.n_cells
-        out[scheme] = dict(cells=m.n_cells, steps=k, M_cell_updates_per_s=round(m.n_cells * k / el / 1e6, 1),
-                           launch_ms=round(t_launch * 1e3, 4), achieved_GBs=round(alg / t_launch / 1e9, 1),
-                           frac=round(alg / t_launch / 1e9 / HBM_PEAK_GBS, 4), schedule=s.get_schedule())
+        alg = alg_bytes_per_update(nf, scheme, STORE_BYTES[storage]) / (4 if scheme == "rk4" else 1) * m.n_cells
+        out[f"{scheme}_{storage}"] = dict(cells=m.n_cells, steps=k,
+                                          M_cell_updates_per_s=round(m.n_cells * k / el / 1e6, 1),
+                                          launch_ms=round(t_launch * 1e3, 4), achieved_GBs=round(alg / t_launch / 1e9, 1),
+                                          frac=round(alg / t_launch / 1e9 / HBM_PEAK_GBS, 4), schedule=s.get_schedule())
         s.close()
     mesh.close()
     return out
+
+
+def precision(F):
+    """Max |u - u_oracle| / U of each storage mode against the stored FP64 oracle runs
+    (written by tests/golden/make_oracle_refs.py from the oracle alone)."""
+    from paper_1812_00390_amd import meshgen as mg
+    gold = os.path.join(ROOT, "tests", "golden")
+    out = {}
+    runs = [("cavity 20k tri, RK4, 2000 steps", "oracle_cavity100_rk4_2000.npz",
+             lambda: mg.cavity(n=100, ratio=1.08, jitter=0.2, seed=0, lid_u=0.1), {}, None),
+            ("cylinder 98k quads, RK4, 100 steps", "oracle_cylinder256_rk4_100.npz",
+             lambda: mg.cylinder(nr=256, nt=384), dict(u_ref=0.2, u_dev=(0.1, 0.0)), (0.1, 0.0)),
+            ("cylinder 98k quads, RK4, 20000 steps", "oracle_cylinder256_rk4_20000.npz",
+             lambda: mg.cylinder(nr=256, nt=384), dict(u_ref=0.2, u_dev=(0.1, 0.0)), (0.1, 0.0))]
+    for label, fname, make, extra, u0 in runs:
+        path = os.path.join(gold, fname)
+        if not os.path.exists(path):
+            continue
+        ref = np.load(path)
+        m = make()
+        mesh = F.Mesh(m)
+        errs = {}
+        for storage in ("fp32", "fp32dev", "fp16dev", "i16dev"):
+            kw = dict(u=np.tile(np.asarray(u0, float), (m.n_cells, 1))) if u0 else {}
+            s = F.Solver(mesh, F.make_params(tau=float(ref["tau"]), dt=float(ref["dt"]), scheme="rk4",
+                                             storage=storage, **extra), **kw)
+            s.step(int(ref["steps"]))
+            _, u, _ = s.macros()
+            errs[storage] = float(f"{np.abs(u[ref['idx']] - ref['u']).max() / 0.1:.3g}")
+            s.close()
+        mesh.close()
+        out[label] = errs
+    return {"metric": "max |u - u_oracle| / U at sampled cells", "runs": out}
+
+
+def served(args):
+    """The served workload at a reduced size (its own module runs the full sweep)."""
+    import subprocess
+    cmd = [sys.executable, "-m", "paper_1812_00390_amd.serve", "--requests", "32", "--loads", "0.5,1.0"]
+    r = subprocess.run(cmd, capture_output=True, text=True, cwd=ROOT, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def batched(F, W, stream, steps=1000, single_steps=100):
@@ -146,7 +195,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="fp32dev")
-    ap.add_argument("--only", choices=["all", "headline", "streaming", "batched", "copy"], default="all")
+    ap.add_argument("--only", choices=["all", "headline", "streaming", "batched", "precision", "served", "copy"],
+                    default="all")
     ap.add_argument("--schedule", default="", help="force a launch schedule 'block,xcd,persistent' instead of tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -175,7 +225,7 @@ def main():
         s.step(args.warmup)
         el = events_time(stream, lambda: s.step(args.steps))
         n = inst.n_cells
-        sbytes = 2 if args.storage == "fp16dev" else 4
+        sbytes = STORE_BYTES[args.storage]
         t_launch = el / (4 * args.steps)
         alg_launch = alg_bytes_per_update(nf, "rk4", sbytes) / 4 * n
         rho, u, st = s.macros()
@@ -190,7 +240,7 @@ def main():
             "higher_is_better": True,
             "scaling": "weak",
             "vs_baseline": None,
-            "dtype": "f32" if args.storage != "fp16dev" else "f32 compute, fp16 storage",
+            "dtype": "f32" if args.storage in ("fp32", "fp32dev") else f"f32 compute, {args.storage} storage",
             "data": "synthetic",
             "config": {"workload": "lid-driven cavity Re=1000 U=0.1, 20000 jittered triangles "
                                    "(100x100 tanh growth 1.08, seed 0), four-stage RK, CFL 0.5",
@@ -217,6 +267,10 @@ def main():
         rec["streaming"] = streaming(F, W, stream)
     if args.only in ("all", "batched"):
         rec["batched"] = batched(F, W, stream)
+    if args.only in ("all", "precision"):
+        rec["precision"] = precision(F)
+    if args.only in ("all", "served"):
+        rec["served"] = served(args)
     print(json.dumps(rec))
 
 

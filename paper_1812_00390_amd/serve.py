@@ -68,7 +68,7 @@ class Result:
 class GpuBackend:
     """Device work through the C ABI (one stream shared by all members)."""
 
-    def __init__(self, scheme: str = "rk4", storage: str = "fp16dev", chunk: int = 1000, autotune: bool = True,
+    def __init__(self, scheme: str = "rk4", storage: str = "i16dev", chunk: int = 1000, autotune: bool = True,
                  schedule: Optional[dict] = None):
         from . import fvlbm as F
         self.F = F
@@ -90,10 +90,10 @@ class GpuBackend:
         n = inst.n_cells
         nf = 4 if np.diff(inst.mesh.cell_ptr).max() == 4 else 3
         np_ = (n + 511) // 512 * 512
-        sbytes = 2 if self.storage == "fp16dev" else 4
+        copy = {"fp16dev": 18, "i16dev": 19}.get(self.storage, 36) * np_
         nbuf = 3 if self.scheme == "rk4" else 2
         mesh = np_ * (nf * 16 + 16) + n * 12 + np_ * 8
-        state = nbuf * 9 * np_ * sbytes + 9 * np_ * 4 + 4 * n * 8 + 9 * n * 8
+        state = nbuf * copy + 9 * np_ * 4 + 4 * n * 8 + 9 * n * 8
         return int(mesh + state)
 
     def advance(self, handles: List, steps: int):
@@ -251,12 +251,13 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--hbm-budget-gb", type=float, default=2.0, help="artificial admission budget")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--storage", default="i16dev", choices=["fp32dev", "fp16dev", "i16dev"])
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     out = {"config": vars(args)}
     # capacity: a saturated batch of requests drawn like the stream
-    backend = GpuBackend(chunk=args.chunk)
+    backend = GpuBackend(chunk=args.chunk, storage=args.storage)
     calib = make_requests(args.slots // 2, 1e9, args.seed + 100, args.min_cells, args.max_cells, 0.0, 2 * args.chunk)
     srv = Server(backend, int(args.hbm_budget_gb * 2 ** 30), args.slots, args.chunk)
     srv.run(calib)
@@ -269,7 +270,8 @@ def main():
     for load in [float(x) for x in args.loads.split(",")]:
         reqs = make_requests(args.requests, load * capacity, args.seed, args.min_cells, args.max_cells,
                              args.tol, args.budget)
-        srv = Server(GpuBackend(chunk=args.chunk, schedule=backend.schedule), int(args.hbm_budget_gb * 2 ** 30),
+        srv = Server(GpuBackend(chunk=args.chunk, storage=args.storage, schedule=backend.schedule),
+                     int(args.hbm_budget_gb * 2 ** 30),
                      args.slots, args.chunk)
         res = srv.run(reqs)
         out[f"load_{load}"] = summarize(res, srv.wall, srv.cell_updates)

@@ -25,15 +25,15 @@ def test_served_equals_alone_bitwise(F):
     chunk = 64
     budgets = [128, 320, 192, 256, 128]
     reqs = [Request(k, inst, tol=0.0, budget=b, arrival=0.0) for k, (inst, b) in enumerate(zip(insts, budgets))]
-    srv = Server(GpuBackend(chunk=chunk, autotune=False), hbm_budget=2 ** 31, max_slots=3, chunk=chunk,
-                 keep_fields=True)
+    backend = GpuBackend(chunk=chunk, autotune=False)
+    srv = Server(backend, hbm_budget=2 ** 31, max_slots=3, chunk=chunk, keep_fields=True)
     res = {r.rid: r for r in srv.run(reqs)}
     assert sorted(res) == list(range(5))
     # membership changed while requests ran: more requests than slots
     assert srv.used == 0
     for k, inst in enumerate(insts):
         mesh = F.Mesh(inst.mesh, reorder=F.REORDER_BISECT)
-        p = F.make_params(tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme="rk4", storage="fp16dev",
+        p = F.make_params(tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme="rk4", storage=backend.storage,
                           u_dev=inst.u0, residual_lag=chunk)
         s = F.Solver(mesh, p, u=np.tile(np.asarray(inst.u0, float), (inst.n_cells, 1)))
         for _ in range(budgets[k] // chunk):
