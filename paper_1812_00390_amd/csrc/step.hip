@@ -84,28 +84,27 @@ __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // (cell, direction): results do not depend on launch order, schedule,
 // batching or graphs.
 
-// A hash with avalanche in every input bit (full-rate 24-bit multiplies and
-// shifts): a small change of the input changes the output unpredictably.
-__device__ inline uint32_t mix(uint32_t x) {
-    x = __umul24(x ^ (x >> 15), 0x9e3779u);
-    x = __umul24(x ^ (x >> 13), 0x85ebcau);
-    return x ^ (x >> 16);
-}
+// Dither bits: the top of a 24-bit product (full-rate multiply) of the input
+// folded on itself, with one odd multiplier per direction.  The input is the
+// increment's bits, which change from step to step; the key is the cell.
+__device__ constexpr uint32_t MIXK[Q] = {0x9e3779u, 0x85ebcbu, 0xc2b2afu, 0x27d4ebu, 0x165667u,
+                                         0xd3a265u, 0xfd7047u, 0x6c8e95u, 0x4cf5adu};
+__device__ inline uint32_t mix(uint32_t x, int a) { return __umul24(x ^ (x >> 13), MIXK[a]); }
 
 // b + p rounded to FP32 with a centred dither of one ulp of b.  The dither is
 // drawn from the increment's bits, never from the bits being rounded away.
-__device__ inline float add_sr(float b, float p, uint32_t key) {
+__device__ inline float add_sr(float b, float p, uint32_t key, int a) {
     const float g = __uint_as_float(__float_as_uint(b) & 0x7f800000u) * 0x1p-47f;   // ulp(b) / 2^24; 0 for b = 0
-    const int32_t r = (int32_t)mix(__float_as_uint(p) ^ key) >> 8;                 // uniform in [-2^23, 2^23)
+    const int32_t r = (int32_t)mix(__float_as_uint(p) ^ key, a) >> 8;              // uniform in [-2^23, 2^23)
     return b + fmaf((float)r, g, p);
 }
 
 // unbiased rounding of v = (b + p) / unit to FP16: 13 random bits (from the
 // increment p) are added below the FP16 mantissa, then truncated (exact for
 // FP16 normals)
-__device__ inline __half round_fp16(float v, float p, uint32_t key) {
+__device__ inline __half round_fp16(float v, float p, uint32_t key, int a) {
     const uint32_t b = __float_as_uint(v);
-    const uint32_t mag = (b & 0x7fffffffu) + (mix(__float_as_uint(p) ^ key) >> 19);
+    const uint32_t mag = (b & 0x7fffffffu) + (mix(__float_as_uint(p) ^ key, a) >> 19);
     return __float2half_rz(__uint_as_float((b & 0x80000000u) | mag));
 }
 
@@ -121,15 +120,15 @@ struct Storage<FVLBM_STORE_FP32> {
         return ldo<float>(p, off) - r.fref[a];
     }
     __device__ static void store(void *p, uint32_t off, int a, float b, float inc, const RefDev &r, uint32_t key) {
-        sto<float>(p, off, add_sr(b + r.fref[a], inc, key));   // b + fref is the stored f (b came from it by Sterbenz)
+        sto<float>(p, off, add_sr(b + r.fref[a], inc, key, a));   // b + fref is the stored f (b came from it by Sterbenz)
     }
 };
 template <>
 struct Storage<FVLBM_STORE_FP32_DEV> {
     static constexpr uint32_t SZ = 4;
     __device__ static float load(const void *p, uint32_t off, int, const RefDev &) { return ldo<float>(p, off); }
-    __device__ static void store(void *p, uint32_t off, int, float b, float inc, const RefDev &, uint32_t key) {
-        sto<float>(p, off, add_sr(b, inc, key));
+    __device__ static void store(void *p, uint32_t off, int a, float b, float inc, const RefDev &, uint32_t key) {
+        sto<float>(p, off, add_sr(b, inc, key, a));
     }
 };
 template <>
@@ -139,7 +138,7 @@ struct Storage<FVLBM_STORE_FP16_DEV> {
         return __half2float(ldo<__half>(p, off)) * (WT[a] * r.scale);
     }
     __device__ static void store(void *p, uint32_t off, int a, float b, float inc, const RefDev &r, uint32_t key) {
-        sto<__half>(p, off, round_fp16((b + inc) * r.inv_unit[a], inc, key));
+        sto<__half>(p, off, round_fp16((b + inc) * r.inv_unit[a], inc, key, a));
     }
 };
 
@@ -169,7 +168,7 @@ struct BlockI16 {
         for (int a = 0; a < Q; a++) {
             const float x = sb ? ldexpf(v[a], sh) : 0.f;                     // |x| < 2^15, exact scaling
             const float fl = floorf(x);
-            const float u = (float)(mix(__float_as_uint(inc[a]) ^ (key0 + (uint32_t)a)) >> 8) * 0x1p-24f;
+            const float u = (float)(mix(__float_as_uint(inc[a]) ^ key0, a) >> 8) * 0x1p-24f;
             int q = (int)fl + (u < x - fl ? 1 : 0);
             q = max(-32767, min(32767, q));
             sto<int16_t>(plane(buf, np * 2, a), (uint32_t)c * 2u, (int16_t)q);
@@ -202,7 +201,7 @@ __device__ inline void store_cell(void *buf, size_t np, int c, const float b[Q],
         using S = Storage<STORE>;
         const uint32_t off = (uint32_t)c * S::SZ;
 #pragma unroll
-        for (int a = 0; a < Q; a++) S::store(plane(buf, np * S::SZ, a), off, a, b[a], inc[a], r, key0 + (uint32_t)a);
+        for (int a = 0; a < Q; a++) S::store(plane(buf, np * S::SZ, a), off, a, b[a], inc[a], r, key0);
     }
 }
 
@@ -577,7 +576,7 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
             sto<float>(plane(d.rhs_prev, pb4, a), o4, rhs);
         }
     }
-    if (d.mode != 3) store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i * 9u);
+    if (d.mode != 3) store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i);
 }
 
 // One RHS evaluation and update for one tile of T cells.
