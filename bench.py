@@ -100,14 +100,18 @@ def make_solver(F, inst, scheme, storage, reorder=None):
     return mesh, s
 
 
-def streaming(F, W, stream):
+def streaming(F, W, stream, schedule=None):
     out = {}
     m = W.streaming()
     mesh = F.Mesh(m, reorder=F.REORDER_BISECT)
     nf = mesh.info()["nf"]
     for scheme, storage, k in (("euler", "fp32dev", 20), ("rk4", "fp32dev", 5), ("rk4", "i16dev", 5)):
         s = F.Solver(mesh, F.make_params(tau=3e-5, scheme=scheme, storage=storage))
-        s.autotune(4)
+        if schedule:
+            s.set_schedule(*schedule)
+            s.step(2)
+        else:
+            s.autotune(4)
         el = events_time(stream, lambda: s.step(k))
         n_launch = k * (4 if scheme == "rk4" else 1)
         t_launch = el / n_launch
@@ -212,14 +216,17 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    schedule = None
+    if args.schedule:
+        b, x, p = (int(v) for v in args.schedule.split(","))
+        schedule = (b, bool(x), bool(p))
     rec = {}
     if args.only in ("all", "headline"):
         inst = W.cavity20k()
         mesh, s = make_solver(F, inst, "rk4", args.storage)
         nf = mesh.info()["nf"]
         if args.schedule:
-            b, x, p = (int(v) for v in args.schedule.split(","))
-            s.set_schedule(b, bool(x), bool(p))
+            s.set_schedule(*schedule)
         elif not args.no_autotune:
             s.autotune(64)
         s.step(args.warmup)
@@ -264,7 +271,7 @@ def main():
         el = events_time(stream, lambda: [dst.copy_(src) for _ in range(5)])
         rec["copy"] = dict(bytes_each_way=4 * n, launches=5, GBs=round(2 * 4 * n * 5 / el / 1e9, 1))
     if args.only in ("all", "streaming"):
-        rec["streaming"] = streaming(F, W, stream)
+        rec["streaming"] = streaming(F, W, stream, schedule)
     if args.only in ("all", "batched"):
         rec["batched"] = batched(F, W, stream)
     if args.only in ("all", "precision"):
