@@ -162,6 +162,20 @@ fvlbm_status fvlbm_restore(fvlbm_solver *s, const void *host_buf, size_t bytes);
 void fvlbm_solver_destroy(fvlbm_solver *s);
 void fvlbm_mesh_destroy(fvlbm_mesh *mesh);
 
+/* Force on a wall group (post-processing for the force coefficients of Sections 3.3-3.4, whose
+ * formula the paper takes from elsewhere; here the discrete momentum flux through the wall faces):
+ *   F = sum over the group's faces of sum_a e_a (e_a . n dl) f_P,a,
+ * with n dl the outward normal of the fluid cell times the face length and f_P the wall value of
+ * Eq. 18, which is the face value of every direction at a wall (Eq. 11).  This is the force the
+ * fluid exerts on the wall (pressure rho/3 plus the non-equilibrium stress), per unit depth.
+ * FP64 from the stored state; syncs the stream.
+ *   force[2]  (may be NULL) receives (Fx, Fy)
+ *   n_faces   (may be NULL) receives the number of the group's faces
+ *   face_p    (may be NULL) receives p = rho/3 of each face's border cell, n_faces values, in the
+ *             order the faces appear in the bface arrays given to fvlbm_create_mesh
+ * Errors: FVLBM_E_ARG (null solver, group out of range or not a wall), FVLBM_E_DEVICE. */
+fvlbm_status fvlbm_wall_force(fvlbm_solver *s, int32_t group, double force[2], int32_t *n_faces, double *face_p);
+
 /*
  * Batched solves: several solvers (each with its own mesh, parameters and
  * state) advanced by shared launches, one work unit per (solver, cell tile).

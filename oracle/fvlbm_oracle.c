@@ -76,6 +76,9 @@ typedef struct {
     double tau, dt;
     int scheme;
     double *f, *tmp0, *tmp1, *rhs_prev;
+    int n_bf;                /* boundary faces as given, and the (cell * MAXF + slot) each lies on */
+    int *bf_slot;
+    int *bf_group;
     int have_prev;
     long steps;
 } oracle_t;
@@ -270,7 +273,10 @@ oracle_t *orc_create(int n_nodes, const double *xy, int n_cells, const int *cell
         o->grp[sa] = -1; o->grp[sb] = -1;
     }
     free(edges);
-    free(bf_slot);
+    o->n_bf = n_bf;
+    o->bf_slot = bf_slot;
+    o->bf_group = (int *)malloc((n_bf > 0 ? n_bf : 1) * sizeof(int));
+    for (int b = 0; b < n_bf; b++) o->bf_group[b] = bface_group[b];
     for (int c = 0; c < N; c++)
         for (int k = 0; k < o->nf[c]; k++) {
             int s = c * MAXF + k;
@@ -329,6 +335,7 @@ void orc_destroy(oracle_t *o) {
     free(o->area); free(o->cx); free(o->cy); free(o->lx); free(o->ly);
     free(o->m11); free(o->m12); free(o->m22);
     free(o->groups); free(o->f); free(o->tmp0); free(o->tmp1); free(o->rhs_prev);
+    free(o->bf_slot); free(o->bf_group);
     free(o);
 }
 
@@ -494,6 +501,40 @@ void orc_face_values(const oracle_t *o, const double *f, double *face_out) {
 }
 
 /* Step 0: f = f_eq(rho0, u0); rho/u may be NULL for uniform values. */
+/* Force on wall group g: the momentum flux through the group's faces, with the
+ * scheme's face values (at a wall, f_P of Eq. 18 for every direction):
+ *   F = sum over the group's faces of sum_a e_a (e_a . n) dl phi_a,
+ * n the outward unit normal of the fluid cell.  Also p = rho/3 of each face's
+ * border cell, faces in the order of the boundary-face arrays.  Returns the
+ * number of faces. */
+int orc_wall_force(const oracle_t *o, const double *f, int g, double *force, double *face_p) {
+    double *face = (double *)malloc((size_t)o->n_cells * MAXF * Q * sizeof(double));
+    double *rhs = (double *)malloc((size_t)o->n_cells * Q * sizeof(double));
+    operator_rhs(o, f, rhs, face);
+    double fx = 0.0, fy = 0.0;
+    int n = 0;
+    for (int b = 0; b < o->n_bf; b++) {
+        if (o->bf_group[b] != g) continue;
+        const int s = o->bf_slot[b], c = s / MAXF;
+        for (int a = 0; a < Q; a++) {
+            const double en = (EX[a] * o->nx[s] + EY[a] * o->ny[s]) * o->len[s];
+            fx += EX[a] * en * face[(size_t)s * Q + a];
+            fy += EY[a] * en * face[(size_t)s * Q + a];
+        }
+        if (face_p) {
+            double rho = 0.0;
+            for (int a = 0; a < Q; a++) rho += f[(size_t)c * Q + a];
+            face_p[n] = rho / 3.0;
+        }
+        n++;
+    }
+    force[0] = fx;
+    force[1] = fy;
+    free(face);
+    free(rhs);
+    return n;
+}
+
 void orc_init(oracle_t *o, const double *rho, const double *u, double rho0, double ux0, double uy0) {
     for (int c = 0; c < o->n_cells; c++)
         orc_feq(rho ? rho[c] : rho0, u ? u[2 * c] : ux0, u ? u[2 * c + 1] : uy0, &o->f[c * Q]);

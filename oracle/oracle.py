@@ -57,6 +57,7 @@ def lib():
         L.orc_lsq_gradient.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_rhs.argtypes = [C.c_void_p, dp, dp]
         L.orc_face_values.argtypes = [C.c_void_p, dp, dp]
+        L.orc_wall_force.argtypes = [C.c_void_p, dp, C.c_int, dp, dp]; L.orc_wall_force.restype = C.c_int
         L.orc_init.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double]
         L.orc_set_f.argtypes = [C.c_void_p, dp]
         L.orc_get_f.argtypes = [C.c_void_p, dp]
@@ -168,6 +169,15 @@ class Oracle:
         out = np.zeros((self.n, MAXF, Q))
         lib().orc_face_values(self.h, np.ascontiguousarray(f, dtype=np.float64).reshape(self.n, Q), out)
         return out
+
+    def wall_force(self, f, group: int):
+        """Momentum flux through the faces of wall group `group` with the scheme's face values
+        (f_P of Eq. 18 at a wall): (Fx, Fy), and p = rho/3 of each face's border cell."""
+        fr = np.ascontiguousarray(f, dtype=np.float64).reshape(self.n, Q)
+        force = np.zeros(2)
+        face_p = np.zeros(max(1, 4 * self.n))
+        k = lib().orc_wall_force(self.h, fr, int(group), force, face_p)
+        return force, face_p[:k].copy()
 
     def step(self, n: int = 1):
         lib().orc_step(self.h, int(n))

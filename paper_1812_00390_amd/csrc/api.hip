@@ -47,7 +47,7 @@ Layout layout(int n, int np, const fvlbm_params &p) {
     L.r32 = take((size_t)Q * np * sizeof(float));
     L.snap[0] = take((size_t)2 * n * sizeof(double));
     L.snap[1] = take((size_t)2 * n * sizeof(double));
-    L.partial = take((size_t)2 * reduce_blocks(n) * sizeof(double));
+    L.partial = take((size_t)2 * reduce_blocks(n * MAX_NF) * sizeof(double));   // also wall-face sums
     L.scal = take(8 * sizeof(double));
     L.flag = take(sizeof(int) * 4);
     L.out = take((size_t)Q * n * sizeof(double));   // FP64 staging for copy-out (rho,u or f or rhs)
@@ -484,6 +484,33 @@ fvlbm_status fvlbm_macros(fvlbm_solver *s, double *rho, double *u, double *stats
         stats[3] = (double)s->steps;
     }
     if (fl) return fail(FVLBM_E_DIVERGED, "non-finite density or velocity");
+    return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_wall_force(fvlbm_solver *s, int32_t group, double force[2], int32_t *n_faces, double *face_p) {
+    if (!s) return fail(FVLBM_E_ARG, "null solver");
+    const MeshDev &m = s->mesh->dev;
+    if (group < 0 || group >= m.n_groups) return fail(FVLBM_E_ARG, "group out of range");
+    if (m.groups_host[group].kind != FVLBM_BC_WALL) return fail(FVLBM_E_ARG, "the force is defined on wall groups");
+    const int n = m.gface_off[group + 1] - m.gface_off[group];
+    if (n_faces) *n_faces = n;
+    if (!force && !face_p) return FVLBM_OK;
+    double *partial = reinterpret_cast<double *>(s->buf + s->L.partial);
+    double *scal = reinterpret_cast<double *>(s->buf + s->L.scal);
+    double *out = reinterpret_cast<double *>(s->buf + s->L.out);
+    double fr[2] = {0, 0};
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        e = launch_wall_force(fptr(s, s->cur), s->p.storage, m.np, s->ref, m.gfaces_dev + m.gface_off[group], n, m.vxy,
+                              m.nf, m.groups_host[group].u[0], m.groups_host[group].u[1], partial, face_p ? out : nullptr,
+                              s->stream);
+        if (e == hipSuccess) e = launch_finish_sums(partial, reduce_blocks(n), scal + 2, 2, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(fr, scal + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess && face_p) e = hipMemcpyAsync(face_p, out, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    }
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("wall force failed: ") + hipGetErrorString(e));
+    if (force) { force[0] = fr[0]; force[1] = fr[1]; }
     return FVLBM_OK;
 }
 

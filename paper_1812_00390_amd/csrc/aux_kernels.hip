@@ -163,7 +163,43 @@ __global__ void k_snapshot(const void *src, int storage, int n, int np, RefDev r
     block_sum2(num, den, partial);
 }
 
-// mode 0: out[0] = sum col0 (mass); mode 1: out[1] = sqrt(sum col0)/sqrt(sum col1) (residual)
+// Momentum flux through wall faces (FP64 from the stored state): per face k of
+// border cell c, F = sum_a e_a (e_a . n dl) f_P,a with f_P = f_eq(rho_c, u_w) +
+// f_c - f_eq(rho_c, u_c) (Eq. 18) and n dl the outward normal times the face
+// length, from the cell's corner offsets.  Also p = rho_c / 3 per face.
+__global__ void k_wall_force(const void *src, int storage, int np, RefDev ref, const int2 *faces, int n,
+                             const float2 *vxy, int nf, double uwx, double uwy, double *partial, double *face_p) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    double fx = 0.0, fy = 0.0;
+    if (j < n) {
+        const int c = faces[j].x, k = faces[j].y;
+        double h[Q], f[Q];
+        load_cell_dev(src, storage, np, c, ref, h);
+        double r = 0, mx = 0, my = 0;
+        for (int a = 0; a < Q; a++) {
+            f[a] = wref(a, ref) + h[a];
+            r += f[a]; mx += EXd[a] * f[a]; my += EYd[a] * f[a];
+        }
+        const double ux = mx / r, uy = my / r;
+        const float2 v0 = vxy[(size_t)k * np + c], v1 = vxy[(size_t)(k + 1 == nf ? 0 : k + 1) * np + c];
+        // a triangle stored in a quad-slot mesh repeats corner 0 as its fourth corner
+        const double nx = (double)v1.y - (double)v0.y, ny = -((double)v1.x - (double)v0.x);
+        for (int a = 0; a < Q; a++) {
+            const double ec = EXd[a] * ux + EYd[a] * uy, ew = EXd[a] * uwx + EYd[a] * uwy;
+            const double feq_c = WD[a] * r * (1.0 + 3.0 * ec + 4.5 * ec * ec - 1.5 * (ux * ux + uy * uy));
+            const double feq_w = WD[a] * r * (1.0 + 3.0 * ew + 4.5 * ew * ew - 1.5 * (uwx * uwx + uwy * uwy));
+            const double fp = feq_w + f[a] - feq_c;
+            const double en = EXd[a] * nx + EYd[a] * ny;
+            fx += EXd[a] * en * fp;
+            fy += EYd[a] * en * fp;
+        }
+        if (face_p) face_p[j] = r / 3.0;
+    }
+    block_sum2(fx, fy, partial);
+}
+
+// mode 0: out[0] = sum col0 (mass); mode 1: out[1] = sqrt(sum col0)/sqrt(sum col1) (residual);
+// mode 2: out[0], out[1] = sum col0, sum col1
 __global__ void k_finish(const double *partial, int nblk, double *out, int mode) {
     __shared__ double sa[RB], sb[RB];
     double a = 0, b = 0;
@@ -176,7 +212,8 @@ __global__ void k_finish(const double *partial, int nblk, double *out, int mode)
     }
     if (threadIdx.x == 0) {
         if (mode == 0) out[0] = sa[0];
-        else out[1] = sqrt(sa[0]) / sqrt(sb[0]);
+        else if (mode == 1) out[1] = sqrt(sa[0]) / sqrt(sb[0]);
+        else { out[0] = sa[0]; out[1] = sb[0]; }
     }
 }
 
@@ -239,6 +276,14 @@ hipError_t launch_macros(const void *src, int storage, int n, int np, const RefD
                          const double *area, const int *perm_dev, double *rho_out, double *u_out,
                          double *partial, int *flag, hipStream_t stream) {
     hipLaunchKernelGGL(k_macros, grid(n), dim3(RB), 0, stream, src, storage, n, np, ref, area, perm_dev, rho_out, u_out, partial, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_force(const void *src, int storage, int np, const RefDev &ref, const int2 *faces, int n,
+                             const float2 *vxy, int nf, double uwx, double uwy, double *partial, double *face_p,
+                             hipStream_t stream) {
+    hipLaunchKernelGGL(k_wall_force, grid(n), dim3(RB), 0, stream, src, storage, np, ref, faces, n, vxy, nf, uwx, uwy,
+                       partial, face_p);
     return hipGetLastError();
 }
 

@@ -32,6 +32,8 @@ struct HostTopology {
     std::vector<int> back;             // [n][nf] slot of the same face in the neighbour (or -1)
     std::vector<double> shift;         // [n][nf][2] added to the neighbour centre (periodic image)
     int n_boundary_cells = 0;
+    // the caller's boundary faces, in the caller's order: cell (new order), slot, group (-1 periodic)
+    std::vector<int> bface_cell, bface_slot, bface_group;
 };
 
 // Builds topology from the raw mesh, validates it and reorders cells.
@@ -91,6 +93,9 @@ struct MeshDev {
     int n_boundary_cells = 0;
     std::vector<int> perm;       // perm[new] = input index
     int *perm_dev = nullptr;     // same, on the device
+    // boundary faces grouped by boundary group (caller's order within a group): (cell, slot)
+    int2 *gfaces_dev = nullptr;
+    int gface_off[MAX_GROUPS + 1] = {0};
     size_t bytes = 0;
     void *block = nullptr;       // one allocation holding everything above
 };
@@ -194,6 +199,11 @@ hipError_t launch_snapshot(const void *src, int storage, int n, int np, const Re
                            hipStream_t stream);
 // partial: [nblk][2] -> out[0] = sum col0, out[1] = sum col1 (fixed order)
 hipError_t launch_finish_sums(const double *partial, int nblk, double *out, int mode, hipStream_t stream);
+// Momentum flux through n wall faces (cell, slot) with wall velocity (uwx, uwy): partial sums of
+// (Fx, Fy) per block, and p = rho/3 of each face's border cell.
+hipError_t launch_wall_force(const void *src, int storage, int np, const RefDev &ref, const int2 *faces, int n,
+                             const float2 *vxy, int nf, double uwx, double uwy, double *partial, double *face_p,
+                             hipStream_t stream);
 int reduce_blocks(int n);
 
 }  // namespace fvlbm

@@ -134,6 +134,15 @@ fvlbm_status build_device_mesh(const HostTopology &topo, const fvlbm_bc *groups,
     size_t o_minv = take((size_t)3 * np * sizeof(float));
     size_t o_area = take((size_t)n * sizeof(double));
     size_t o_perm = take((size_t)n * sizeof(int));
+    // boundary faces by group, the caller's order within each group
+    std::vector<int2> gfaces;
+    for (int g = 0; g < n_groups; g++) {
+        mesh.gface_off[g] = (int)gfaces.size();
+        for (size_t b = 0; b < topo.bface_group.size(); b++)
+            if (topo.bface_group[b] == g) gfaces.push_back(make_int2(topo.bface_cell[b], topo.bface_slot[b]));
+    }
+    for (int g = n_groups; g <= MAX_GROUPS; g++) mesh.gface_off[g] = (int)gfaces.size();
+    size_t o_gf = take(std::max<size_t>(1, gfaces.size()) * sizeof(int2));
     size_t total = off;
     char *blk = nullptr;
     if (hipMalloc(&blk, total) != hipSuccess) { err = "device allocation of mesh arrays failed"; return FVLBM_E_NOMEM; }
@@ -145,6 +154,7 @@ fvlbm_status build_device_mesh(const HostTopology &topo, const fvlbm_bc *groups,
     mesh.nbr_host = topo.nbr;
     mesh.area = (double *)(blk + o_area);
     mesh.perm_dev = (int *)(blk + o_perm);
+    mesh.gfaces_dev = (int2 *)(blk + o_gf);
 
     // scratch for the FP64 pass
     size_t soff = 0;
@@ -170,6 +180,8 @@ fvlbm_status build_device_mesh(const HostTopology &topo, const fvlbm_bc *groups,
     chk(hipMemcpyAsync(scr + s_gk, gk, sizeof(gk), hipMemcpyHostToDevice, stream));
     chk(hipMemsetAsync(scr + s_bad, 0, sizeof(int), stream));
     chk(hipMemcpyAsync(mesh.perm_dev, topo.perm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, stream));
+    if (!gfaces.empty())
+        chk(hipMemcpyAsync(mesh.gfaces_dev, gfaces.data(), gfaces.size() * sizeof(int2), hipMemcpyHostToDevice, stream));
     // zero the padded tails of every plane so stray reads see finite values
     chk(hipMemsetAsync(blk, 0, o_area, stream));
     int nb = (n + 255) / 256;

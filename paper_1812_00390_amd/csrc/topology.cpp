@@ -332,6 +332,13 @@ fvlbm_status build_topology(int32_t n_nodes, const double *xy, int32_t n_cells,
         }
         topo.n_boundary_cells += bnd;
     }
+    topo.bface_cell.assign(n_bfaces, -1);
+    topo.bface_slot.assign(n_bfaces, -1);
+    topo.bface_group.assign(bface_group, bface_group + n_bfaces);
+    for (int b = 0; b < n_bfaces; b++) {
+        topo.bface_cell[b] = topo.iperm[bslot[b] / MAXS];
+        topo.bface_slot[b] = bslot[b] % MAXS;
+    }
     return FVLBM_OK;
 }
 

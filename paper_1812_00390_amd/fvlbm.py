@@ -63,6 +63,7 @@ SIGNATURES = {
     "fvlbm_get_f": (C.c_int, [_vp, _dp]),
     "fvlbm_set_f": (C.c_int, [_vp, _dp]),
     "fvlbm_rhs": (C.c_int, [_vp, _dp]),
+    "fvlbm_wall_force": (C.c_int, [_vp, C.c_int32, _dp, C.POINTER(C.c_int32), _dp]),
     "fvlbm_checkpoint_bytes": (C.c_size_t, [_vp]),
     "fvlbm_checkpoint": (C.c_int, [_vp, _vp, C.c_size_t]),
     "fvlbm_restore": (C.c_int, [_vp, _vp, C.c_size_t]),
@@ -251,6 +252,16 @@ class Solver:
         out = np.zeros((self.n, 9))
         _check(lib().fvlbm_rhs(self.h, _dptr(out)))
         return out
+
+    def wall_force(self, group: int):
+        """Force the fluid exerts on wall group `group` (Fx, Fy) and p = rho/3 at each of its faces
+        (the order of the mesh's boundary-face arrays)."""
+        n = C.c_int32(0)
+        _check(lib().fvlbm_wall_force(self.h, int(group), None, C.byref(n), None))
+        force = np.zeros(2)
+        face_p = np.zeros(max(1, n.value))
+        _check(lib().fvlbm_wall_force(self.h, int(group), _dptr(force), C.byref(n), _dptr(face_p)))
+        return force, face_p[:n.value]
 
     def checkpoint(self) -> bytes:
         nb = int(lib().fvlbm_checkpoint_bytes(self.h))

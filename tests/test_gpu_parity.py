@@ -380,3 +380,26 @@ def test_streaming_size_mesh_invariants(F):
     rho, u, st = s.macros()
     assert np.abs(u).max() < 1e-7
     assert abs(st["mass"] - st0["mass"]) / st0["mass"] < 1e-7
+
+
+@pytest.mark.parametrize("storage", ["fp32dev", "i16dev"])
+def test_wall_force_matches_oracle(F, O, storage):
+    # the force on the cylinder (group 0) and on the cavity walls, from the GPU's
+    # state, against the oracle's momentum flux evaluated at the same state
+    cases = [(mg.cylinder(nr=24, nt=36, R=8.0, h0=0.02), 3e-3, 0.2, (0.1, 0.0), [0], 200),
+             (mg.cavity(n=20, jitter=0.2, seed=9, lid_u=0.1), 3e-4, 0.1, (0.0, 0.0), [0, 1], 300)]
+    for m, tau, u_ref, u0, groups, steps in cases:
+        o = O.Oracle(m, tau=tau, cfl=0.5, u_ref=u_ref)
+        mesh = F.Mesh(m)
+        s = F.Solver(mesh, F.make_params(tau=tau, dt=o.dt, scheme="rk4", storage=storage, u_ref=u_ref, u_dev=u0),
+                     u=np.tile(np.asarray(u0, float), (m.n_cells, 1)))
+        s.step(steps)
+        f = s.f
+        for g in groups:
+            fg, pg = s.wall_force(g)
+            fo, po = o.wall_force(f, g)
+            assert len(pg) == len(po) > 0
+            assert np.abs(pg - po).max() <= 1e-12
+            assert np.abs(fg - fo).max() <= 1e-7 + 1e-6 * np.abs(fo).max(), (g, fg, fo)
+    with pytest.raises(F.FvlbmError):
+        s.wall_force(5)

@@ -640,3 +640,41 @@ def test_wall_face_value(oracle_mod):
     assert len(faces) == 8
     for c, k, grp in faces:
         assert np.allclose(phi[c, k], oracle_mod.feq(rho0, *grp.u), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- wall force
+# The force on a wall group is the momentum flux through its faces with the
+# scheme's face values (f_P of Eq. 18 at a wall).  Pinned by hydrostatics (a
+# state at rest pushes on each wall with p = rho/3 along the outward normal) and
+# by the steady Couette shear stress rho nu U / H with nu = tau/3 (Eq. 6).
+
+def test_wall_force_at_rest_is_pressure(oracle_mod):
+    m = mg.cavity(n=12, jitter=0.2, seed=3, lid_u=0.1)
+    o = oracle_mod.Oracle(m, tau=0.01, cfl=0.5, u_ref=0.1)
+    o.init()
+    f = o.f
+    f_walls, p_walls = o.wall_force(f, 0)        # left, right, bottom at rest
+    f_lid, p_lid = o.wall_force(f, 1)            # moving lid over fluid at rest
+    assert len(p_walls) == 36 and len(p_lid) == 12
+    assert np.allclose(p_walls, 1 / 3, atol=1e-15) and np.allclose(p_lid, 1 / 3, atol=1e-15)
+    # outward normals: left (-1,0), right (1,0), bottom (0,-1); top (0,1); walls of length 1
+    assert np.allclose(f_walls, [0.0, -1 / 3], atol=1e-14)
+    assert np.allclose(f_lid, [0.0, 1 / 3], atol=1e-14)
+
+
+def test_wall_force_couette_shear_stress(oracle_mod):
+    U, tau = 0.1, 0.8
+    m = mg.couette(16, 16, U=U)
+    o = oracle_mod.Oracle(m, tau=tau, cfl=0.5, u_ref=U, scheme="euler")
+    o.init()
+    o.step(10000)
+    f = o.f
+    nu = tau / 3
+    f_bot, _ = o.wall_force(f, 0)                # wall at rest, y = 0
+    f_top, _ = o.wall_force(f, 1)                # moving wall, y = 1
+    # the fluid drags the moving wall backwards and the resting wall forwards
+    assert f_top[0] == pytest.approx(-nu * U, rel=1e-6)
+    assert f_bot[0] == pytest.approx(nu * U, rel=1e-6)
+    assert f_top[1] == pytest.approx(1 / 3, rel=1e-9) and f_bot[1] == pytest.approx(-1 / 3, rel=1e-9)
+    # a wrong viscosity (tau + 1/2, excluded in Section 2.1) would be 60 % off
+    assert abs(f_top[0] + (tau + 0.5) / 3 * U) > 0.3 * nu * U
