@@ -403,3 +403,22 @@ def test_wall_force_matches_oracle(F, O, storage):
             assert np.abs(fg - fo).max() <= 1e-7 + 1e-6 * np.abs(fo).max(), (g, fg, fo)
     with pytest.raises(F.FvlbmError):
         s.wall_force(5)
+
+
+def test_tiny_meshes_and_degenerate_calls(F, O):
+    # one quad (four wall slots), two triangles, eight triangles, a two-cell periodic channel:
+    # tiles far smaller than any block size, every cell a boundary cell
+    U = 0.1
+    for m in [mg.cavity(n=1, ratio=1.0, jitter=0.0, tri=False), mg.cavity(n=1, ratio=1.0, jitter=0.0, tri=True),
+              mg.cavity(n=2, ratio=1.0, jitter=0.0, tri=True), mg.couette(1, 2, U=U)]:
+        (rg, ug, st), (ro, uo), o, s = _run_pair(F, O, m, 0.01, "rk4", 20, storage="fp32dev")
+        assert np.abs(ug - uo).max() <= 1e-5 * U and np.abs(rg - ro).max() <= 1e-6
+        f0 = s.f
+        s.step(0)                                      # no-op
+        assert np.array_equal(s.f, f0) and s.stats()["steps"] == 20
+        for block in (64, 512):                        # one tile either way
+            s.set_schedule(block, True, False)
+        b = F.Batch([s])                               # a batch of one
+        b.step(3)
+        b.close()
+        assert s.stats()["steps"] == 23
