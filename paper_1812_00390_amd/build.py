@@ -13,9 +13,12 @@ OUT = os.path.join(HERE, "libfvlbm.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("FVLBM_OFFLOAD_ARCH", "gfx950")
 
-# -packed-fp32-ops: no packed FP32 instructions in any device code
+# -packed-fp32-ops: no packed FP32 instructions in any device code.
+# kernarg preload: kernel arguments arrive in scalar registers at wave start (the
+# code object keeps a load prologue for firmware without the feature).
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-kernarg-preload-count=16",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
