@@ -81,6 +81,7 @@ struct fvlbm_solver {
     int lag = 1000;
     bool failed = false;
     InstDesc *desc_dev = nullptr;   // [N_KINDS]
+    InstDesc desc_host[N_KINDS];    // host copies (a single instance's first-load values go as kernel arguments)
     UnitTable ut;
     Schedule sched;
     const TileTables *tiles = nullptr;
@@ -228,12 +229,13 @@ hipGraphExec_t solver_graph(fvlbm_solver *s, int cur, int nsteps) {
     for (int it2 = 0; it2 < nsteps && ok; it2++) {
         step_kinds(s->p.scheme, c, hp, ks);
         for (int k : ks) {
-            argstore.emplace_back(new void *[8]);
+            argstore.emplace_back(new void *[16]);
             void **ab = argstore.back().get();
-            ab[0] = new char[64];
+            ab[0] = new char[sizeof(StageArgs)];
             hipGraphNode_t node;
             ok = add_stage_node(g, &node, prev ? &prev : nullptr, prev ? 1 : 0, s->desc_dev + k, s->ut,
-                                s->mesh->dev.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->h2max, s->tiles->h1max, ab) == hipSuccess;
+                                s->mesh->dev.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->h2max,
+                                s->tiles->h1max, ab, &s->desc_host[k]) == hipSuccess;
             prev = node;
             if (!ok) break;
         }
@@ -268,7 +270,8 @@ fvlbm_status enqueue_steps(fvlbm_solver *s, int64_t n) {
         }
         step_kinds(s->p.scheme, s->cur, s->have_prev, ks);
         for (int k : ks) {
-            hipError_t e = launch_stage(s->desc_dev + k, s->ut, nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->h2max, s->tiles->h1max, s->stream);
+            hipError_t e = launch_stage(s->desc_dev + k, s->ut, nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent,
+                                        s->tiles->h2max, s->tiles->h1max, s->stream, &s->desc_host[k]);
             if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("stage launch failed: ") + hipGetErrorString(e));
         }
         advance_position(s->p.scheme, s->cur, s->have_prev);
@@ -279,9 +282,9 @@ fvlbm_status enqueue_steps(fvlbm_solver *s, int64_t n) {
 }
 
 fvlbm_status upload_descs(fvlbm_solver *s) {
-    InstDesc d[N_KINDS];
+    InstDesc *d = s->desc_host;
     fill_descs(s, s->tiles, d);
-    if (hipMemcpy(s->desc_dev, d, sizeof(d), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(s->desc_dev, d, sizeof(InstDesc) * N_KINDS, hipMemcpyHostToDevice) != hipSuccess)
         return fail(FVLBM_E_DEVICE, "descriptor upload failed");
     return FVLBM_OK;
 }
@@ -547,7 +550,8 @@ fvlbm_status fvlbm_rhs(fvlbm_solver *s, double *rhs) {
     const MeshDev &m = s->mesh->dev;
     double *out = reinterpret_cast<double *>(s->buf + s->L.out);
     int k = s->cur == 0 ? RH0 : (s->cur == 1 ? RH1 : RH2);
-    hipError_t e = launch_stage(s->desc_dev + k, s->ut, m.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->h2max, s->tiles->h1max, s->stream);
+    hipError_t e = launch_stage(s->desc_dev + k, s->ut, m.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent,
+                                s->tiles->h2max, s->tiles->h1max, s->stream, &s->desc_host[k]);
     if (e == hipSuccess) e = launch_rhs_out(reinterpret_cast<float *>(s->buf + s->L.r32), m.n_cells, m.np, m.perm_dev, out, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(rhs, out, (size_t)Q * m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -732,9 +736,9 @@ hipGraphExec_t batch_graph(fvlbm_batch *b, int cur, int nsteps) {
             std::vector<hipGraphNode_t> now;
             for (int t = 0; t < 2 && ok; t++) {
                 if (b->ut[t].n_units == 0) continue;
-                argstore.emplace_back(new void *[8]);
+                argstore.emplace_back(new void *[16]);
                 void **ab = argstore.back().get();
-                ab[0] = new char[64];
+                ab[0] = new char[sizeof(StageArgs)];
                 hipGraphNode_t node;
                 ok = add_stage_node(g, &node, prev.empty() ? nullptr : prev.data(), (int)prev.size(),
                                     b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,

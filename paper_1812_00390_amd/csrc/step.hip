@@ -579,6 +579,13 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
     if (d.mode != 3) store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i);
 }
 
+// The values a tile's first loads depend on (kernel arguments for a single instance).
+struct Hot {
+    const void *src;
+    const int *halo_idx;
+    int np, n_cells, h1s, h2s;
+};
+
 // One RHS evaluation and update for one tile of T cells.
 //   Phase 1  one round of loads: the tile's values, both halo rings' values
 //            (to LDS), this thread's cell geometry and faces, its ring-1
@@ -590,18 +597,23 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
 //            update, store.
 // Dynamic LDS: nA = T + (largest ring-1 slot count) region-A records, then
 // region-B records for the largest ring-2 slot count (sized by the launcher).
-template <int NF, int STORE, int T>
-__device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, int2 u, float4 *A, float4 *B) {
+template <int NF, int STORE, int T, bool DIRECT>
+__device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, int2 u, const Hot &hot, float4 *A,
+                                          float4 *B) {
     const InstDesc &d = descs[u.x];
+    // the values the first loads depend on: kernel arguments for a single instance
+    // (no descriptor load on the path to the first loads), else the descriptor
+    const void *src = DIRECT ? hot.src : d.src;
+    const int n_cells = DIRECT ? hot.n_cells : d.n_cells;
+    const int h1s = DIRECT ? hot.h1s : d.h1s, h2s = DIRECT ? hot.h2s : d.h2s;
+    const int *halo_idx = DIRECT ? hot.halo_idx : d.halo_idx;
+    const size_t np = (size_t)(DIRECT ? hot.np : d.np);
     const int tile = u.y;
     const int tid = threadIdx.x;
     const int i = tile * T + tid;
-    const bool valid = i < d.n_cells;
-    const int h1s = d.h1s, h2s = d.h2s;
+    const bool valid = i < n_cells;
     const int a_end = T + h1s;                     // local indices below this are region A
-    const int *hidx = d.halo_idx + (size_t)tile * (size_t)(h1s + h2s);
-    const size_t np = (size_t)d.np;
-    const bool sep_base = d.mode == 0 && d.base != d.src;
+    const int *hidx = halo_idx + (size_t)tile * (size_t)(h1s + h2s);
 
     // ---- phase 1
     // Straight-line loads (indices clamped into range instead of branching, so
@@ -620,7 +632,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     CellGeo<NF> geo;
     CellFaces<NF> cf;
     const int ic = valid ? i : 0;
-    load_cell<STORE>(d.src, np, ic, f, d.ref);
+    load_cell<STORE>(src, np, ic, f, d.ref);
     const uint2 ln = ldo<uint2>(d.lnbr, (uint32_t)ic * 8u);
     geo.load(d, ic);
     cf.load(d, ic);
@@ -628,10 +640,11 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     float hf0 = 0.f, f1[Q], f2[Q];
     CellGeo<NF> hgeo;
     {
-        load_cell<STORE>(d.src, np, c1 >= 0 ? c1 : 0, f1, d.ref);
+        load_cell<STORE>(src, np, c1 >= 0 ? c1 : 0, f1, d.ref);
         hgeo.load(d, c1 >= 0 ? c1 : 0);
-        load_cell<STORE>(d.src, np, c2 >= 0 ? c2 : 0, f2, d.ref, 1);
+        load_cell<STORE>(src, np, c2 >= 0 ? c2 : 0, f2, d.ref, 1);
     }
+    const bool sep_base = d.mode == 0 && d.base != src;   // (descriptor fields: after the first loads are out)
     if (sep_base) load_cell<STORE>(d.base, np, ic, base, d.ref);
     h0 = f[0];
 #pragma unroll
@@ -651,14 +664,14 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         const int c = ldg(hidx, k);
         if (c < 0) continue;
         float g[Q];
-        load_cell<STORE>(d.src, np, c, g, d.ref, 1);
+        load_cell<STORE>(src, np, c, g, d.ref, 1);
         wr_f(A + (T + k) * RA, g);
     }
     for (int k = tid + T; k < h2s; k += T) {        // ring 2 larger than the tile
         const int c = ldg(hidx, h1s + k);
         if (c < 0) continue;
         float g[Q];
-        load_cell<STORE>(d.src, np, c, g, d.ref, 1);
+        load_cell<STORE>(src, np, c, g, d.ref, 1);
         wr_f(B + k * RB, g);
     }
     __syncthreads();
@@ -690,7 +703,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
             g2.invert(cc);
             {
                 float t[Q];
-                load_cell<STORE>(d.src, np, c, t, d.ref);
+                load_cell<STORE>(src, np, c, t, d.ref);
                 hc[0] = t[0];
             }
             rd_f(A + (T + k) * RA, hc);
@@ -702,57 +715,66 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     if (valid) tile_update<NF, STORE>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A);
 }
 
-template <int NF, int STORE, int T>
-__global__ void __launch_bounds__(T) k_tile(const InstDesc *__restrict__ descs,
-                                            const int2 *__restrict__ units, int n_units,
-                                            int xcd_remap, int nA) {
+// DIRECT: one instance whose unit b is tile b, its first-load values passed as
+// arguments (they reach scalar registers with the wave); otherwise units are
+// read from the table and everything from the descriptors.
+// (Arguments in the order the kernel needs them: the first sixteen dwords arrive in
+// scalar registers.)
+template <int NF, int STORE, int T, bool DIRECT>
+__global__ void __launch_bounds__(T) k_tile(const int *hot_halo_idx, const void *hot_src, int hot_h1s, int hot_h2s,
+                                            int hot_np, int hot_n_cells, int n_units, int xcd_remap,
+                                            const InstDesc *__restrict__ descs, int nA,
+                                            const int2 *__restrict__ units) {
     extern __shared__ float4 lds4[];
     const int ub = remap_block(blockIdx.x, n_units, xcd_remap);
-    tile_body<NF, STORE, T>(descs, units ? units[ub] : make_int2(0, ub), lds4, lds4 + nA * RA);
+    const Hot hot{hot_src, hot_halo_idx, hot_np, hot_n_cells, hot_h1s, hot_h2s};
+    tile_body<NF, STORE, T, DIRECT>(descs, (DIRECT || !units) ? make_int2(0, ub) : units[ub], hot, lds4, lds4 + nA * RA);
 }
 
 // (units null: a single instance whose unit b is tile b.)
 // Persistent form: a grid sized to the resident capacity walks the unit list
 // (a multiple of 8 blocks, so each block stays on one XCD's range of tiles).
 template <int NF, int STORE, int T>
-__global__ void __launch_bounds__(T) k_tile_persistent(const InstDesc *__restrict__ descs,
-                                                       const int2 *__restrict__ units, int n_units,
-                                                       int xcd_remap, int nA) {
+__global__ void __launch_bounds__(T) k_tile_persistent(const int *, const void *, int, int, int, int, int n_units,
+                                                       int xcd_remap, const InstDesc *__restrict__ descs, int nA,
+                                                       const int2 *__restrict__ units) {
     extern __shared__ float4 lds4[];
+    const Hot hot{};
     for (int b = blockIdx.x; b < n_units; b += gridDim.x) {
         const int ub = remap_block(b, n_units, xcd_remap);
-        tile_body<NF, STORE, T>(descs, units ? units[ub] : make_int2(0, ub), lds4, lds4 + nA * RA);
+        tile_body<NF, STORE, T, false>(descs, units ? units[ub] : make_int2(0, ub), hot, lds4, lds4 + nA * RA);
         __syncthreads();             // the next unit reuses the LDS records
     }
 }
 
 template <int NF, int STORE, int T>
-const void *fn(bool persistent) {
-    return persistent ? reinterpret_cast<const void *>(&k_tile_persistent<NF, STORE, T>)
-                      : reinterpret_cast<const void *>(&k_tile<NF, STORE, T>);
+const void *fn(bool persistent, bool direct) {
+    if (persistent) return reinterpret_cast<const void *>(&k_tile_persistent<NF, STORE, T>);
+    return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true>)
+                  : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false>);
 }
 
 template <int NF, int STORE>
-const void *pick_t(int T, bool persistent) {
+const void *pick_t(int T, bool persistent, bool direct) {
     switch (T) {
-    case 64: return fn<NF, STORE, 64>(persistent);
-    case 128: return fn<NF, STORE, 128>(persistent);
-    case 256: return fn<NF, STORE, 256>(persistent);
-    default: return fn<NF, STORE, 512>(persistent);
+    case 64: return fn<NF, STORE, 64>(persistent, direct);
+    case 128: return fn<NF, STORE, 128>(persistent, direct);
+    case 256: return fn<NF, STORE, 256>(persistent, direct);
+    default: return fn<NF, STORE, 512>(persistent, direct);
     }
 }
 
-const void *pick(int nf, int storage, int T, bool persistent) {
+const void *pick(int nf, int storage, int T, bool persistent, bool direct) {
     if (nf == 3) {
-        if (storage == FVLBM_STORE_FP32) return pick_t<3, FVLBM_STORE_FP32>(T, persistent);
-        if (storage == FVLBM_STORE_FP32_DEV) return pick_t<3, FVLBM_STORE_FP32_DEV>(T, persistent);
-        if (storage == FVLBM_STORE_I16_DEV) return pick_t<3, FVLBM_STORE_I16_DEV>(T, persistent);
-        return pick_t<3, FVLBM_STORE_FP16_DEV>(T, persistent);
+        if (storage == FVLBM_STORE_FP32) return pick_t<3, FVLBM_STORE_FP32>(T, persistent, direct);
+        if (storage == FVLBM_STORE_FP32_DEV) return pick_t<3, FVLBM_STORE_FP32_DEV>(T, persistent, direct);
+        if (storage == FVLBM_STORE_I16_DEV) return pick_t<3, FVLBM_STORE_I16_DEV>(T, persistent, direct);
+        return pick_t<3, FVLBM_STORE_FP16_DEV>(T, persistent, direct);
     }
-    if (storage == FVLBM_STORE_FP32) return pick_t<4, FVLBM_STORE_FP32>(T, persistent);
-    if (storage == FVLBM_STORE_FP32_DEV) return pick_t<4, FVLBM_STORE_FP32_DEV>(T, persistent);
-    if (storage == FVLBM_STORE_I16_DEV) return pick_t<4, FVLBM_STORE_I16_DEV>(T, persistent);
-    return pick_t<4, FVLBM_STORE_FP16_DEV>(T, persistent);
+    if (storage == FVLBM_STORE_FP32) return pick_t<4, FVLBM_STORE_FP32>(T, persistent, direct);
+    if (storage == FVLBM_STORE_FP32_DEV) return pick_t<4, FVLBM_STORE_FP32_DEV>(T, persistent, direct);
+    if (storage == FVLBM_STORE_I16_DEV) return pick_t<4, FVLBM_STORE_I16_DEV>(T, persistent, direct);
+    return pick_t<4, FVLBM_STORE_FP16_DEV>(T, persistent, direct);
 }
 
 // Grid of a launch: one block per unit, or (persistent) the number of blocks
@@ -760,7 +782,7 @@ const void *pick(int nf, int storage, int T, bool persistent) {
 int grid_blocks(const UnitTable &ut, int persistent, int nf, int storage, size_t lds) {
     if (!persistent) return ut.n_units;
     int per_cu = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick(nf, storage, ut.block, true), ut.block, lds);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick(nf, storage, ut.block, true, false), ut.block, lds);
     int dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -769,6 +791,26 @@ int grid_blocks(const UnitTable &ut, int persistent, int nf, int storage, size_t
 }
 
 }  // namespace
+
+StageArgs stage_args(const InstDesc *descs_dev, const UnitTable &ut, int xcd_remap, int persistent, int h1max,
+                     const InstDesc *host_desc) {
+    StageArgs a{};
+    a.d = descs_dev;
+    a.u = ut.units;
+    a.n = ut.n_units;
+    a.x = xcd_remap;
+    a.nA = ut.block + h1max;
+    a.direct = ut.direct && host_desc && !persistent;
+    if (a.direct) {
+        a.src = host_desc->src;
+        a.hidx = host_desc->halo_idx;
+        a.np = host_desc->np;
+        a.nc = host_desc->n_cells;
+        a.h1 = host_desc->h1s;
+        a.h2 = host_desc->h2s;
+    }
+    return a;
+}
 
 size_t stage_lds_limit() {
     int dev = 0, v = 0;
@@ -782,14 +824,12 @@ size_t stage_lds_bytes(int T, int h2max, int h1max) {
 }
 
 hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                        int xcd_remap, int persistent, int h2max, int h1max, hipStream_t stream) {
+                        int xcd_remap, int persistent, int h2max, int h1max, hipStream_t stream, const InstDesc *host_desc) {
     if (ut.n_units == 0) return hipSuccess;
-    const int2 *units = ut.units;
-    int n_units = ut.n_units;
-    int nA = ut.block + h1max;
+    StageArgs a = stage_args(descs_dev, ut, xcd_remap, persistent, h1max, host_desc);
+    void *args[] = {&a.hidx, &a.src, &a.h1, &a.h2, &a.np, &a.nc, &a.n, &a.x, &a.d, &a.nA, &a.u};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
-    void *args[] = {(void *)&descs_dev, (void *)&units, (void *)&n_units, (void *)&xcd_remap, (void *)&nA};
-    const void *fn_ptr = pick(nf, storage, ut.block, persistent);
+    const void *fn_ptr = pick(nf, storage, ut.block, persistent, a.direct);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn_ptr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -799,16 +839,18 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
 
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                          int xcd_remap, int persistent, int h2max, int h1max, void **argbuf) {
-    // argbuf: caller-owned storage for the argument values, alive until the graph is instantiated
-    struct Args { const InstDesc *d; const int2 *u; int n; int x; int nA; };
-    Args *a = reinterpret_cast<Args *>(argbuf[0]);
-    a->d = descs_dev; a->u = ut.units; a->n = ut.n_units; a->x = xcd_remap; a->nA = ut.block + h1max;
+                          int xcd_remap, int persistent, int h2max, int h1max, void **argbuf,
+                          const InstDesc *host_desc) {
+    // argbuf: caller-owned storage (a StageArgs block in argbuf[0], then one pointer per
+    // argument), alive until the graph is instantiated
+    StageArgs *a = reinterpret_cast<StageArgs *>(argbuf[0]);
+    *a = stage_args(descs_dev, ut, xcd_remap, persistent, h1max, host_desc);
     void **kp = argbuf + 1;
-    kp[0] = &a->d; kp[1] = &a->u; kp[2] = &a->n; kp[3] = &a->x; kp[4] = &a->nA;
+    kp[0] = &a->hidx; kp[1] = &a->src; kp[2] = &a->h1; kp[3] = &a->h2; kp[4] = &a->np; kp[5] = &a->nc;
+    kp[6] = &a->n; kp[7] = &a->x; kp[8] = &a->d; kp[9] = &a->nA; kp[10] = &a->u;
     hipKernelNodeParams p{};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
-    p.func = const_cast<void *>(pick(nf, storage, ut.block, persistent));
+    p.func = const_cast<void *>(pick(nf, storage, ut.block, persistent, a->direct));
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(p.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
