@@ -557,13 +557,30 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
     }
     if (bnd) boundary_flux<NF>(d, i, hi, gxi, gyi, mi, hei, packed, cf.inva, acc);
 
+    // The BGK source moves no mass and no momentum: f_eq carries the density and
+    // momentum of f (Eqs. 3, 5).  In FP32 the rounding of f_eq (terms near 0.05,
+    // an ulp near 4e-9, divided by tau) leaves residual moments that act as a steady
+    // momentum source and add up over a run.  They are projected out of f_eq - f
+    // (subtracting w_a (m0 + 3 e_a.m), an identity in exact arithmetic).
+    float neq[Q];
+#pragma unroll
+    for (int a = 0; a < Q; a++) neq[a] = hei[a] - hi[a];
+    {
+        const float m0 = ((neq[0] + neq[1]) + (neq[2] + neq[3])) + ((neq[4] + neq[5]) + (neq[6] + neq[7])) + neq[8];
+        const float mx = ((neq[1] - neq[3]) + (neq[5] - neq[6])) + (neq[8] - neq[7]);
+        const float my = ((neq[2] - neq[4]) + (neq[5] + neq[6])) - (neq[7] + neq[8]);
+        neq[0] = fmaf(-WT[0], m0, neq[0]);
+#pragma unroll
+        for (int a = 1; a < Q; a++) neq[a] = fmaf(-WT[a], fmaf(3.f, edot(a, mx, my), m0), neq[a]);
+    }
+
     // RHS = -sum (e.n dl/A) phi - (f - f_eq)/tau  (Eq. 10), then the update.
     const uint32_t o4 = (uint32_t)i * 4u;
     const size_t pb4 = (size_t)d.np * 4;
     float bv[Q], inc[Q];
 #pragma unroll
     for (int a = 0; a < Q; a++) {
-        const float rhs = fmaf(hei[a] - hi[a], d.inv_tau, -acc[a]);
+        const float rhs = fmaf(neq[a], d.inv_tau, -acc[a]);
         if (d.mode == 0) {
             bv[a] = sep_base ? base[a] : hi[a];
             inc[a] = d.coef * rhs;
