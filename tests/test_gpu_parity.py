@@ -120,6 +120,12 @@ FP16_CAVITY_UTOL = 2.5e-3
 # 16-bit block-scaled deviations (15 bits for a cell's largest deviation): the
 # 1e-3 U target holds.
 I16_UTOL = 1e-3
+# FP16 deviations over the 20,000-step cylinder run: each store's rounding is
+# unbiased, but its noise in a cell's mass and momentum is not relaxed by the
+# collision and adds up as a random walk (about sqrt(20000) store roundings);
+# 8.5e-3 U was measured, so FP16 misses the 1e-3 U target on this run, which
+# the block-scaled format meets.
+FP16_LONG_UTOL = 1.5e-2
 
 
 @pytest.mark.parametrize("scheme", ["euler", "rk4", "ab2"])
@@ -368,6 +374,34 @@ def test_cylinder_cfg3_full_size_vs_stored_oracle(F):
         err = np.abs(u[idx] - ref["u"]).max()
         print(f"cylinder 98k quads RK4 100 steps {storage}: max|u-u_ref| = {err:.3e}")
         assert err <= utol * 0.1
+
+
+def test_cylinder_cfg3_full_run_vs_stored_oracle(F):
+    # the full start-up run of the cylinder case: 20,000 four-stage RK steps
+    path = os.path.join(GOLDEN, "oracle_cylinder256_rk4_20000.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle run not generated (tests/golden/make_oracle_refs.py)")
+    ref = np.load(path)
+    m = mg.cylinder(nr=256, nt=384)
+    mesh = F.Mesh(m)
+    errs = {}
+    for storage, utol in (("fp32", 1e-5), ("fp32dev", 1e-5), ("fp16dev", FP16_LONG_UTOL), ("i16dev", I16_UTOL)):
+        s = F.Solver(mesh, F.make_params(tau=float(ref["tau"]), dt=float(ref["dt"]), scheme="rk4",
+                                         storage=storage, u_ref=0.2, u_dev=(0.1, 0.0)),
+                     u=np.tile([0.1, 0.0], (m.n_cells, 1)))
+        s.step(int(ref["steps"]))
+        rho, u, _ = s.macros()
+        idx = ref["idx"]
+        d = np.abs(u[idx] - ref["u"]).max(axis=1)
+        k = int(np.argmax(d))
+        cn = m.cell_nodes[m.cell_ptr[idx[k]]:m.cell_ptr[idx[k] + 1]]
+        c = np.round(m.nodes[cn].mean(axis=0), 4)
+        print(f"cylinder 98k quads RK4 20000 steps {storage}: max|u-u_ref| = {d[k]:.3e} at cell {idx[k]} {c}; "
+              f"99th pct {np.percentile(d, 99):.3e}, median {np.median(d):.3e}")
+        errs[storage] = (d[k], utol)
+        s.close()
+    for storage, (err, utol) in errs.items():
+        assert err <= utol * 0.1, storage
 
 
 def test_streaming_size_mesh_invariants(F):
