@@ -229,13 +229,11 @@ struct Macro {
 // Eq. 5 on deviations h = f - f_eq(rho0, u_dev): rho = rho0 + sum h, rho u = rho0 u_dev + sum e h.
 __device__ inline Macro moments(const float h[Q], const RefDev &r) {
     Macro m;
-    float s = 0.f, mx = 0.f, my = 0.f;
+    float s = h[0];
 #pragma unroll
-    for (int a = 0; a < Q; a++) {
-        s += h[a];
-        if (EX[a]) mx += EX[a] * h[a];
-        if (EY[a]) my += EY[a] * h[a];
-    }
+    for (int a = 1; a < Q; a++) s += h[a];
+    const float mx = ((((h[1] - h[3]) + h[5]) - h[6]) - h[7]) + h[8];   // sum e_x h
+    const float my = ((((h[2] - h[4]) + h[5]) + h[6]) - h[7]) - h[8];   // sum e_y h
     m.drho = s;
     m.rho = r.rho0 + s;
     m.jx = r.jx0 + mx;
@@ -547,12 +545,23 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
         float hj[Q], gxj[Q], gyj[Q];
         rd_f(rec, hj);
         rd_g(rec, gxj, gyj);
+        // upwind side (Eq. 11): one comparison per pair of opposite directions, whose
+        // e.n differ in sign only (where e.n = 0 the choice is multiplied by zero)
+        bool up[Q];
+        up[1] = g.x > 0.f;
+        up[2] = g.y > 0.f;
+        up[5] = edot(5, g.x, g.y) > 0.f;
+        up[6] = edot(6, g.x, g.y) > 0.f;
+        up[3] = !up[1];
+        up[4] = !up[2];
+        up[7] = !up[5];
+        up[8] = !up[6];
 #pragma unroll
         for (int a = 1; a < Q; a++) {
             const float en = edot(a, g.x, g.y);
             const float own_v = fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a]));
             const float nb_v = fmaf(gyj[a], q.y, fmaf(gxj[a], q.x, hj[a]));
-            acc[a] = fmaf(en, en > 0.f ? own_v : nb_v, acc[a]);
+            acc[a] = fmaf(en, up[a] ? own_v : nb_v, acc[a]);
         }
     }
     if (bnd) boundary_flux<NF>(d, i, hi, gxi, gyi, mi, hei, packed, cf.inva, acc);
@@ -575,6 +584,10 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
     }
 
     // RHS = -sum (e.n dl/A) phi - (f - f_eq)/tau  (Eq. 10), then the update.
+    // (The uniform mode test stays inside the direction loop.  Written as one
+    // switch per cell, hipcc 7.2 emitted the Adams-Bashforth path with its store
+    // offset register never set on one branch: the IR was right, the machine code
+    // was not.)
     const uint32_t o4 = (uint32_t)i * 4u;
     const size_t pb4 = (size_t)d.np * 4;
     float bv[Q], inc[Q];
