@@ -56,6 +56,8 @@ Layout layout(int n, int np, const fvlbm_params &p) {
 }
 
 enum Kind { E0 = 0, E1, R1, R2, R3, R4, F0, F1, A0, A1, RH0, RH1, RH2, N_KINDS };
+// stage kinds whose update is base + coef RHS (descriptor mode 0)
+bool mode0(int k) { return k <= R4; }
 
 }  // namespace
 
@@ -235,7 +237,7 @@ hipGraphExec_t solver_graph(fvlbm_solver *s, int cur, int nsteps) {
             hipGraphNode_t node;
             ok = add_stage_node(g, &node, prev ? &prev : nullptr, prev ? 1 : 0, s->desc_dev + k, s->ut,
                                 s->mesh->dev.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent, s->tiles->h2max,
-                                s->tiles->h1max, ab, &s->desc_host[k]) == hipSuccess;
+                                s->tiles->h1max, mode0(k), ab, &s->desc_host[k]) == hipSuccess;
             prev = node;
             if (!ok) break;
         }
@@ -271,7 +273,7 @@ fvlbm_status enqueue_steps(fvlbm_solver *s, int64_t n) {
         step_kinds(s->p.scheme, s->cur, s->have_prev, ks);
         for (int k : ks) {
             hipError_t e = launch_stage(s->desc_dev + k, s->ut, nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent,
-                                        s->tiles->h2max, s->tiles->h1max, s->stream, &s->desc_host[k]);
+                                        s->tiles->h2max, s->tiles->h1max, mode0(k), s->stream, &s->desc_host[k]);
             if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("stage launch failed: ") + hipGetErrorString(e));
         }
         advance_position(s->p.scheme, s->cur, s->have_prev);
@@ -551,7 +553,7 @@ fvlbm_status fvlbm_rhs(fvlbm_solver *s, double *rhs) {
     double *out = reinterpret_cast<double *>(s->buf + s->L.out);
     int k = s->cur == 0 ? RH0 : (s->cur == 1 ? RH1 : RH2);
     hipError_t e = launch_stage(s->desc_dev + k, s->ut, m.nf, s->p.storage, s->sched.xcd_remap, s->sched.persistent,
-                                s->tiles->h2max, s->tiles->h1max, s->stream, &s->desc_host[k]);
+                                s->tiles->h2max, s->tiles->h1max, mode0(k), s->stream, &s->desc_host[k]);
     if (e == hipSuccess) e = launch_rhs_out(reinterpret_cast<float *>(s->buf + s->L.r32), m.n_cells, m.np, m.perm_dev, out, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(rhs, out, (size_t)Q * m.n_cells * sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -742,7 +744,7 @@ hipGraphExec_t batch_graph(fvlbm_batch *b, int cur, int nsteps) {
                 hipGraphNode_t node;
                 ok = add_stage_node(g, &node, prev.empty() ? nullptr : prev.data(), (int)prev.size(),
                                     b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
-                                    b->sched.xcd_remap, b->sched.persistent, b->h2max[t], b->h1max[t], ab) == hipSuccess;
+                                    b->sched.xcd_remap, b->sched.persistent, b->h2max[t], b->h1max[t], mode0(k), ab) == hipSuccess;
                 now.push_back(node);
             }
             prev = now;
@@ -785,7 +787,8 @@ fvlbm_status batch_enqueue(fvlbm_batch *b, int64_t n_steps, bool snapshots) {
                 for (int k : ks)
                     for (int t = 0; t < 2; t++) {
                         hipError_t e = launch_stage(b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
-                                                    b->sched.xcd_remap, b->sched.persistent, b->h2max[t], b->h1max[t], b->stream);
+                                                    b->sched.xcd_remap, b->sched.persistent, b->h2max[t], b->h1max[t], mode0(k),
+                                                    b->stream);
                         if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
                     }
                 advance_position(b->scheme, c, hp);

@@ -169,10 +169,13 @@ struct UnitTable {
 // Launch one RHS-evaluation stage over all units (one unit = one tile of
 // ut.block cells).  nf: 3 or 4; storage FVLBM_STORE_*; h2max, h1max: the
 // largest ring-2 and ring-1 slot counts over the launch's instances (LDS size).
+// mode0: the stage is a base + coef RHS update (descriptor mode 0: Euler, RK
+// stages), which runs a kernel compiled for it; other modes run one block per
+// unit whatever `persistent` says.
 // host_desc: the host copy of the launch's descriptor when it is a single instance
 // (its first-load values then go as kernel arguments), or null.
 hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                        int xcd_remap, int persistent, int h2max, int h1max, hipStream_t stream,
+                        int xcd_remap, int persistent, int h2max, int h1max, bool mode0, hipStream_t stream,
                         const InstDesc *host_desc = nullptr);
 size_t stage_lds_bytes(int T, int h2max, int h1max);
 // LDS a workgroup may use on the current device (160 KiB on gfx950).
@@ -192,7 +195,7 @@ StageArgs stage_args(const InstDesc *descs_dev, const UnitTable &ut, int xcd_rem
                      const InstDesc *host_desc);
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                          int xcd_remap, int persistent, int h2max, int h1max, void **argbuf,
+                          int xcd_remap, int persistent, int h2max, int h1max, bool mode0, void **argbuf,
                           const InstDesc *host_desc = nullptr);
 
 // Step 0 and conversions (FP64 host data in input order <-> device storage).

@@ -516,7 +516,7 @@ __device__ inline void boundary_flux(const InstDesc &d, int i, const float hi[Q]
 
 // Phase 3 for one tile cell: face values, flux sum, BGK source, update, store.
 // base[] holds f(0) of the update when it is not the evaluated state.
-template <int NF, int STORE>
+template <int NF, int STORE, bool M0>
 __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, const float base[Q], bool sep_base,
                                             const int (&code)[NF], uint2 packed, const CellGeo<NF> &geo, const CellFaces<NF> &cf,
                                             const float4 *own, const float4 *A) {
@@ -590,23 +590,24 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
     // was not.)
     const uint32_t o4 = (uint32_t)i * 4u;
     const size_t pb4 = (size_t)d.np * 4;
+    const int mode = M0 ? 0 : d.mode;
     float bv[Q], inc[Q];
 #pragma unroll
     for (int a = 0; a < Q; a++) {
         const float rhs = fmaf(neq[a], d.inv_tau, -acc[a]);
-        if (d.mode == 0) {
+        if (mode == 0) {
             bv[a] = sep_base ? base[a] : hi[a];
             inc[a] = d.coef * rhs;
-        } else if (d.mode == 3) {
+        } else if (mode == 3) {
             sto<float>(plane(d.dst, pb4, a), o4, rhs);
         } else {
-            const float prev = (d.mode == 1) ? rhs : ldo<float>(plane(d.rhs_prev, pb4, a), o4);
+            const float prev = (mode == 1) ? rhs : ldo<float>(plane(d.rhs_prev, pb4, a), o4);
             bv[a] = hi[a];
             inc[a] = (0.5f * d.coef) * (3.f * rhs - prev);
             sto<float>(plane(d.rhs_prev, pb4, a), o4, rhs);
         }
     }
-    if (d.mode != 3) store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i);
+    if (mode != 3) store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i);
 }
 
 // The values a tile's first loads depend on (kernel arguments for a single instance).
@@ -627,7 +628,7 @@ struct Hot {
 //            update, store.
 // Dynamic LDS: nA = T + (largest ring-1 slot count) region-A records, then
 // region-B records for the largest ring-2 slot count (sized by the launcher).
-template <int NF, int STORE, int T, bool DIRECT>
+template <int NF, int STORE, int T, bool DIRECT, bool M0>
 __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, int2 u, const Hot &hot, float4 *A,
                                           float4 *B) {
     const InstDesc &d = descs[u.x];
@@ -674,7 +675,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         hgeo.load(d, c1 >= 0 ? c1 : 0);
         load_cell<STORE>(src, np, c2 >= 0 ? c2 : 0, f2, d.ref, 1);
     }
-    const bool sep_base = d.mode == 0 && d.base != src;   // (descriptor fields: after the first loads are out)
+    const bool sep_base = (M0 || d.mode == 0) && d.base != src;   // (descriptor fields: after the first loads are out)
     if (sep_base) load_cell<STORE>(d.base, np, ic, base, d.ref);
     h0 = f[0];
 #pragma unroll
@@ -742,15 +743,18 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         }
     }
     __syncthreads();
-    if (valid) tile_update<NF, STORE>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A);
+    if (valid) tile_update<NF, STORE, M0>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A);
 }
 
 // DIRECT: one instance whose unit b is tile b, its first-load values passed as
 // arguments (they reach scalar registers with the wave); otherwise units are
 // read from the table and everything from the descriptors.
+// M0: the stage is a base + coef RHS update (Euler, RK stages), fixed at compile
+// time, so the update carries no mode tests; otherwise the mode is read from the
+// descriptor (Adams-Bashforth, RHS output).
 // (Arguments in the order the kernel needs them: the first sixteen dwords arrive in
 // scalar registers.)
-template <int NF, int STORE, int T, bool DIRECT>
+template <int NF, int STORE, int T, bool DIRECT, bool M0>
 __global__ void __launch_bounds__(T) k_tile(const int *hot_halo_idx, const void *hot_src, int hot_h1s, int hot_h2s,
                                             int hot_np, int hot_n_cells, int n_units, int xcd_remap,
                                             const InstDesc *__restrict__ descs, int nA,
@@ -758,13 +762,13 @@ __global__ void __launch_bounds__(T) k_tile(const int *hot_halo_idx, const void 
     extern __shared__ float4 lds4[];
     const int ub = remap_block(blockIdx.x, n_units, xcd_remap);
     const Hot hot{hot_src, hot_halo_idx, hot_np, hot_n_cells, hot_h1s, hot_h2s};
-    tile_body<NF, STORE, T, DIRECT>(descs, (DIRECT || !units) ? make_int2(0, ub) : units[ub], hot, lds4, lds4 + nA * RA);
+    tile_body<NF, STORE, T, DIRECT, M0>(descs, (DIRECT || !units) ? make_int2(0, ub) : units[ub], hot, lds4, lds4 + nA * RA);
 }
 
 // (units null: a single instance whose unit b is tile b.)
 // Persistent form: a grid sized to the resident capacity walks the unit list
 // (a multiple of 8 blocks, so each block stays on one XCD's range of tiles).
-template <int NF, int STORE, int T>
+template <int NF, int STORE, int T, bool M0>
 __global__ void __launch_bounds__(T) k_tile_persistent(const int *, const void *, int, int, int, int, int n_units,
                                                        int xcd_remap, const InstDesc *__restrict__ descs, int nA,
                                                        const int2 *__restrict__ units) {
@@ -772,39 +776,42 @@ __global__ void __launch_bounds__(T) k_tile_persistent(const int *, const void *
     const Hot hot{};
     for (int b = blockIdx.x; b < n_units; b += gridDim.x) {
         const int ub = remap_block(b, n_units, xcd_remap);
-        tile_body<NF, STORE, T, false>(descs, units ? units[ub] : make_int2(0, ub), hot, lds4, lds4 + nA * RA);
+        tile_body<NF, STORE, T, false, M0>(descs, units ? units[ub] : make_int2(0, ub), hot, lds4, lds4 + nA * RA);
         __syncthreads();             // the next unit reuses the LDS records
     }
 }
 
 template <int NF, int STORE, int T>
-const void *fn(bool persistent, bool direct) {
-    if (persistent) return reinterpret_cast<const void *>(&k_tile_persistent<NF, STORE, T>);
-    return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true>)
-                  : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false>);
+const void *fn(bool persistent, bool direct, bool m0) {
+    if (!m0)    // runtime mode: one block per unit (the launchers never ask for persistence here)
+        return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, false>)
+                      : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false, false>);
+    if (persistent) return reinterpret_cast<const void *>(&k_tile_persistent<NF, STORE, T, true>);
+    return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, true>)
+                  : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false, true>);
 }
 
 template <int NF, int STORE>
-const void *pick_t(int T, bool persistent, bool direct) {
+const void *pick_t(int T, bool persistent, bool direct, bool m0) {
     switch (T) {
-    case 64: return fn<NF, STORE, 64>(persistent, direct);
-    case 128: return fn<NF, STORE, 128>(persistent, direct);
-    case 256: return fn<NF, STORE, 256>(persistent, direct);
-    default: return fn<NF, STORE, 512>(persistent, direct);
+    case 64: return fn<NF, STORE, 64>(persistent, direct, m0);
+    case 128: return fn<NF, STORE, 128>(persistent, direct, m0);
+    case 256: return fn<NF, STORE, 256>(persistent, direct, m0);
+    default: return fn<NF, STORE, 512>(persistent, direct, m0);
     }
 }
 
-const void *pick(int nf, int storage, int T, bool persistent, bool direct) {
+const void *pick(int nf, int storage, int T, bool persistent, bool direct, bool m0) {
     if (nf == 3) {
-        if (storage == FVLBM_STORE_FP32) return pick_t<3, FVLBM_STORE_FP32>(T, persistent, direct);
-        if (storage == FVLBM_STORE_FP32_DEV) return pick_t<3, FVLBM_STORE_FP32_DEV>(T, persistent, direct);
-        if (storage == FVLBM_STORE_I16_DEV) return pick_t<3, FVLBM_STORE_I16_DEV>(T, persistent, direct);
-        return pick_t<3, FVLBM_STORE_FP16_DEV>(T, persistent, direct);
+        if (storage == FVLBM_STORE_FP32) return pick_t<3, FVLBM_STORE_FP32>(T, persistent, direct, m0);
+        if (storage == FVLBM_STORE_FP32_DEV) return pick_t<3, FVLBM_STORE_FP32_DEV>(T, persistent, direct, m0);
+        if (storage == FVLBM_STORE_I16_DEV) return pick_t<3, FVLBM_STORE_I16_DEV>(T, persistent, direct, m0);
+        return pick_t<3, FVLBM_STORE_FP16_DEV>(T, persistent, direct, m0);
     }
-    if (storage == FVLBM_STORE_FP32) return pick_t<4, FVLBM_STORE_FP32>(T, persistent, direct);
-    if (storage == FVLBM_STORE_FP32_DEV) return pick_t<4, FVLBM_STORE_FP32_DEV>(T, persistent, direct);
-    if (storage == FVLBM_STORE_I16_DEV) return pick_t<4, FVLBM_STORE_I16_DEV>(T, persistent, direct);
-    return pick_t<4, FVLBM_STORE_FP16_DEV>(T, persistent, direct);
+    if (storage == FVLBM_STORE_FP32) return pick_t<4, FVLBM_STORE_FP32>(T, persistent, direct, m0);
+    if (storage == FVLBM_STORE_FP32_DEV) return pick_t<4, FVLBM_STORE_FP32_DEV>(T, persistent, direct, m0);
+    if (storage == FVLBM_STORE_I16_DEV) return pick_t<4, FVLBM_STORE_I16_DEV>(T, persistent, direct, m0);
+    return pick_t<4, FVLBM_STORE_FP16_DEV>(T, persistent, direct, m0);
 }
 
 // Grid of a launch: one block per unit, or (persistent) the number of blocks
@@ -812,7 +819,7 @@ const void *pick(int nf, int storage, int T, bool persistent, bool direct) {
 int grid_blocks(const UnitTable &ut, int persistent, int nf, int storage, size_t lds) {
     if (!persistent) return ut.n_units;
     int per_cu = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick(nf, storage, ut.block, true, false), ut.block, lds);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick(nf, storage, ut.block, true, false, true), ut.block, lds);
     int dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -854,12 +861,14 @@ size_t stage_lds_bytes(int T, int h2max, int h1max) {
 }
 
 hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                        int xcd_remap, int persistent, int h2max, int h1max, hipStream_t stream, const InstDesc *host_desc) {
+                        int xcd_remap, int persistent, int h2max, int h1max, bool mode0, hipStream_t stream,
+                        const InstDesc *host_desc) {
     if (ut.n_units == 0) return hipSuccess;
+    if (!mode0) persistent = 0;
     StageArgs a = stage_args(descs_dev, ut, xcd_remap, persistent, h1max, host_desc);
     void *args[] = {&a.hidx, &a.src, &a.h1, &a.h2, &a.np, &a.nc, &a.n, &a.x, &a.d, &a.nA, &a.u};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
-    const void *fn_ptr = pick(nf, storage, ut.block, persistent, a.direct);
+    const void *fn_ptr = pick(nf, storage, ut.block, persistent, a.direct, mode0);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn_ptr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -869,8 +878,9 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
 
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                          int xcd_remap, int persistent, int h2max, int h1max, void **argbuf,
+                          int xcd_remap, int persistent, int h2max, int h1max, bool mode0, void **argbuf,
                           const InstDesc *host_desc) {
+    if (!mode0) persistent = 0;
     // argbuf: caller-owned storage (a StageArgs block in argbuf[0], then one pointer per
     // argument), alive until the graph is instantiated
     StageArgs *a = reinterpret_cast<StageArgs *>(argbuf[0]);
@@ -880,7 +890,7 @@ hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode
     kp[6] = &a->n; kp[7] = &a->x; kp[8] = &a->d; kp[9] = &a->nA; kp[10] = &a->u;
     hipKernelNodeParams p{};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
-    p.func = const_cast<void *>(pick(nf, storage, ut.block, persistent, a->direct));
+    p.func = const_cast<void *>(pick(nf, storage, ut.block, persistent, a->direct, mode0));
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(p.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
