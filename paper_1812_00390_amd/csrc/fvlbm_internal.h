@@ -178,7 +178,8 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
                         int xcd_remap, int persistent, int h2max, int h1max, bool mode0, hipStream_t stream,
                         const InstDesc *host_desc = nullptr);
 size_t stage_lds_bytes(int T, int h2max, int h1max);
-// LDS a workgroup may use on the current device (160 KiB on gfx950).
+// Dynamic LDS a stage workgroup may use on the current device: the device's
+// per-workgroup LDS (160 KiB on gfx950) less the kernel's static group table.
 size_t stage_lds_limit();
 // Same as a kernel node for a graph.
 // argbuf: argbuf[0] holds a StageArgs, argbuf[1..11] receive the argument pointers.

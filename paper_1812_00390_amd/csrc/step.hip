@@ -329,6 +329,15 @@ __device__ inline float2 corner(const InstDesc &d, int k, int c) {
     return ldo<float2>(plane(d.vxy, (size_t)d.np * 8, k), (uint32_t)c * 8u);
 }
 
+// v[k] for a wave-uniform k, from registers (no dynamic register indexing)
+template <int NF>
+__device__ __forceinline__ float2 pick2(const float2 (&v)[NF], int k) {
+    float2 r = v[0];
+#pragma unroll
+    for (int j = 1; j < NF; j++) r = k == j ? v[j] : r;
+    return r;
+}
+
 // Least-squares data of one cell held in registers: the stencil offsets and
 // the inverse of M = sum_k w_k d_k d_k^T, w_k = 1/|d_k|^2 (Eq. 12), formed
 // here from the offsets (M is dimensionless and well scaled, so FP32 is
@@ -416,8 +425,8 @@ __device__ inline void wr_g(float4 *rec, const float gx[Q], const float gy[Q]) {
 // Boundary-slot terms of the gradient of cell c: phi_k is the wall / ghost
 // value (Eqs. 18-22) formed from the cell's own state.
 template <int NF>
-__device__ inline void boundary_gradient_body(const InstDesc &d, int c, const CellGeo<NF> &geo, const float hc[Q],
-                                              uint2 packed, float gx[Q], float gy[Q]) {
+__device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
+                                              uint2 packed, const GroupDev *lg, float gx[Q], float gy[Q]) {
     const Macro m = moments(hc, d.ref);
     float he[Q];
     heq(m.drho, m.rho, m.jx, m.jy, d.ref, he);
@@ -425,12 +434,15 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, int c, const Ce
     for (int k = 0; k < NF; k++) {
         const int ck = unpack16(k < 2 ? packed.x : packed.y, k & 1);
         if (ck >= 0 || ck < PAD_BELOW) continue;
-        const float2 dk = ldo<float2>(plane(d.dxy, (size_t)d.np * 8, k), (uint32_t)c * 8u);
+        const float2 dk = pick2<NF>(geo.dk, k);
         const float2 w = lsq_coef(dk, geo.m11, geo.m12, geo.m22);
-        // an outward normal of face k (only its direction enters the ghost values)
-        const float2 gn = scaled_normal(corner(d, k, c), corner(d, k + 1 == NF ? 0 : k + 1, c), 1.f);
+        // the ghost values take only the direction of the face's outward normal (a
+        // symmetry face), and a ghost slot's offset is twice the centre-to-face
+        // distance along that normal (the mirrored centre): dk has the direction
+        const float2 gn = dk;
+        const GroupDev g = lg[-1 - ck];
         float phi[Q];
-        boundary_value(d.groups[-1 - ck], hc, m, he, gn, d.ref, phi);
+        boundary_value(g, hc, m, he, gn, d.ref, phi);
 #pragma unroll
         for (int a = 1; a < Q; a++) {
             const float df = phi[a] - hc[a];
@@ -445,9 +457,9 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, int c, const Ce
 // boundary slots).  Local indices below `a_end` are region-A records, the rest
 // region B.
 template <int NF>
-__device__ inline void gradient_staged(const InstDesc &d, int c, const CellGeo<NF> &geo, const float hc[Q],
+__device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                        const int (&code)[NF], uint2 packed, const float4 *A, const float4 *B, int a_end,
-                                       float gx[Q], float gy[Q]) {
+                                       const GroupDev *lg, float gx[Q], float gy[Q]) {
 #pragma unroll
     for (int a = 1; a < Q; a++) { gx[a] = 0.f; gy[a] = 0.f; }
     bool bnd = false;
@@ -468,30 +480,22 @@ __device__ inline void gradient_staged(const InstDesc &d, int c, const CellGeo<N
             gy[a] = fmaf(w.y, df, gy[a]);
         }
     }
-    if (bnd) boundary_gradient_body<NF>(d, c, geo, hc, packed, gx, gy);
+    if (bnd) boundary_gradient_body<NF>(d, geo, hc, packed, lg, gx, gy);
 }
 
 // Boundary-face terms of the flux sum of tile cell i (Eqs. 18, 23-26).
 template <int NF>
-__device__ inline void boundary_flux(const InstDesc &d, int i, const float hi[Q], const float gxi[Q], const float gyi[Q],
-                                     const Macro &mi, const float hei[Q], uint2 packed, float inva, float acc[Q]) {
+__device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const float gxi[Q], const float gyi[Q],
+                                     const Macro &mi, const float hei[Q], uint2 packed, const CellFaces<NF> &cf,
+                                     const GroupDev *lg, float acc[Q]) {
 #pragma unroll 1
     for (int k = 0; k < NF; k++) {
         const int ck = unpack16(k < 2 ? packed.x : packed.y, k & 1);
         if (ck >= 0 || ck < PAD_BELOW) continue;
-        float2 v0, v1;
-        if (NF == 3) {                          // the same corner offsets as the interior faces use
-            const float2 c0 = corner(d, 0, i), c1 = corner(d, 1, i);
-            const float2 c2 = make_float2(-(c0.x + c1.x), -(c0.y + c1.y));
-            v0 = k == 0 ? c0 : (k == 1 ? c1 : c2);
-            v1 = k == 0 ? c1 : (k == 1 ? c2 : c0);
-        } else {
-            v0 = corner(d, k, i);
-            v1 = corner(d, k + 1 == NF ? 0 : k + 1, i);
-        }
-        const float2 g = scaled_normal(v0, v1, inva);
+        const float2 v0 = pick2<NF>(cf.v, k), v1 = pick2<NF>(cf.v, k + 1 == NF ? 0 : k + 1);   // the interior faces' corners
+        const float2 g = scaled_normal(v0, v1, cf.inva);
         const float2 r = make_float2(0.5f * (v0.x + v1.x), 0.5f * (v0.y + v1.y));   // x_f - x_i
-        const GroupDev &gr = d.groups[-1 - ck];
+        const GroupDev gr = lg[-1 - ck];
         float bv[Q];
         boundary_value(gr, hi, mi, hei, g, d.ref, bv);
         const int kind = gr.kind;
@@ -519,7 +523,7 @@ __device__ inline void boundary_flux(const InstDesc &d, int i, const float hi[Q]
 template <int NF, int STORE, bool M0>
 __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, const float base[Q], bool sep_base,
                                             const int (&code)[NF], uint2 packed, const CellGeo<NF> &geo, const CellFaces<NF> &cf,
-                                            const float4 *own, const float4 *A) {
+                                            const float4 *own, const float4 *A, const GroupDev *lg) {
     float hi[Q], gxi[Q], gyi[Q];
     hi[0] = h0;
     rd_f(own, hi);
@@ -564,7 +568,7 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
             acc[a] = fmaf(en, up[a] ? own_v : nb_v, acc[a]);
         }
     }
-    if (bnd) boundary_flux<NF>(d, i, hi, gxi, gyi, mi, hei, packed, cf.inva, acc);
+    if (bnd) boundary_flux<NF>(d, hi, gxi, gyi, mi, hei, packed, cf, lg, acc);
 
     // The BGK source moves no mass and no momentum: f_eq carries the density and
     // momentum of f (Eqs. 3, 5).  In FP32 the rounding of f_eq (terms near 0.05,
@@ -654,6 +658,13 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     const int hs = h1s + h2s;
     const int hraw1 = ldg(hidx, tid < hs ? tid : 0);
     const int hraw2 = ldg(hidx, h1s + tid < hs ? h1s + tid : 0);
+    // the instance's boundary groups, staged in LDS for the boundary slots (read
+    // whole, without waiting for the group count)
+    __shared__ GroupDev lg[MAX_GROUPS];
+    constexpr int GW = MAX_GROUPS * (int)(sizeof(GroupDev) / sizeof(int));
+    const int *gsrc = reinterpret_cast<const int *>(d.groups);
+    const int gv0 = ldg(gsrc, tid < GW ? tid : 0);
+    const int gv1 = ldg(gsrc, T < GW && tid + T < GW ? tid + T : 0);
     const uint2 hl = ldg(d.halo_code, (size_t)tile * h1s + (tid < h1s ? tid : 0));
     const int c1 = tid < h1s ? hraw1 : -1;
     const int c2 = tid < h2s ? hraw2 : -1;
@@ -691,6 +702,8 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         hgeo.invert(hcode);
     }
     if (c2 >= 0) wr_f(B + tid * RB, f2);
+    if (tid < GW) reinterpret_cast<int *>(lg)[tid] = gv0;
+    if (T < GW && tid + T < GW) reinterpret_cast<int *>(lg)[tid + T] = gv1;
     for (int k = tid + T; k < h1s; k += T) {        // ring 1 larger than the tile
         const int c = ldg(hidx, k);
         if (c < 0) continue;
@@ -713,13 +726,13 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         if (valid) {
             hc[0] = h0;
             rd_f(A + tid * RA, hc);
-            gradient_staged<NF>(d, i, geo, hc, code, ln, A, B, a_end, gx, gy);
+            gradient_staged<NF>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy);
             wr_g(A + tid * RA, gx, gy);
         }
         if (c1 >= 0) {
             hc[0] = hf0;
             rd_f(A + (T + tid) * RA, hc);
-            gradient_staged<NF>(d, c1, hgeo, hc, hcode, hl, A, B, a_end, gx, gy);
+            gradient_staged<NF>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy);
             wr_g(A + (T + tid) * RA, gx, gy);
         }
         for (int k = tid + T; k < h1s; k += T) {
@@ -738,12 +751,12 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
                 hc[0] = t[0];
             }
             rd_f(A + (T + k) * RA, hc);
-            gradient_staged<NF>(d, c, g2, hc, cc, hl2, A, B, a_end, gx, gy);
+            gradient_staged<NF>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy);
             wr_g(A + (T + k) * RA, gx, gy);
         }
     }
     __syncthreads();
-    if (valid) tile_update<NF, STORE, M0>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A);
+    if (valid) tile_update<NF, STORE, M0>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A, lg);
 }
 
 // DIRECT: one instance whose unit b is tile b, its first-load values passed as
@@ -852,8 +865,8 @@ StageArgs stage_args(const InstDesc *descs_dev, const UnitTable &ut, int xcd_rem
 size_t stage_lds_limit() {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
-        return 65536;
-    return (size_t)v;
+        v = 65536;
+    return (size_t)v - sizeof(GroupDev) * MAX_GROUPS;   // less the staged group table
 }
 
 size_t stage_lds_bytes(int T, int h2max, int h1max) {
