@@ -423,17 +423,19 @@ __device__ inline void wr_g(float4 *rec, const float gx[Q], const float gy[Q]) {
 }
 
 // Boundary-slot terms of the gradient of cell c: phi_k is the wall / ghost
-// value (Eqs. 18-22) formed from the cell's own state.
+// value (Eqs. 18-22) formed from the cell's own state.  bm: the cell's boundary
+// slots as bits; each lane walks its own (so a wave makes as many passes as its
+// lane with the most boundary faces), in slot order.
 template <int NF>
 __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
-                                              uint2 packed, const GroupDev *lg, float gx[Q], float gy[Q]) {
+                                              uint2 packed, uint32_t bm, const GroupDev *lg, float gx[Q], float gy[Q]) {
     const Macro m = moments(hc, d.ref);
     float he[Q];
     heq(m.drho, m.rho, m.jx, m.jy, d.ref, he);
 #pragma unroll 1
-    for (int k = 0; k < NF; k++) {
+    for (uint32_t b = bm; b != 0u; b &= b - 1u) {
+        const int k = __builtin_ctz(b);
         const int ck = unpack16(k < 2 ? packed.x : packed.y, k & 1);
-        if (ck >= 0 || ck < PAD_BELOW) continue;
         const float2 dk = pick2<NF>(geo.dk, k);
         const float2 w = lsq_coef(dk, geo.m11, geo.m12, geo.m22);
         // the ghost values take only the direction of the face's outward normal (a
@@ -462,11 +464,11 @@ __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo
                                        const GroupDev *lg, float gx[Q], float gy[Q]) {
 #pragma unroll
     for (int a = 1; a < Q; a++) { gx[a] = 0.f; gy[a] = 0.f; }
-    bool bnd = false;
+    uint32_t bm = 0u;                     // boundary slots (padded slots have no face)
 #pragma unroll
     for (int k = 0; k < NF; k++) {
         if (code[k] < 0) {
-            bnd = bnd || code[k] >= PAD_BELOW;
+            if (code[k] >= PAD_BELOW) bm |= 1u << k;
             continue;
         }
         const float2 w = lsq_coef(geo.dk[k], geo.m11, geo.m12, geo.m22);
@@ -480,18 +482,19 @@ __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo
             gy[a] = fmaf(w.y, df, gy[a]);
         }
     }
-    if (bnd) boundary_gradient_body<NF>(d, geo, hc, packed, lg, gx, gy);
+    if (bm) boundary_gradient_body<NF>(d, geo, hc, packed, bm, lg, gx, gy);
 }
 
-// Boundary-face terms of the flux sum of tile cell i (Eqs. 18, 23-26).
+// Boundary-face terms of the flux sum of tile cell i (Eqs. 18, 23-26); bm as in
+// boundary_gradient_body.
 template <int NF>
 __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const float gxi[Q], const float gyi[Q],
-                                     const Macro &mi, const float hei[Q], uint2 packed, const CellFaces<NF> &cf,
-                                     const GroupDev *lg, float acc[Q]) {
+                                     const Macro &mi, const float hei[Q], uint2 packed, uint32_t bm,
+                                     const CellFaces<NF> &cf, const GroupDev *lg, float acc[Q]) {
 #pragma unroll 1
-    for (int k = 0; k < NF; k++) {
+    for (uint32_t b = bm; b != 0u; b &= b - 1u) {
+        const int k = __builtin_ctz(b);
         const int ck = unpack16(k < 2 ? packed.x : packed.y, k & 1);
-        if (ck >= 0 || ck < PAD_BELOW) continue;
         const float2 v0 = pick2<NF>(cf.v, k), v1 = pick2<NF>(cf.v, k + 1 == NF ? 0 : k + 1);   // the interior faces' corners
         const float2 g = scaled_normal(v0, v1, cf.inva);
         const float2 r = make_float2(0.5f * (v0.x + v1.x), 0.5f * (v0.y + v1.y));   // x_f - x_i
@@ -534,11 +537,11 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
     float acc[Q];
 #pragma unroll
     for (int a = 0; a < Q; a++) acc[a] = 0.f;
-    bool bnd = false;
+    uint32_t bm = 0u;                     // boundary faces (padded slots have no face)
 #pragma unroll
     for (int k = 0; k < NF; k++) {
         if (code[k] < 0) {
-            bnd = bnd || code[k] >= PAD_BELOW;
+            if (code[k] >= PAD_BELOW) bm |= 1u << k;
             continue;
         }
         const float2 v0 = cf.v[k], v1 = cf.v[k + 1 == NF ? 0 : k + 1];
@@ -568,7 +571,7 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
             acc[a] = fmaf(en, up[a] ? own_v : nb_v, acc[a]);
         }
     }
-    if (bnd) boundary_flux<NF>(d, hi, gxi, gyi, mi, hei, packed, cf, lg, acc);
+    if (bm) boundary_flux<NF>(d, hi, gxi, gyi, mi, hei, packed, bm, cf, lg, acc);
 
     // The BGK source moves no mass and no momentum: f_eq carries the density and
     // momentum of f (Eqs. 3, 5).  In FP32 the rounding of f_eq (terms near 0.05,
