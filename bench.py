@@ -53,7 +53,7 @@ def measured_traffic(schedule):
     """HBM bytes per launch of the stage kernel from the committed counter runs
     (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain copy of
     known size), or None when the kernel sources changed since they were taken
-    or the timed schedule is not the one they were taken with."""
+    or the timed schedule is not one they were taken with."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_tile_traffic.json")
     if not os.path.exists(path):
@@ -62,10 +62,11 @@ def measured_traffic(schedule):
     h = hashlib.sha256()
     for src in rec["sources"]:
         h.update(open(os.path.join(ROOT, src), "rb").read())
-    sched = [schedule["block"], int(schedule["xcd_remap"]), int(schedule["persistent"])]
-    if h.hexdigest() != rec["source_sha256"] or sched != rec["schedule"]:
+    if h.hexdigest() != rec["source_sha256"]:
         return None
-    return rec["bytes_per_launch"]
+    key = "%d,%d,%d" % (schedule["block"], int(schedule["xcd_remap"]), int(schedule["persistent"]))
+    ent = rec["per_schedule"].get(key)
+    return ent["bytes_per_launch"] if ent else None
 
 
 def events_time(stream, fn):
