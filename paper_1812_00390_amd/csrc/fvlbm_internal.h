@@ -182,14 +182,19 @@ size_t stage_lds_bytes(int T, int h2max, int h1max);
 // per-workgroup LDS (160 KiB on gfx950) less the kernel's static group table.
 size_t stage_lds_limit();
 // Same as a kernel node for a graph.
-// argbuf: argbuf[0] holds a StageArgs, argbuf[1..11] receive the argument pointers.
+// argbuf: argbuf[0] holds a StageArgs, argbuf[1..14] receive the argument pointers.
+// (Kernel argument order: the first fourteen dwords, hidx .. ux, are preloaded.)
 struct StageArgs {
-    const InstDesc *d;
-    const int2 *u;
-    int n, x, nA;
-    const void *src;
     const int *hidx;
-    int np, nc, h1, h2;
+    const void *src;
+    const uint2 *lnbr;
+    const float2 *dxy, *vxy;
+    int h12, np, nc, ux;      // h1s + 2^16 h2s; 2 n_units + XCD remap
+    const uint2 *hcode;
+    const void *base;
+    const InstDesc *d;
+    int nA;
+    const int2 *u;
     bool direct;
 };
 StageArgs stage_args(const InstDesc *descs_dev, const UnitTable &ut, int xcd_remap, int persistent, int h1max,

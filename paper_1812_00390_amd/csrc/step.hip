@@ -325,10 +325,6 @@ __device__ inline int unpack16(uint32_t w, int hi) { return (int)(int16_t)(hi ? 
 
 
 // corner k of cell c (offset from the centroid)
-__device__ inline float2 corner(const InstDesc &d, int k, int c) {
-    return ldo<float2>(plane(d.vxy, (size_t)d.np * 8, k), (uint32_t)c * 8u);
-}
-
 // v[k] for a wave-uniform k, from registers (no dynamic register indexing)
 template <int NF>
 __device__ __forceinline__ float2 pick2(const float2 (&v)[NF], int k) {
@@ -346,10 +342,10 @@ template <int NF>
 struct CellGeo {
     float2 dk[NF];
     float m11, m12, m22;
-    __device__ void load(const InstDesc &d, int c) {
+    __device__ void load(const float2 *dxy, size_t np, int c) {
         const uint32_t o8 = (uint32_t)c * 8u;
 #pragma unroll
-        for (int k = 0; k < NF; k++) dk[k] = ldo<float2>(plane(d.dxy, (size_t)d.np * 8, k), o8);
+        for (int k = 0; k < NF; k++) dk[k] = ldo<float2>(plane(dxy, np * 8, k), o8);
     }
     // padded slots (no face) do not enter M
     __device__ void invert(const int (&code)[NF]) {
@@ -377,9 +373,10 @@ template <int NF>
 struct CellFaces {
     float2 v[NF];
     float inva;
-    __device__ void load(const InstDesc &d, int c) {
+    __device__ void load(const float2 *vxy, size_t np, int c) {
+        const uint32_t o8 = (uint32_t)c * 8u;
 #pragma unroll
-        for (int k = 0; k < (NF == 3 ? 2 : NF); k++) v[k] = corner(d, k, c);
+        for (int k = 0; k < (NF == 3 ? 2 : NF); k++) v[k] = ldo<float2>(plane(vxy, np * 8, k), o8);
     }
     __device__ void finish() {
         if (NF == 3) v[2] = make_float2(-(v[0].x + v[1].x), -(v[0].y + v[1].y));
@@ -617,10 +614,12 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
     if (mode != 3) store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i);
 }
 
-// The values a tile's first loads depend on (kernel arguments for a single instance).
+// The values a tile's loads depend on (kernel arguments for a single instance).
 struct Hot {
-    const void *src;
+    const void *src, *base;
     const int *halo_idx;
+    const uint2 *halo_code, *lnbr;
+    const float2 *dxy, *vxy;
     int np, n_cells, h1s, h2s;
 };
 
@@ -646,6 +645,10 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     const int h1s = DIRECT ? hot.h1s : d.h1s, h2s = DIRECT ? hot.h2s : d.h2s;
     const int *halo_idx = DIRECT ? hot.halo_idx : d.halo_idx;
     const size_t np = (size_t)(DIRECT ? hot.np : d.np);
+    const uint2 *halo_code = DIRECT ? hot.halo_code : d.halo_code;
+    const uint2 *lnbr = DIRECT ? hot.lnbr : d.lnbr;
+    const float2 *dxy = DIRECT ? hot.dxy : d.dxy;
+    const float2 *vxy = DIRECT ? hot.vxy : d.vxy;
     const int tile = u.y;
     const int tid = threadIdx.x;
     const int i = tile * T + tid;
@@ -657,18 +660,11 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // Straight-line loads (indices clamped into range instead of branching, so
     // the compiler can wait on each load precisely): halo slot indices first,
     // then the own cell's data, then the halo values as soon as their indices
-    // return, then the update base.
+    // return; last the loads whose bases may arrive a level later (ring-1 codes,
+    // group table, update base).
     const int hs = h1s + h2s;
     const int hraw1 = ldg(hidx, tid < hs ? tid : 0);
     const int hraw2 = ldg(hidx, h1s + tid < hs ? h1s + tid : 0);
-    // the instance's boundary groups, staged in LDS for the boundary slots (read
-    // whole, without waiting for the group count)
-    __shared__ GroupDev lg[MAX_GROUPS];
-    constexpr int GW = MAX_GROUPS * (int)(sizeof(GroupDev) / sizeof(int));
-    const int *gsrc = reinterpret_cast<const int *>(d.groups);
-    const int gv0 = ldg(gsrc, tid < GW ? tid : 0);
-    const int gv1 = ldg(gsrc, T < GW && tid + T < GW ? tid + T : 0);
-    const uint2 hl = ldg(d.halo_code, (size_t)tile * h1s + (tid < h1s ? tid : 0));
     const int c1 = tid < h1s ? hraw1 : -1;
     const int c2 = tid < h2s ? hraw2 : -1;
 
@@ -678,19 +674,28 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     CellFaces<NF> cf;
     const int ic = valid ? i : 0;
     load_cell<STORE>(src, np, ic, f, d.ref);
-    const uint2 ln = ldo<uint2>(d.lnbr, (uint32_t)ic * 8u);
-    geo.load(d, ic);
-    cf.load(d, ic);
+    const uint2 ln = ldo<uint2>(lnbr, (uint32_t)ic * 8u);
+    geo.load(dxy, np, ic);
+    cf.load(vxy, np, ic);
     int hcode[NF];
     float hf0 = 0.f, f1[Q], f2[Q];
     CellGeo<NF> hgeo;
     {
         load_cell<STORE>(src, np, c1 >= 0 ? c1 : 0, f1, d.ref);
-        hgeo.load(d, c1 >= 0 ? c1 : 0);
+        hgeo.load(dxy, np, c1 >= 0 ? c1 : 0);
         load_cell<STORE>(src, np, c2 >= 0 ? c2 : 0, f2, d.ref, 1);
     }
-    const bool sep_base = (M0 || d.mode == 0) && d.base != src;   // (descriptor fields: after the first loads are out)
-    if (sep_base) load_cell<STORE>(d.base, np, ic, base, d.ref);
+    const uint2 hl = ldg(halo_code, (size_t)tile * h1s + (tid < h1s ? tid : 0));
+    // the instance's boundary groups, staged in LDS for the boundary slots (read
+    // whole, without waiting for the group count)
+    __shared__ GroupDev lg[MAX_GROUPS];
+    constexpr int GW = MAX_GROUPS * (int)(sizeof(GroupDev) / sizeof(int));
+    const int *gsrc = reinterpret_cast<const int *>(d.groups);
+    const int gv0 = ldg(gsrc, tid < GW ? tid : 0);
+    const int gv1 = ldg(gsrc, T < GW && tid + T < GW ? tid + T : 0);
+    const void *basep = DIRECT ? hot.base : d.base;
+    const bool sep_base = (M0 || d.mode == 0) && basep != src;
+    if (sep_base) load_cell<STORE>(basep, np, ic, base, d.ref);
     h0 = f[0];
 #pragma unroll
     for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
@@ -741,12 +746,12 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         for (int k = tid + T; k < h1s; k += T) {
             const int c = ldg(hidx, k);
             if (c < 0) continue;
-            const uint2 hl2 = ldg(d.halo_code, (size_t)tile * h1s + k);
+            const uint2 hl2 = ldg(halo_code, (size_t)tile * h1s + k);
             int cc[NF];
 #pragma unroll
             for (int s = 0; s < NF; s++) cc[s] = unpack16(s < 2 ? hl2.x : hl2.y, s & 1);
             CellGeo<NF> g2;
-            g2.load(d, c);
+            g2.load(dxy, np, c);
             g2.invert(cc);
             {
                 float t[Q];
@@ -762,22 +767,27 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     if (valid) tile_update<NF, STORE, M0>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A, lg);
 }
 
-// DIRECT: one instance whose unit b is tile b, its first-load values passed as
-// arguments (they reach scalar registers with the wave); otherwise units are
-// read from the table and everything from the descriptors.
+// DIRECT: one instance whose unit b is tile b, the bases and sizes its loads
+// need passed as arguments; the first fourteen dwords (up to units_x) reach
+// scalar registers with the wave, so no descriptor or argument load precedes
+// the first loads (the ring-1 codes and the base are read one level later, as
+// the halo values are); otherwise units are read from the table and everything
+// from the descriptors.  units_x = 2 n_units + (XCD remap on), h12 = h1s + 2^16 h2s.
 // M0: the stage is a base + coef RHS update (Euler, RK stages), fixed at compile
 // time, so the update carries no mode tests; otherwise the mode is read from the
 // descriptor (Adams-Bashforth, RHS output).
 // (Arguments in the order the kernel needs them: the first sixteen dwords arrive in
 // scalar registers.)
 template <int NF, int STORE, int T, bool DIRECT, bool M0>
-__global__ void __launch_bounds__(T) k_tile(const int *hot_halo_idx, const void *hot_src, int hot_h1s, int hot_h2s,
-                                            int hot_np, int hot_n_cells, int n_units, int xcd_remap,
+__global__ void __launch_bounds__(T) k_tile(const int *hot_halo_idx, const void *hot_src, const uint2 *hot_lnbr,
+                                            const float2 *hot_dxy, const float2 *hot_vxy, int hot_h12, int hot_np,
+                                            int hot_n_cells, int units_x, const uint2 *hot_halo_code, const void *hot_base,
                                             const InstDesc *__restrict__ descs, int nA,
                                             const int2 *__restrict__ units) {
     extern __shared__ float4 lds4[];
-    const int ub = remap_block(blockIdx.x, n_units, xcd_remap);
-    const Hot hot{hot_src, hot_halo_idx, hot_np, hot_n_cells, hot_h1s, hot_h2s};
+    const int ub = remap_block(blockIdx.x, units_x >> 1, units_x & 1);
+    const Hot hot{hot_src, hot_base, hot_halo_idx, hot_halo_code, hot_lnbr, hot_dxy, hot_vxy,
+                  hot_np, hot_n_cells, hot_h12 & 0xffff, hot_h12 >> 16};
     tile_body<NF, STORE, T, DIRECT, M0>(descs, (DIRECT || !units) ? make_int2(0, ub) : units[ub], hot, lds4, lds4 + nA * RA);
 }
 
@@ -785,11 +795,13 @@ __global__ void __launch_bounds__(T) k_tile(const int *hot_halo_idx, const void 
 // Persistent form: a grid sized to the resident capacity walks the unit list
 // (a multiple of 8 blocks, so each block stays on one XCD's range of tiles).
 template <int NF, int STORE, int T, bool M0>
-__global__ void __launch_bounds__(T) k_tile_persistent(const int *, const void *, int, int, int, int, int n_units,
-                                                       int xcd_remap, const InstDesc *__restrict__ descs, int nA,
+__global__ void __launch_bounds__(T) k_tile_persistent(const int *, const void *, const uint2 *, const float2 *,
+                                                       const float2 *, int, int, int, int units_x, const uint2 *,
+                                                       const void *, const InstDesc *__restrict__ descs, int nA,
                                                        const int2 *__restrict__ units) {
     extern __shared__ float4 lds4[];
     const Hot hot{};
+    const int n_units = units_x >> 1, xcd_remap = units_x & 1;
     for (int b = blockIdx.x; b < n_units; b += gridDim.x) {
         const int ub = remap_block(b, n_units, xcd_remap);
         tile_body<NF, STORE, T, false, M0>(descs, units ? units[ub] : make_int2(0, ub), hot, lds4, lds4 + nA * RA);
@@ -850,17 +862,20 @@ StageArgs stage_args(const InstDesc *descs_dev, const UnitTable &ut, int xcd_rem
     StageArgs a{};
     a.d = descs_dev;
     a.u = ut.units;
-    a.n = ut.n_units;
-    a.x = xcd_remap;
+    a.ux = 2 * ut.n_units + (xcd_remap ? 1 : 0);
     a.nA = ut.block + h1max;
     a.direct = ut.direct && host_desc && !persistent;
     if (a.direct) {
         a.src = host_desc->src;
+        a.base = host_desc->base;
         a.hidx = host_desc->halo_idx;
+        a.hcode = host_desc->halo_code;
+        a.lnbr = host_desc->lnbr;
+        a.dxy = host_desc->dxy;
+        a.vxy = host_desc->vxy;
         a.np = host_desc->np;
         a.nc = host_desc->n_cells;
-        a.h1 = host_desc->h1s;
-        a.h2 = host_desc->h2s;
+        a.h12 = host_desc->h1s | (host_desc->h2s << 16);
     }
     return a;
 }
@@ -882,7 +897,8 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
     if (ut.n_units == 0) return hipSuccess;
     if (!mode0) persistent = 0;
     StageArgs a = stage_args(descs_dev, ut, xcd_remap, persistent, h1max, host_desc);
-    void *args[] = {&a.hidx, &a.src, &a.h1, &a.h2, &a.np, &a.nc, &a.n, &a.x, &a.d, &a.nA, &a.u};
+    void *args[] = {&a.hidx, &a.src, &a.lnbr, &a.dxy, &a.vxy, &a.h12, &a.np, &a.nc, &a.ux, &a.hcode, &a.base,
+                    &a.d, &a.nA, &a.u};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
     const void *fn_ptr = pick(nf, storage, ut.block, persistent, a.direct, mode0);
     if (lds > 65536) {
@@ -902,8 +918,9 @@ hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode
     StageArgs *a = reinterpret_cast<StageArgs *>(argbuf[0]);
     *a = stage_args(descs_dev, ut, xcd_remap, persistent, h1max, host_desc);
     void **kp = argbuf + 1;
-    kp[0] = &a->hidx; kp[1] = &a->src; kp[2] = &a->h1; kp[3] = &a->h2; kp[4] = &a->np; kp[5] = &a->nc;
-    kp[6] = &a->n; kp[7] = &a->x; kp[8] = &a->d; kp[9] = &a->nA; kp[10] = &a->u;
+    kp[0] = &a->hidx; kp[1] = &a->src; kp[2] = &a->lnbr; kp[3] = &a->dxy; kp[4] = &a->vxy; kp[5] = &a->h12;
+    kp[6] = &a->np; kp[7] = &a->nc; kp[8] = &a->ux; kp[9] = &a->hcode; kp[10] = &a->base; kp[11] = &a->d;
+    kp[12] = &a->nA; kp[13] = &a->u;
     hipKernelNodeParams p{};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
     p.func = const_cast<void *>(pick(nf, storage, ut.block, persistent, a->direct, mode0));
