@@ -422,10 +422,13 @@ __device__ inline void wr_g(float4 *rec, const float gx[Q], const float gy[Q]) {
 // Boundary-slot terms of the gradient of cell c: phi_k is the wall / ghost
 // value (Eqs. 18-22) formed from the cell's own state.  bm: the cell's boundary
 // slots as bits; each lane walks its own (so a wave makes as many passes as its
-// lane with the most boundary faces), in slot order.
-template <int NF>
+// lane with the most boundary faces), in slot order.  SAVE: the values of the
+// first boundary slot are kept (save, save_k) for the cell's boundary flux, which
+// forms the same values from the same state.
+template <int NF, bool SAVE>
 __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
-                                              uint2 packed, uint32_t bm, const GroupDev *lg, float gx[Q], float gy[Q]) {
+                                              uint2 packed, uint32_t bm, const GroupDev *lg, float gx[Q], float gy[Q],
+                                              float save[Q], int &save_k) {
     const Macro m = moments(hc, d.ref);
     float he[Q];
     heq(m.drho, m.rho, m.jx, m.jy, d.ref, he);
@@ -442,6 +445,11 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
         const GroupDev g = lg[-1 - ck];
         float phi[Q];
         boundary_value(g, hc, m, he, gn, d.ref, phi);
+        if (SAVE && save_k < 0) {
+            save_k = k;
+#pragma unroll
+            for (int a = 1; a < Q; a++) save[a] = phi[a];
+        }
 #pragma unroll
         for (int a = 1; a < Q; a++) {
             const float df = phi[a] - hc[a];
@@ -455,10 +463,10 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
 // phi_k the staged value of local cell code[k] (interior slots first, then
 // boundary slots).  Local indices below `a_end` are region-A records, the rest
 // region B.
-template <int NF>
+template <int NF, bool SAVE>
 __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                        const int (&code)[NF], uint2 packed, const float4 *A, const float4 *B, int a_end,
-                                       const GroupDev *lg, float gx[Q], float gy[Q]) {
+                                       const GroupDev *lg, float gx[Q], float gy[Q], float save[Q], int &save_k) {
 #pragma unroll
     for (int a = 1; a < Q; a++) { gx[a] = 0.f; gy[a] = 0.f; }
     uint32_t bm = 0u;                     // boundary slots (padded slots have no face)
@@ -479,15 +487,16 @@ __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo
             gy[a] = fmaf(w.y, df, gy[a]);
         }
     }
-    if (bm) boundary_gradient_body<NF>(d, geo, hc, packed, bm, lg, gx, gy);
+    if (bm) boundary_gradient_body<NF, SAVE>(d, geo, hc, packed, bm, lg, gx, gy, save, save_k);
 }
 
 // Boundary-face terms of the flux sum of tile cell i (Eqs. 18, 23-26); bm as in
-// boundary_gradient_body.
+// boundary_gradient_body; the values of slot save_k were formed in phase 2.
 template <int NF>
 __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const float gxi[Q], const float gyi[Q],
                                      const Macro &mi, const float hei[Q], uint2 packed, uint32_t bm,
-                                     const CellFaces<NF> &cf, const GroupDev *lg, float acc[Q]) {
+                                     const CellFaces<NF> &cf, const GroupDev *lg, const float save[Q], int save_k,
+                                     float acc[Q]) {
 #pragma unroll 1
     for (uint32_t b = bm; b != 0u; b &= b - 1u) {
         const int k = __builtin_ctz(b);
@@ -497,7 +506,12 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
         const float2 r = make_float2(0.5f * (v0.x + v1.x), 0.5f * (v0.y + v1.y));   // x_f - x_i
         const GroupDev gr = lg[-1 - ck];
         float bv[Q];
-        boundary_value(gr, hi, mi, hei, g, d.ref, bv);
+        if (k == save_k) {
+#pragma unroll
+            for (int a = 1; a < Q; a++) bv[a] = save[a];
+        } else {
+            boundary_value(gr, hi, mi, hei, g, d.ref, bv);
+        }
         const int kind = gr.kind;
         const bool upwind = kind == FVLBM_BC_INLET || (kind == FVLBM_BC_OUTLET && gr.internal);
 #pragma unroll
@@ -523,7 +537,8 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
 template <int NF, int STORE, bool M0>
 __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, const float base[Q], bool sep_base,
                                             const int (&code)[NF], uint2 packed, const CellGeo<NF> &geo, const CellFaces<NF> &cf,
-                                            const float4 *own, const float4 *A, const GroupDev *lg) {
+                                            const float4 *own, const float4 *A, const GroupDev *lg,
+                                            const float bsave[Q], int bsave_k) {
     float hi[Q], gxi[Q], gyi[Q];
     hi[0] = h0;
     rd_f(own, hi);
@@ -568,7 +583,7 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
             acc[a] = fmaf(en, up[a] ? own_v : nb_v, acc[a]);
         }
     }
-    if (bm) boundary_flux<NF>(d, hi, gxi, gyi, mi, hei, packed, bm, cf, lg, acc);
+    if (bm) boundary_flux<NF>(d, hi, gxi, gyi, mi, hei, packed, bm, cf, lg, bsave, bsave_k, acc);
 
     // The BGK source moves no mass and no momentum: f_eq carries the density and
     // momentum of f (Eqs. 3, 5).  In FP32 the rounding of f_eq (terms near 0.05,
@@ -729,18 +744,21 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     __syncthreads();
 
     // ---- phase 2
+    float bsave[Q];                                // the cell's first boundary values, for phase 3
+    int bsave_k = -1;
     {
         float hc[Q], gx[Q], gy[Q];
+        int no_k = 0;
         if (valid) {
             hc[0] = h0;
             rd_f(A + tid * RA, hc);
-            gradient_staged<NF>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy);
+            gradient_staged<NF, true>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, bsave, bsave_k);
             wr_g(A + tid * RA, gx, gy);
         }
         if (c1 >= 0) {
             hc[0] = hf0;
             rd_f(A + (T + tid) * RA, hc);
-            gradient_staged<NF>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy);
+            gradient_staged<NF, false>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy, hc, no_k);
             wr_g(A + (T + tid) * RA, gx, gy);
         }
         for (int k = tid + T; k < h1s; k += T) {
@@ -759,12 +777,12 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
                 hc[0] = t[0];
             }
             rd_f(A + (T + k) * RA, hc);
-            gradient_staged<NF>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy);
+            gradient_staged<NF, false>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy, hc, no_k);
             wr_g(A + (T + k) * RA, gx, gy);
         }
     }
     __syncthreads();
-    if (valid) tile_update<NF, STORE, M0>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A, lg);
+    if (valid) tile_update<NF, STORE, M0>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A, lg, bsave, bsave_k);
 }
 
 // DIRECT: one instance whose unit b is tile b, the bases and sizes its loads
