@@ -220,7 +220,7 @@ def main():
     schedule = None
     if args.schedule:
         b, x, p = (int(v) for v in args.schedule.split(","))
-        schedule = (b, bool(x), bool(p))
+        schedule = (b, bool(x), int(p))
     rec = {}
     if args.only in ("all", "headline"):
         inst = W.cavity20k()

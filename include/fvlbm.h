@@ -191,10 +191,14 @@ void fvlbm_batch_destroy(fvlbm_batch *b);
 
 /* Launch schedule: tile size in cells (one workgroup per tile: 64, 128, 256 or
  * 512), whether tiles are renumbered so that each XCD walks one contiguous
- * range of tiles (neighbouring tiles then share that XCD's L2), and whether a
- * persistent grid sized to the resident capacity walks the tile list instead
- * of one workgroup per tile.  A schedule never changes the per-cell
- * arithmetic: results are bitwise identical under every schedule.
+ * range of tiles (neighbouring tiles then share that XCD's L2), and the launch
+ * form `persistent`: 0 one workgroup per tile; 1 a persistent grid sized to
+ * the resident capacity walks the tile list; 2 one workgroup per tile with one
+ * more wave that loads the tile's halo and forms the ring-1 gradients beside
+ * the tile's own (single solvers, tiles of 64 or 128 cells, Euler and RK
+ * stages; elsewhere it acts as 0).  A batch takes 0 or 1.  A schedule never
+ * changes the per-cell arithmetic: results are bitwise identical under every
+ * schedule.
  * Errors: FVLBM_E_ARG (unsupported tile size, or tile plus halo do not fit
  * the LDS a workgroup may use: 160 KiB on gfx950). */
 fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap, int32_t persistent);

@@ -616,7 +616,7 @@ fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_rema
     if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "stream synchronize failed");
     s->sched.block = block;
     s->sched.xcd_remap = xcd_remap ? 1 : 0;
-    s->sched.persistent = persistent ? 1 : 0;
+    s->sched.persistent = persistent == 2 ? 2 : (persistent ? 1 : 0);
     s->tiles = tt;
     free_graphs(s->graphs);
     st = make_units({{0, s->mesh->dev.n_cells}}, block, s->ut);
@@ -710,7 +710,7 @@ fvlbm_status fvlbm_batch_set_schedule(fvlbm_batch *b, int32_t block, int32_t xcd
     Schedule old = b->sched;
     b->sched.block = block;
     b->sched.xcd_remap = xcd_remap ? 1 : 0;
-    b->sched.persistent = persistent ? 1 : 0;
+    b->sched.persistent = (persistent && persistent != 2) ? 1 : 0;   // (the ring form is for single solvers)
     fvlbm_status st = batch_build(b);
     if (st != FVLBM_OK) {
         b->sched = old;
@@ -888,7 +888,7 @@ fvlbm_status fvlbm_autotune(fvlbm_solver *s, int32_t trial_steps, double *best_m
     double best_t = 1e300;
     for (int T : TUNE_BLOCKS)
         for (int x = 0; x < 2; x++)
-            for (int ps = 0; ps < 2; ps++) {
+            for (int ps = 0; ps < (T <= 128 ? 3 : 2); ps++) {
                 if (fvlbm_set_schedule(s, T, x, ps) != FVLBM_OK) continue;
                 double t = time_steps(s->stream, trial_steps, [&](int n) { return enqueue_steps(s, n); });
                 if (t > 0 && t < best_t) { best_t = t; best = s->sched; }

@@ -169,6 +169,9 @@ struct UnitTable {
 // Launch one RHS-evaluation stage over all units (one unit = one tile of
 // ut.block cells).  nf: 3 or 4; storage FVLBM_STORE_*; h2max, h1max: the
 // largest ring-2 and ring-1 slot counts over the launch's instances (LDS size).
+// persistent: 0 one workgroup per tile, 1 a resident-sized grid walking the
+// units, 2 one workgroup per tile with one more wave for the halo slots (used by
+// a single instance's mode-0 stages with tiles of 64 or 128 cells, else as 0).
 // mode0: the stage is a base + coef RHS update (descriptor mode 0: Euler, RK
 // stages), which runs a kernel compiled for it; other modes run one block per
 // unit whatever `persistent` says.

@@ -649,7 +649,7 @@ struct Hot {
 //            update, store.
 // Dynamic LDS: nA = T + (largest ring-1 slot count) region-A records, then
 // region-B records for the largest ring-2 slot count (sized by the launcher).
-template <int NF, int STORE, int T, bool DIRECT, bool M0>
+template <int NF, int STORE, int T, bool DIRECT, bool M0, bool RING>
 __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, int2 u, const Hot &hot, float4 *A,
                                           float4 *B) {
     const InstDesc &d = descs[u.x];
@@ -666,8 +666,14 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     const float2 *vxy = DIRECT ? hot.vxy : d.vxy;
     const int tile = u.y;
     const int tid = threadIdx.x;
+    // RING: threads [0, T) own the tile's cells and one more wave, [T, T + 64),
+    // owns the halo slots, so halo loads and ring-1 gradients run beside the
+    // tile's own; otherwise thread t owns tile cell t and halo slot t.
+    constexpr int RS = RING ? 64 : T;                 // halo slots per pass
+    const bool ownw = !RING || __builtin_amdgcn_readfirstlane(tid) < T;   // (wave-uniform)
+    const int rj = RING ? tid - T : tid;              // this thread's halo slot (< 0: none)
     const int i = tile * T + tid;
-    const bool valid = i < n_cells;
+    const bool valid = ownw && i < n_cells;
     const int a_end = T + h1s;                     // local indices below this are region A
     const int *hidx = halo_idx + (size_t)tile * (size_t)(h1s + h2s);
 
@@ -678,63 +684,73 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // return; last the loads whose bases may arrive a level later (ring-1 codes,
     // group table, update base).
     const int hs = h1s + h2s;
-    const int hraw1 = ldg(hidx, tid < hs ? tid : 0);
-    const int hraw2 = ldg(hidx, h1s + tid < hs ? h1s + tid : 0);
-    const int c1 = tid < h1s ? hraw1 : -1;
-    const int c2 = tid < h2s ? hraw2 : -1;
-
+    const bool rin = rj >= 0;
     float h0 = 0.f, base[Q], f[Q];
     int code[NF];
     CellGeo<NF> geo;
     CellFaces<NF> cf;
+    uint2 ln = make_uint2(0u, 0u);
+    int hraw1 = -1, hraw2 = -1;
+    if (!RING)
+        hraw1 = ldg(hidx, tid < hs ? tid : 0), hraw2 = ldg(hidx, h1s + tid < hs ? h1s + tid : 0);
     const int ic = valid ? i : 0;
-    load_cell<STORE>(src, np, ic, f, d.ref);
-    const uint2 ln = ldo<uint2>(lnbr, (uint32_t)ic * 8u);
-    geo.load(dxy, np, ic);
-    cf.load(vxy, np, ic);
+    if (ownw) {
+        load_cell<STORE>(src, np, ic, f, d.ref);
+        ln = ldo<uint2>(lnbr, (uint32_t)ic * 8u);
+        geo.load(dxy, np, ic);
+        cf.load(vxy, np, ic);
+    }
+    if (RING && !ownw)
+        hraw1 = ldg(hidx, rj < hs ? rj : 0), hraw2 = ldg(hidx, h1s + rj < hs ? h1s + rj : 0);
+    const int c1 = rin && rj < h1s ? hraw1 : -1;
+    const int c2 = rin && rj < h2s ? hraw2 : -1;
     int hcode[NF];
     float hf0 = 0.f, f1[Q], f2[Q];
     CellGeo<NF> hgeo;
-    {
+    uint2 hl = make_uint2(0u, 0u);
+    if (!RING || !ownw) {
         load_cell<STORE>(src, np, c1 >= 0 ? c1 : 0, f1, d.ref);
         hgeo.load(dxy, np, c1 >= 0 ? c1 : 0);
         load_cell<STORE>(src, np, c2 >= 0 ? c2 : 0, f2, d.ref, 1);
+        hl = ldg(halo_code, (size_t)tile * h1s + (rin && rj < h1s ? rj : 0));
     }
-    const uint2 hl = ldg(halo_code, (size_t)tile * h1s + (tid < h1s ? tid : 0));
     // the instance's boundary groups, staged in LDS for the boundary slots (read
     // whole, without waiting for the group count)
     __shared__ GroupDev lg[MAX_GROUPS];
+    constexpr int BS = T + (RING ? 64 : 0);           // threads per block
     constexpr int GW = MAX_GROUPS * (int)(sizeof(GroupDev) / sizeof(int));
     const int *gsrc = reinterpret_cast<const int *>(d.groups);
     const int gv0 = ldg(gsrc, tid < GW ? tid : 0);
-    const int gv1 = ldg(gsrc, T < GW && tid + T < GW ? tid + T : 0);
+    const int gv1 = ldg(gsrc, BS < GW && tid + BS < GW ? tid + BS : 0);
     const void *basep = DIRECT ? hot.base : d.base;
     const bool sep_base = (M0 || d.mode == 0) && basep != src;
-    if (sep_base) load_cell<STORE>(basep, np, ic, base, d.ref);
-    h0 = f[0];
+    if (ownw) {
+        if (sep_base) load_cell<STORE>(basep, np, ic, base, d.ref);
+        h0 = f[0];
 #pragma unroll
-    for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
-    geo.invert(code);
-    cf.finish();
+        for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
+        geo.invert(code);
+        cf.finish();
+    }
     if (valid) wr_f(A + tid * RA, f);
     if (c1 >= 0) {
         hf0 = f1[0];
-        wr_f(A + (T + tid) * RA, f1);
+        wr_f(A + (T + rj) * RA, f1);
 #pragma unroll
         for (int k = 0; k < NF; k++) hcode[k] = unpack16(k < 2 ? hl.x : hl.y, k & 1);
         hgeo.invert(hcode);
     }
-    if (c2 >= 0) wr_f(B + tid * RB, f2);
+    if (c2 >= 0) wr_f(B + rj * RB, f2);
     if (tid < GW) reinterpret_cast<int *>(lg)[tid] = gv0;
-    if (T < GW && tid + T < GW) reinterpret_cast<int *>(lg)[tid + T] = gv1;
-    for (int k = tid + T; k < h1s; k += T) {        // ring 1 larger than the tile
+    if (BS < GW && tid + BS < GW) reinterpret_cast<int *>(lg)[tid + BS] = gv1;
+    for (int k = rin ? rj + RS : h1s; k < h1s; k += RS) {   // ring 1 larger than a pass
         const int c = ldg(hidx, k);
         if (c < 0) continue;
         float g[Q];
         load_cell<STORE>(src, np, c, g, d.ref, 1);
         wr_f(A + (T + k) * RA, g);
     }
-    for (int k = tid + T; k < h2s; k += T) {        // ring 2 larger than the tile
+    for (int k = rin ? rj + RS : h2s; k < h2s; k += RS) {   // ring 2 larger than a pass
         const int c = ldg(hidx, h1s + k);
         if (c < 0) continue;
         float g[Q];
@@ -757,11 +773,11 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         }
         if (c1 >= 0) {
             hc[0] = hf0;
-            rd_f(A + (T + tid) * RA, hc);
+            rd_f(A + (T + rj) * RA, hc);
             gradient_staged<NF, false>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy, hc, no_k);
-            wr_g(A + (T + tid) * RA, gx, gy);
+            wr_g(A + (T + rj) * RA, gx, gy);
         }
-        for (int k = tid + T; k < h1s; k += T) {
+        for (int k = rin ? rj + RS : h1s; k < h1s; k += RS) {
             const int c = ldg(hidx, k);
             if (c < 0) continue;
             const uint2 hl2 = ldg(halo_code, (size_t)tile * h1s + k);
@@ -796,8 +812,8 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
 // descriptor (Adams-Bashforth, RHS output).
 // (Arguments in the order the kernel needs them: the first sixteen dwords arrive in
 // scalar registers.)
-template <int NF, int STORE, int T, bool DIRECT, bool M0>
-__global__ void __launch_bounds__(T) k_tile(const int *hot_halo_idx, const void *hot_src, const uint2 *hot_lnbr,
+template <int NF, int STORE, int T, bool DIRECT, bool M0, bool RING>
+__global__ void __launch_bounds__(T + (RING ? 64 : 0)) k_tile(const int *hot_halo_idx, const void *hot_src, const uint2 *hot_lnbr,
                                             const float2 *hot_dxy, const float2 *hot_vxy, int hot_h12, int hot_np,
                                             int hot_n_cells, int units_x, const uint2 *hot_halo_code, const void *hot_base,
                                             const InstDesc *__restrict__ descs, int nA,
@@ -806,7 +822,8 @@ __global__ void __launch_bounds__(T) k_tile(const int *hot_halo_idx, const void 
     const int ub = remap_block(blockIdx.x, units_x >> 1, units_x & 1);
     const Hot hot{hot_src, hot_base, hot_halo_idx, hot_halo_code, hot_lnbr, hot_dxy, hot_vxy,
                   hot_np, hot_n_cells, hot_h12 & 0xffff, hot_h12 >> 16};
-    tile_body<NF, STORE, T, DIRECT, M0>(descs, (DIRECT || !units) ? make_int2(0, ub) : units[ub], hot, lds4, lds4 + nA * RA);
+    tile_body<NF, STORE, T, DIRECT, M0, RING>(descs, (DIRECT || !units) ? make_int2(0, ub) : units[ub], hot, lds4,
+                                             lds4 + nA * RA);
 }
 
 // (units null: a single instance whose unit b is tile b.)
@@ -822,42 +839,44 @@ __global__ void __launch_bounds__(T) k_tile_persistent(const int *, const void *
     const int n_units = units_x >> 1, xcd_remap = units_x & 1;
     for (int b = blockIdx.x; b < n_units; b += gridDim.x) {
         const int ub = remap_block(b, n_units, xcd_remap);
-        tile_body<NF, STORE, T, false, M0>(descs, units ? units[ub] : make_int2(0, ub), hot, lds4, lds4 + nA * RA);
+        tile_body<NF, STORE, T, false, M0, false>(descs, units ? units[ub] : make_int2(0, ub), hot, lds4, lds4 + nA * RA);
         __syncthreads();             // the next unit reuses the LDS records
     }
 }
 
 template <int NF, int STORE, int T>
-const void *fn(bool persistent, bool direct, bool m0) {
+const void *fn(bool persistent, bool direct, bool m0, bool ring) {
     if (!m0)    // runtime mode: one block per unit (the launchers never ask for persistence here)
-        return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, false>)
-                      : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false, false>);
+        return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, false, false>)
+                      : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false, false, false>);
     if (persistent) return reinterpret_cast<const void *>(&k_tile_persistent<NF, STORE, T, true>);
-    return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, true>)
-                  : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false, true>);
+    if constexpr (T <= 128)   // a ring wave: single instance, mode 0, tiles of 64 or 128 cells
+        if (ring && direct) return reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, true, true>);
+    return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, true, false>)
+                  : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false, true, false>);
 }
 
 template <int NF, int STORE>
-const void *pick_t(int T, bool persistent, bool direct, bool m0) {
+const void *pick_t(int T, bool persistent, bool direct, bool m0, bool ring) {
     switch (T) {
-    case 64: return fn<NF, STORE, 64>(persistent, direct, m0);
-    case 128: return fn<NF, STORE, 128>(persistent, direct, m0);
-    case 256: return fn<NF, STORE, 256>(persistent, direct, m0);
-    default: return fn<NF, STORE, 512>(persistent, direct, m0);
+    case 64: return fn<NF, STORE, 64>(persistent, direct, m0, ring);
+    case 128: return fn<NF, STORE, 128>(persistent, direct, m0, ring);
+    case 256: return fn<NF, STORE, 256>(persistent, direct, m0, ring);
+    default: return fn<NF, STORE, 512>(persistent, direct, m0, ring);
     }
 }
 
-const void *pick(int nf, int storage, int T, bool persistent, bool direct, bool m0) {
+const void *pick(int nf, int storage, int T, bool persistent, bool direct, bool m0, bool ring) {
     if (nf == 3) {
-        if (storage == FVLBM_STORE_FP32) return pick_t<3, FVLBM_STORE_FP32>(T, persistent, direct, m0);
-        if (storage == FVLBM_STORE_FP32_DEV) return pick_t<3, FVLBM_STORE_FP32_DEV>(T, persistent, direct, m0);
-        if (storage == FVLBM_STORE_I16_DEV) return pick_t<3, FVLBM_STORE_I16_DEV>(T, persistent, direct, m0);
-        return pick_t<3, FVLBM_STORE_FP16_DEV>(T, persistent, direct, m0);
+        if (storage == FVLBM_STORE_FP32) return pick_t<3, FVLBM_STORE_FP32>(T, persistent, direct, m0, ring);
+        if (storage == FVLBM_STORE_FP32_DEV) return pick_t<3, FVLBM_STORE_FP32_DEV>(T, persistent, direct, m0, ring);
+        if (storage == FVLBM_STORE_I16_DEV) return pick_t<3, FVLBM_STORE_I16_DEV>(T, persistent, direct, m0, ring);
+        return pick_t<3, FVLBM_STORE_FP16_DEV>(T, persistent, direct, m0, ring);
     }
-    if (storage == FVLBM_STORE_FP32) return pick_t<4, FVLBM_STORE_FP32>(T, persistent, direct, m0);
-    if (storage == FVLBM_STORE_FP32_DEV) return pick_t<4, FVLBM_STORE_FP32_DEV>(T, persistent, direct, m0);
-    if (storage == FVLBM_STORE_I16_DEV) return pick_t<4, FVLBM_STORE_I16_DEV>(T, persistent, direct, m0);
-    return pick_t<4, FVLBM_STORE_FP16_DEV>(T, persistent, direct, m0);
+    if (storage == FVLBM_STORE_FP32) return pick_t<4, FVLBM_STORE_FP32>(T, persistent, direct, m0, ring);
+    if (storage == FVLBM_STORE_FP32_DEV) return pick_t<4, FVLBM_STORE_FP32_DEV>(T, persistent, direct, m0, ring);
+    if (storage == FVLBM_STORE_I16_DEV) return pick_t<4, FVLBM_STORE_I16_DEV>(T, persistent, direct, m0, ring);
+    return pick_t<4, FVLBM_STORE_FP16_DEV>(T, persistent, direct, m0, ring);
 }
 
 // Grid of a launch: one block per unit, or (persistent) the number of blocks
@@ -865,7 +884,7 @@ const void *pick(int nf, int storage, int T, bool persistent, bool direct, bool 
 int grid_blocks(const UnitTable &ut, int persistent, int nf, int storage, size_t lds) {
     if (!persistent) return ut.n_units;
     int per_cu = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick(nf, storage, ut.block, true, false, true), ut.block, lds);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick(nf, storage, ut.block, true, false, true, false), ut.block, lds);
     int dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -913,41 +932,46 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
                         int xcd_remap, int persistent, int h2max, int h1max, bool mode0, hipStream_t stream,
                         const InstDesc *host_desc) {
     if (ut.n_units == 0) return hipSuccess;
-    if (!mode0) persistent = 0;
+    const bool ring_form = persistent == 2;
+    if (!mode0 || ring_form) persistent = 0;
     StageArgs a = stage_args(descs_dev, ut, xcd_remap, persistent, h1max, host_desc);
+    const bool ring = ring_form && mode0 && a.direct && ut.block <= 128;
     void *args[] = {&a.hidx, &a.src, &a.lnbr, &a.dxy, &a.vxy, &a.h12, &a.np, &a.nc, &a.ux, &a.hcode, &a.base,
                     &a.d, &a.nA, &a.u};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
-    const void *fn_ptr = pick(nf, storage, ut.block, persistent, a.direct, mode0);
+    const void *fn_ptr = pick(nf, storage, ut.block, persistent, a.direct, mode0, ring);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn_ptr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    return hipLaunchKernel(fn_ptr, dim3(grid_blocks(ut, persistent, nf, storage, lds)), dim3(ut.block), args, lds, stream);
+    return hipLaunchKernel(fn_ptr, dim3(grid_blocks(ut, persistent, nf, storage, lds)), dim3(ut.block + (ring ? 64 : 0)),
+                           args, lds, stream);
 }
 
 hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
                           int xcd_remap, int persistent, int h2max, int h1max, bool mode0, void **argbuf,
                           const InstDesc *host_desc) {
-    if (!mode0) persistent = 0;
+    const bool ring_form = persistent == 2;
+    if (!mode0 || ring_form) persistent = 0;
     // argbuf: caller-owned storage (a StageArgs block in argbuf[0], then one pointer per
     // argument), alive until the graph is instantiated
     StageArgs *a = reinterpret_cast<StageArgs *>(argbuf[0]);
     *a = stage_args(descs_dev, ut, xcd_remap, persistent, h1max, host_desc);
+    const bool ring = ring_form && mode0 && a->direct && ut.block <= 128;
     void **kp = argbuf + 1;
     kp[0] = &a->hidx; kp[1] = &a->src; kp[2] = &a->lnbr; kp[3] = &a->dxy; kp[4] = &a->vxy; kp[5] = &a->h12;
     kp[6] = &a->np; kp[7] = &a->nc; kp[8] = &a->ux; kp[9] = &a->hcode; kp[10] = &a->base; kp[11] = &a->d;
     kp[12] = &a->nA; kp[13] = &a->u;
     hipKernelNodeParams p{};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
-    p.func = const_cast<void *>(pick(nf, storage, ut.block, persistent, a->direct, mode0));
+    p.func = const_cast<void *>(pick(nf, storage, ut.block, persistent, a->direct, mode0, ring));
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(p.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     p.gridDim = dim3(grid_blocks(ut, persistent, nf, storage, lds));
-    p.blockDim = dim3(ut.block);
+    p.blockDim = dim3(ut.block + (ring ? 64 : 0));
     p.sharedMemBytes = (unsigned)lds;
     p.kernelParams = kp;
     p.extra = nullptr;

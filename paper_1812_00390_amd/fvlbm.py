@@ -273,13 +273,16 @@ class Solver:
         buf = C.create_string_buffer(data, len(data))
         _check(lib().fvlbm_restore(self.h, buf, len(data)))
 
-    def set_schedule(self, block: int, xcd_remap: bool = True, persistent: bool = False):
-        _check(lib().fvlbm_set_schedule(self.h, int(block), int(bool(xcd_remap)), int(bool(persistent))))
+    def set_schedule(self, block: int, xcd_remap: bool = True, persistent: int = 0):
+        """persistent: 0 (or False) one workgroup per tile, 1 (True) a resident
+        grid walking the tiles, 2 one workgroup per tile plus a wave for the halo
+        slots (tiles of 64 or 128 cells; Euler and RK stages)."""
+        _check(lib().fvlbm_set_schedule(self.h, int(block), int(bool(xcd_remap)), int(persistent)))
 
     def get_schedule(self):
         b, x, p = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().fvlbm_get_schedule(self.h, C.byref(b), C.byref(x), C.byref(p)))
-        return dict(block=b.value, xcd_remap=bool(x.value), persistent=bool(p.value))
+        return dict(block=b.value, xcd_remap=bool(x.value), persistent=int(p.value))
 
     def autotune(self, trial_steps: int = 64) -> float:
         """Pick the fastest launch schedule (state restored afterwards); returns ms per step."""

@@ -281,7 +281,8 @@ def test_graph_and_direct_launches_bitwise(F):
 def test_schedules_do_not_change_results(F, scheme):
     m = mg.cavity(n=22, jitter=0.2, seed=13)
     outs = []
-    for block, x, p in [(256, True, False), (64, False, True), (128, True, True), (256, False, False)]:
+    for block, x, p in [(256, True, False), (64, False, True), (128, True, True), (256, False, False),
+                        (64, True, 2), (128, False, 2)]:
         mesh = F.Mesh(m)
         s = F.Solver(mesh, F.make_params(tau=3e-4, scheme=scheme))
         s.set_schedule(block, x, p)
@@ -289,6 +290,30 @@ def test_schedules_do_not_change_results(F, scheme):
         outs.append(s.f)
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp32dev", "fp16dev", "i16dev"])
+@pytest.mark.parametrize("scheme", ["euler", "rk4"])
+def test_ring_wave_form_is_bitwise_the_plain_form(F, scheme, storage):
+    # launch form 2 (a wave for the halo slots) against one workgroup per tile:
+    # a natural-order mesh (halo rings wider than one 64-slot pass), a channel
+    # with inlet, outlet and symmetry groups, and quads
+    meshes = [(mg.cavity(n=30, jitter=0.2, seed=21), F.REORDER_NONE),
+              (mg.channel(26, 10, jitter=0.2, seed=22, tri=True, top="symmetry"), F.REORDER_BISECT),
+              (mg.cavity(n=12, jitter=0.1, seed=23, tri=False), F.REORDER_BISECT)]
+    for m, reorder in meshes:
+        mesh = F.Mesh(m, reorder=reorder)
+        outs = []
+        for block, p in [(64, 0), (64, 2), (128, 0), (128, 2)]:
+            s = F.Solver(mesh, F.make_params(tau=3e-3, cfl=0.5, u_ref=0.1, scheme=scheme, storage=storage))
+            s.set_schedule(block, True, p)
+            assert s.get_schedule()["persistent"] == p
+            s.step(23)
+            outs.append(s.f)
+            s.close()
+        assert np.all(np.isfinite(outs[0]))
+        for o in outs[1:]:
+            assert np.array_equal(outs[0], o)
 
 
 @pytest.mark.parametrize("scheme", ["rk4", "ab2"])
