@@ -84,18 +84,19 @@ __device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // (cell, direction): results do not depend on launch order, schedule,
 // batching or graphs.
 
-// Dither bits: the top of a 24-bit product (full-rate multiply) of the input
-// folded on itself, with one odd multiplier per direction.  The input is the
-// increment's bits, which change from step to step; the key is the cell.
+// Dither bits: the top of a 24-bit product (full-rate multiply) of the input's
+// low 24 bits, with one odd multiplier per direction.  The input is the
+// increment's bits (its mantissa fills the low 23) xor the cell, so it changes
+// from step to step and from cell to cell.
 __device__ constexpr uint32_t MIXK[Q] = {0x9e3779u, 0x85ebcbu, 0xc2b2afu, 0x27d4ebu, 0x165667u,
                                          0xd3a265u, 0xfd7047u, 0x6c8e95u, 0x4cf5adu};
-__device__ inline uint32_t mix(uint32_t x, int a) { return __umul24(x ^ (x >> 13), MIXK[a]); }
+__device__ inline uint32_t mix(uint32_t x, int a) { return __umul24(x, MIXK[a]); }
 
 // b + p rounded to FP32 with a centred dither of one ulp of b.  The dither is
 // drawn from the increment's bits, never from the bits being rounded away.
 __device__ inline float add_sr(float b, float p, uint32_t key, int a) {
-    const float g = __uint_as_float(__float_as_uint(b) & 0x7f800000u) * 0x1p-47f;   // ulp(b) / 2^24; 0 for b = 0
-    const int32_t r = (int32_t)mix(__float_as_uint(p) ^ key, a) >> 8;              // uniform in [-2^23, 2^23)
+    const float g = __uint_as_float(__float_as_uint(b) & 0x7f800000u) * 0x1p-55f;   // ulp(b) / 2^32; 0 for b = 0
+    const int32_t r = (int32_t)mix(__float_as_uint(p) ^ key, a);                    // uniform in [-2^31, 2^31)
     return b + fmaf((float)r, g, p);
 }
 
