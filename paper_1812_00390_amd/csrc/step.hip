@@ -181,7 +181,8 @@ struct BlockI16 {
 // Per-cell access for every storage mode.  load_cell fills f[a0..8] with the
 // deviations of cell c; store_cell writes b + inc.
 template <int STORE>
-__device__ inline void load_cell(const void *buf, size_t np, int c, float f[Q], const RefDev &r, int a0 = 0) {
+__device__ inline void load_cell(const void *buf, size_t np, int c, float f[Q], const RefDev &r, int a0 = 0,
+                                 int a1 = Q) {
     if constexpr (STORE == FVLBM_STORE_I16_DEV) {
         const float sc = BlockI16::scale(buf, np, c);
 #pragma unroll
@@ -190,7 +191,7 @@ __device__ inline void load_cell(const void *buf, size_t np, int c, float f[Q], 
         using S = Storage<STORE>;
         const uint32_t off = (uint32_t)c * S::SZ;
 #pragma unroll
-        for (int a = a0; a < Q; a++) f[a] = S::load(plane(buf, np * S::SZ, a), off, a, r);
+        for (int a = a0; a < a1; a++) f[a] = S::load(plane(buf, np * S::SZ, a), off, a, r);
     }
 }
 template <int STORE>
@@ -204,6 +205,22 @@ __device__ inline void store_cell(void *buf, size_t np, int c, const float b[Q],
 #pragma unroll
         for (int a = 0; a < Q; a++) S::store(plane(buf, np * S::SZ, a), off, a, b[a], inc[a], r, key0);
     }
+}
+
+// Direction halves of a split update: H = -1 all, 0 the rest and axis
+// directions (0-4), 1 the diagonal ones (5-8).
+__device__ constexpr bool in_half(int H, int a) { return H < 0 || (H == 0 ? a <= 4 : a >= 5); }
+
+// store_cell for the directions of half H (per-value storage modes only)
+template <int STORE, int H>
+__device__ inline void store_half(void *buf, size_t np, int c, const float b[Q], const float inc[Q], const RefDev &r,
+                                  uint32_t key0) {
+    static_assert(STORE != FVLBM_STORE_I16_DEV, "the block-scaled format stores a cell whole");
+    using S = Storage<STORE>;
+    const uint32_t off = (uint32_t)c * S::SZ;
+#pragma unroll
+    for (int a = 0; a < Q; a++)
+        if (in_half(H, a)) S::store(plane(buf, np * S::SZ, a), off, a, b[a], inc[a], r, key0);
 }
 
 // e_a . (x, y) for the D2Q9 velocities, folded per direction (no products by 0)
@@ -493,11 +510,11 @@ __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo
 
 // Boundary-face terms of the flux sum of tile cell i (Eqs. 18, 23-26); bm as in
 // boundary_gradient_body; the values of slot save_k were formed in phase 2.
-template <int NF>
+template <int NF, int H>
 __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const float gxi[Q], const float gyi[Q],
                                      const Macro &mi, const float hei[Q], uint2 packed, uint32_t bm,
-                                     const CellFaces<NF> &cf, const GroupDev *lg, const float save[Q], int save_k,
-                                     float acc[Q]) {
+                                     const CellGeo<NF> &geo, const CellFaces<NF> &cf, const GroupDev *lg,
+                                     const float save[Q], int save_k, float acc[Q]) {
 #pragma unroll 1
     for (uint32_t b = bm; b != 0u; b &= b - 1u) {
         const int k = __builtin_ctz(b);
@@ -510,13 +527,14 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
         if (k == save_k) {
 #pragma unroll
             for (int a = 1; a < Q; a++) bv[a] = save[a];
-        } else {
-            boundary_value(gr, hi, mi, hei, g, d.ref, bv);
+        } else {          // (the normal direction from the slot offset, as in the gradient)
+            boundary_value(gr, hi, mi, hei, pick2<NF>(geo.dk, k), d.ref, bv);
         }
         const int kind = gr.kind;
         const bool upwind = kind == FVLBM_BC_INLET || (kind == FVLBM_BC_OUTLET && gr.internal);
 #pragma unroll
         for (int a = 1; a < Q; a++) {
+            if (!in_half(H, a)) continue;
             const float en = edot(a, g.x, g.y);
             float phi;
             if (kind == FVLBM_BC_WALL) {
@@ -534,8 +552,11 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
 }
 
 // Phase 3 for one tile cell: face values, flux sum, BGK source, update, store.
-// base[] holds f(0) of the update when it is not the evaluated state.
-template <int NF, int STORE, bool M0>
+// base[] holds f(0) of the update when it is not the evaluated state.  H >= 0:
+// only the directions of that half (a base + coef RHS update), the other half
+// being another wave's; every per-direction value is the one the whole update
+// forms.
+template <int NF, int STORE, bool M0, int H>
 __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, const float base[Q], bool sep_base,
                                             const int (&code)[NF], uint2 packed, const CellGeo<NF> &geo, const CellFaces<NF> &cf,
                                             const float4 *own, const float4 *A, const GroupDev *lg,
@@ -578,13 +599,14 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
         up[8] = !up[6];
 #pragma unroll
         for (int a = 1; a < Q; a++) {
+            if (!in_half(H, a)) continue;
             const float en = edot(a, g.x, g.y);
             const float own_v = fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a]));
             const float nb_v = fmaf(gyj[a], q.y, fmaf(gxj[a], q.x, hj[a]));
             acc[a] = fmaf(en, up[a] ? own_v : nb_v, acc[a]);
         }
     }
-    if (bm) boundary_flux<NF>(d, hi, gxi, gyi, mi, hei, packed, bm, cf, lg, bsave, bsave_k, acc);
+    if (bm) boundary_flux<NF, H>(d, hi, gxi, gyi, mi, hei, packed, bm, geo, cf, lg, bsave, bsave_k, acc);
 
     // The BGK source moves no mass and no momentum: f_eq carries the density and
     // momentum of f (Eqs. 3, 5).  In FP32 the rounding of f_eq (terms near 0.05,
@@ -611,6 +633,7 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
     const uint32_t o4 = (uint32_t)i * 4u;
     const size_t pb4 = (size_t)d.np * 4;
     const int mode = M0 ? 0 : d.mode;
+    static_assert(H < 0 || M0, "a split update is a base + coef RHS update");
     float bv[Q], inc[Q];
 #pragma unroll
     for (int a = 0; a < Q; a++) {
@@ -627,7 +650,10 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
             sto<float>(plane(d.rhs_prev, pb4, a), o4, rhs);
         }
     }
-    if (mode != 3) store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i);
+    if constexpr (H >= 0)
+        store_half<STORE, H>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i);
+    else if (mode != 3)
+        store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i);
 }
 
 // The values a tile's loads depend on (kernel arguments for a single instance).
@@ -671,6 +697,9 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // owns the halo slots, so halo loads and ring-1 gradients run beside the
     // tile's own; otherwise thread t owns tile cell t and halo slot t.
     constexpr int RS = RING ? 64 : T;                 // halo slots per pass
+    // With 64-cell tiles the halo wave also takes the diagonal directions of the
+    // tile's phase-3 update (lane l: cell l), the tile's wave the others.
+    constexpr bool SPLIT3 = RING && T == 64 && STORE != FVLBM_STORE_I16_DEV;
     const bool ownw = !RING || __builtin_amdgcn_readfirstlane(tid) < T;   // (wave-uniform)
     const int rj = RING ? tid - T : tid;              // this thread's halo slot (< 0: none)
     const int i = tile * T + tid;
@@ -703,6 +732,15 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     }
     if (RING && !ownw)
         hraw1 = ldg(hidx, rj < hs ? rj : 0), hraw2 = ldg(hidx, h1s + rj < hs ? h1s + rj : 0);
+    const int i3 = tile * T + rj;                     // SPLIT3: this halo lane's tile cell
+    const bool valid3 = SPLIT3 && !ownw && i3 < n_cells;
+    if (SPLIT3 && !ownw) {                            // (one level, beside the halo chain)
+        const int ic3 = valid3 ? i3 : 0;
+        load_cell<STORE>(src, np, ic3, f, d.ref, 0, 1);
+        ln = ldo<uint2>(lnbr, (uint32_t)ic3 * 8u);
+        geo.load(dxy, np, ic3);
+        cf.load(vxy, np, ic3);
+    }
     const int c1 = rin && rj < h1s ? hraw1 : -1;
     const int c2 = rin && rj < h2s ? hraw2 : -1;
     int hcode[NF];
@@ -726,11 +764,17 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     const void *basep = DIRECT ? hot.base : d.base;
     const bool sep_base = (M0 || d.mode == 0) && basep != src;
     if (ownw) {
-        if (sep_base) load_cell<STORE>(basep, np, ic, base, d.ref);
+        if (sep_base) load_cell<STORE>(basep, np, ic, base, d.ref, 0, SPLIT3 ? 5 : Q);
         h0 = f[0];
 #pragma unroll
         for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
         geo.invert(code);
+        cf.finish();
+    } else if (SPLIT3) {
+        if (sep_base) load_cell<STORE>(basep, np, valid3 ? i3 : 0, base, d.ref, 5, Q);
+        h0 = f[0];
+#pragma unroll
+        for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
         cf.finish();
     }
     if (valid) wr_f(A + tid * RA, f);
@@ -799,7 +843,12 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         }
     }
     __syncthreads();
-    if (valid) tile_update<NF, STORE, M0>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A, lg, bsave, bsave_k);
+    if (valid)
+        tile_update<NF, STORE, M0, SPLIT3 ? 0 : -1>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A, lg,
+                                                    bsave, bsave_k);
+    if constexpr (SPLIT3)
+        if (valid3)
+            tile_update<NF, STORE, M0, 1>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj * RA, A, lg, bsave, -1);
 }
 
 // DIRECT: one instance whose unit b is tile b, the bases and sizes its loads
