@@ -268,12 +268,18 @@ __device__ inline void heq(float drho, float rho, float jx, float jy, const RefD
     const float ir = frcp(rho);
     const float jj = 1.5f * (jx * jx + jy * jy);
     const float dx = jx - r.jx0, dy = jy - r.jy0;
+    out[0] = WT[0] * (drho + fmaf(3.f, 0.f, fmaf(fmaf(0.f, 0.f, -jj), ir, -r.c0[0])));
+    // Opposite directions (e_b = -e_a) share (e.j)^2 and c0, and their e.(j - j0)
+    // differ in sign only (every negation here is exact): one quadratic term per pair.
+    constexpr int PA[4] = {1, 2, 5, 6}, PB[4] = {3, 4, 7, 8};
 #pragma unroll
-    for (int a = 0; a < Q; a++) {
+    for (int p = 0; p < 4; p++) {
+        const int a = PA[p], b = PB[p];
         const float ej = edot(a, jx, jy);
         const float ed = edot(a, dx, dy);
         const float quad = fmaf(fmaf(4.5f * ej, ej, -jj), ir, -r.c0[a]);
         out[a] = WT[a] * (drho + fmaf(3.f, ed, quad));
+        out[b] = WT[b] * (drho + fmaf(-3.f, ed, quad));
     }
 }
 
