@@ -347,9 +347,8 @@ __device__ inline int remap_block(int b, int nb, int xcd_remap) {
 
 __device__ inline int unpack16(uint32_t w, int hi) { return (int)(int16_t)(hi ? (w >> 16) : (w & 0xffffu)); }
 
-
-// corner k of cell c (offset from the centroid)
-// v[k] for a wave-uniform k, from registers (no dynamic register indexing)
+// v[k] from registers by selects (no dynamic register indexing; k may differ
+// between lanes)
 template <int NF>
 __device__ __forceinline__ float2 pick2(const float2 (&v)[NF], int k) {
     float2 r = v[0];
@@ -680,6 +679,9 @@ struct Hot {
 //   Phase 3  per tile cell: face values (own gradient outgoing, staged
 //            neighbour value and gradient incoming), flux sum, BGK source,
 //            update, store.
+// With RING one more wave takes the halo slots: their loads in phase 1 and the
+// ring-1 gradients in phase 2, beside the tile's own (and, with 64-cell tiles,
+// half of phase 3).
 // Dynamic LDS: nA = T + (largest ring-1 slot count) region-A records, then
 // region-B records for the largest ring-2 slot count (sized by the launcher).
 template <int NF, int STORE, int T, bool DIRECT, bool M0, bool RING>
