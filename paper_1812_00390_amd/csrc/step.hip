@@ -242,6 +242,7 @@ struct Macro {
     float drho, rho;   // rho - rho0, rho
     float jx, jy;      // momentum rho u
     float ux, uy;
+    float ir;          // 1 / rho
 };
 
 // Eq. 5 on deviations h = f - f_eq(rho0, u_dev): rho = rho0 + sum h, rho u = rho0 u_dev + sum e h.
@@ -259,6 +260,7 @@ __device__ inline Macro moments(const float h[Q], const RefDev &r) {
     const float ir = frcp(m.rho);
     m.ux = m.jx * ir;
     m.uy = m.jy * ir;
+    m.ir = ir;
     return m;
 }
 
@@ -283,32 +285,69 @@ __device__ inline void heq(float drho, float rho, float jx, float jy, const RefD
     }
 }
 
-// Boundary stencil value of a cell's boundary slot (Eqs. 18-22), deviation form.
-__device__ inline void boundary_value(const GroupDev &g, const float h[Q], const Macro &m,
-                                      const float heq_c[Q], float2 gn, const RefDev &r, float out[Q]) {
-    float e[Q];
-    switch (g.kind) {
-    case FVLBM_BC_WALL:                 // Eq. 18: f_eq(rho_k, u_w) + f_k - f_eq,k
-        heq(m.drho, m.rho, m.rho * g.ux, m.rho * g.uy, r, e);
+// f_eq(rho, j*) - f_eq(rho, j) (Eq. 3) at one density: the reference terms
+// cancel, and with D = j* - j, S = j* + j the quadratic terms factor,
+// (e.j*)^2 - (e.j)^2 = (e.D)(e.S) and |j*|^2 - |j|^2 = D.S, so the difference is
+// w [3 e.D + (4.5 (e.D)(e.S) - 1.5 D.S) / rho], formed without either equilibrium.
+__device__ inline void eq_delta_same_rho(const Macro &m, float jsx, float jsy, float out[Q]) {
+    const float Dx = jsx - m.jx, Dy = jsy - m.jy;
+    const float Sx = jsx + m.jx, Sy = jsy + m.jy;
+    const float C = 1.5f * fmaf(Dx, Sx, Dy * Sy);
+    out[0] = WT[0] * (-C * m.ir);
+    constexpr int PA[4] = {1, 2, 5, 6}, PB[4] = {3, 4, 7, 8};   // opposite pairs, e_b = -e_a
 #pragma unroll
-        for (int a = 0; a < Q; a++) out[a] = e[a] + (h[a] - heq_c[a]);
+    for (int p = 0; p < 4; p++) {
+        const int a = PA[p], b = PB[p];
+        const float eD = edot(a, Dx, Dy);
+        const float q = fmaf(4.5f * eD, edot(a, Sx, Sy), -C) * m.ir;   // the same for e_b
+        out[a] = WT[a] * fmaf(3.f, eD, q);
+        out[b] = WT[b] * fmaf(-3.f, eD, q);
+    }
+}
+
+// f_eq(rho*, j*) - f_eq(rho, j) (Eq. 3) for a density rho* = rho0 + drs: the
+// reference terms cancel, leaving
+// w [(rho* - rho) + 3 e.(j* - j) + (4.5 (e.j*)^2 - 1.5 |j*|^2) / rho* - (4.5 (e.j)^2 - 1.5 |j|^2) / rho].
+__device__ inline void eq_delta(const Macro &m, float drs, float rs, float jsx, float jsy, float out[Q]) {
+    const float irs = frcp(rs);
+    const float jjs = 1.5f * fmaf(jsx, jsx, jsy * jsy), jj = 1.5f * fmaf(m.jx, m.jx, m.jy * m.jy);
+    const float dd = drs - m.drho;
+    const float dx = jsx - m.jx, dy = jsy - m.jy;
+    out[0] = WT[0] * (dd + fmaf(-jjs, irs, jj * m.ir));
+    constexpr int PA[4] = {1, 2, 5, 6}, PB[4] = {3, 4, 7, 8};
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+        const int a = PA[p], b = PB[p];
+        const float es = edot(a, jsx, jsy), ej = edot(a, m.jx, m.jy);
+        const float q = fmaf(fmaf(4.5f * es, es, -jjs), irs, -(fmaf(4.5f * ej, ej, -jj) * m.ir));
+        const float ed = edot(a, dx, dy);
+        out[a] = WT[a] * (dd + fmaf(3.f, ed, q));
+        out[b] = WT[b] * (dd + fmaf(-3.f, ed, q));
+    }
+}
+
+// Boundary stencil value of a cell's boundary slot (Eqs. 18-22) minus the cell's
+// own value, phi_k - h.  A wall, an inlet and an internal-density outlet set
+// phi_k = f_eq(rho*, j*) + (h - f_eq(rho, j)), so the difference is that of two
+// equilibria, formed directly; a symmetry ghost is an equilibrium itself.
+__device__ inline void boundary_delta(const GroupDev &g, const float h[Q], const Macro &m, float2 gn,
+                                      const RefDev &r, float out[Q]) {
+    switch (g.kind) {
+    case FVLBM_BC_WALL:                 // Eq. 18: rho* = rho_k, u* = u_w
+        eq_delta_same_rho(m, m.rho * g.ux, m.rho * g.uy, out);
         break;
     case FVLBM_BC_INLET: {              // Eq. 19: rho* = rho_inf (external) or rho_k (internal)
         const float dr = g.internal ? m.drho : g.drho;
         const float rs = g.internal ? m.rho : g.rho;
-        heq(dr, rs, rs * g.ux, rs * g.uy, r, e);
-#pragma unroll
-        for (int a = 0; a < Q; a++) out[a] = e[a] + (h[a] - heq_c[a]);
+        eq_delta(m, dr, rs, rs * g.ux, rs * g.uy, out);
         break;
     }
     case FVLBM_BC_OUTLET:
         if (!g.internal) {              // Eq. 20: f_GC = f_i
 #pragma unroll
-            for (int a = 0; a < Q; a++) out[a] = h[a];
-        } else {                        // Eq. 21: f_eq(rho_inf, u_i) + f_k - f_eq,k
-            heq(g.drho, g.rho, g.rho * m.ux, g.rho * m.uy, r, e);
-#pragma unroll
-            for (int a = 0; a < Q; a++) out[a] = e[a] + (h[a] - heq_c[a]);
+            for (int a = 0; a < Q; a++) out[a] = 0.f;
+        } else {                        // Eq. 21: rho* = rho_inf, u* = u_i
+            eq_delta(m, g.drho, g.rho, g.rho * m.ux, g.rho * m.uy, out);
         }
         break;
     default: {                          // Eq. 22: mirrored normal velocity
@@ -316,11 +355,12 @@ __device__ inline void boundary_value(const GroupDev &g, const float h[Q], const
         const float nx = gn.x * il, ny = gn.y * il;
         const float jn = m.jx * nx + m.jy * ny;
         heq(m.drho, m.rho, m.jx - 2.f * jn * nx, m.jy - 2.f * jn * ny, r, out);
+#pragma unroll
+        for (int a = 0; a < Q; a++) out[a] -= h[a];
         break;
     }
     }
 }
-
 
 // Least-squares coefficient of slot k of cell c: M^-1 w_k d_k (Eq. 12).
 __device__ inline float2 lsq_coef(float2 dk, float m11, float m12, float m22) {
@@ -443,18 +483,16 @@ __device__ inline void wr_g(float4 *rec, const float gx[Q], const float gy[Q]) {
 }
 
 // Boundary-slot terms of the gradient of cell c: phi_k is the wall / ghost
-// value (Eqs. 18-22) formed from the cell's own state.  bm: the cell's boundary
-// slots as bits; each lane walks its own (so a wave makes as many passes as its
-// lane with the most boundary faces), in slot order.  SAVE: the values of the
-// first boundary slot are kept (save, save_k) for the cell's boundary flux, which
-// forms the same values from the same state.
+// value (Eqs. 18-22) formed from the cell's own state, taken as phi_k - h_c.
+// bm: the cell's boundary slots as bits; each lane walks its own (so a wave
+// makes as many passes as its lane with the most boundary faces), in slot order.
+// SAVE: phi_k - h_c of the first boundary slot is kept (save, save_k) for the
+// cell's boundary flux, which forms the same values from the same state.
 template <int NF, bool SAVE>
 __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                               uint2 packed, uint32_t bm, const GroupDev *lg, float gx[Q], float gy[Q],
                                               float save[Q], int &save_k) {
     const Macro m = moments(hc, d.ref);
-    float he[Q];
-    heq(m.drho, m.rho, m.jx, m.jy, d.ref, he);
 #pragma unroll 1
     for (uint32_t b = bm; b != 0u; b &= b - 1u) {
         const int k = __builtin_ctz(b);
@@ -466,18 +504,17 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
         // distance along that normal (the mirrored centre): dk has the direction
         const float2 gn = dk;
         const GroupDev g = lg[-1 - ck];
-        float phi[Q];
-        boundary_value(g, hc, m, he, gn, d.ref, phi);
+        float df[Q];
+        boundary_delta(g, hc, m, gn, d.ref, df);
         if (SAVE && save_k < 0) {
             save_k = k;
 #pragma unroll
-            for (int a = 1; a < Q; a++) save[a] = phi[a];
+            for (int a = 1; a < Q; a++) save[a] = df[a];
         }
 #pragma unroll
         for (int a = 1; a < Q; a++) {
-            const float df = phi[a] - hc[a];
-            gx[a] = fmaf(w.x, df, gx[a]);
-            gy[a] = fmaf(w.y, df, gy[a]);
+            gx[a] = fmaf(w.x, df[a], gx[a]);
+            gy[a] = fmaf(w.y, df[a], gy[a]);
         }
     }
 }
@@ -514,10 +551,10 @@ __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo
 }
 
 // Boundary-face terms of the flux sum of tile cell i (Eqs. 18, 23-26); bm as in
-// boundary_gradient_body; the values of slot save_k were formed in phase 2.
+// boundary_gradient_body; phi_k - h_i of slot save_k was formed in phase 2.
 template <int NF, int H>
 __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const float gxi[Q], const float gyi[Q],
-                                     const Macro &mi, const float hei[Q], uint2 packed, uint32_t bm,
+                                     const Macro &mi, uint2 packed, uint32_t bm,
                                      const CellGeo<NF> &geo, const CellFaces<NF> &cf, const GroupDev *lg,
                                      const float save[Q], int save_k, float acc[Q]) {
 #pragma unroll 1
@@ -528,12 +565,12 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
         const float2 g = scaled_normal(v0, v1, cf.inva);
         const float2 r = make_float2(0.5f * (v0.x + v1.x), 0.5f * (v0.y + v1.y));   // x_f - x_i
         const GroupDev gr = lg[-1 - ck];
-        float bv[Q];
+        float dv[Q];      // phi_k - h_i
         if (k == save_k) {
 #pragma unroll
-            for (int a = 1; a < Q; a++) bv[a] = save[a];
+            for (int a = 1; a < Q; a++) dv[a] = save[a];
         } else {          // (the normal direction from the slot offset, as in the gradient)
-            boundary_value(gr, hi, mi, hei, pick2<NF>(geo.dk, k), d.ref, bv);
+            boundary_delta(gr, hi, mi, pick2<NF>(geo.dk, k), d.ref, dv);
         }
         const int kind = gr.kind;
         const bool upwind = kind == FVLBM_BC_INLET || (kind == FVLBM_BC_OUTLET && gr.internal);
@@ -541,15 +578,16 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
         for (int a = 1; a < Q; a++) {
             if (!in_half(H, a)) continue;
             const float en = edot(a, g.x, g.y);
+            const float bv = hi[a] + dv[a];
             float phi;
             if (kind == FVLBM_BC_WALL) {
-                phi = bv[a];                                                    // Eq. 18 face value
+                phi = bv;                                                       // Eq. 18 face value
             } else if (upwind) {
-                phi = en > 0.f ? fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a])) : bv[a];   // Eqs. 23, 24
+                phi = en > 0.f ? fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a])) : bv;   // Eqs. 23, 24
             } else if (kind == FVLBM_BC_OUTLET) {
                 phi = hi[a];                                                    // Eq. 25
             } else {
-                phi = 0.5f * (hi[a] + bv[a]);                                   // Eq. 26
+                phi = fmaf(0.5f, dv[a], hi[a]);                                 // Eq. 26: the mean of h_i and phi_k
             }
             acc[a] = fmaf(en, phi, acc[a]);
         }
@@ -611,7 +649,7 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
             acc[a] = fmaf(en, up[a] ? own_v : nb_v, acc[a]);
         }
     }
-    if (bm) boundary_flux<NF, H>(d, hi, gxi, gyi, mi, hei, packed, bm, geo, cf, lg, bsave, bsave_k, acc);
+    if (bm) boundary_flux<NF, H>(d, hi, gxi, gyi, mi, packed, bm, geo, cf, lg, bsave, bsave_k, acc);
 
     // The BGK source moves no mass and no momentum: f_eq carries the density and
     // momentum of f (Eqs. 3, 5).  In FP32 the rounding of f_eq (terms near 0.05,
@@ -688,6 +726,10 @@ template <int NF, int STORE, int T, bool DIRECT, bool M0, bool RING>
 __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, int2 u, const Hot &hot, float4 *A,
                                           float4 *B) {
     const InstDesc &d = descs[u.x];
+    // Two descriptor lines (reference state and update coefficients) are first
+    // needed in phases 2 and 3; one word of each is read here, so that their
+    // trip to the scalar cache overlaps the phase-1 loads.
+    const float warm0 = d.ref.rho0, warm1 = d.ref.c0[1];
     // the values the first loads depend on: kernel arguments for a single instance
     // (no descriptor load on the path to the first loads), else the descriptor
     const void *src = DIRECT ? hot.src : d.src;
@@ -810,10 +852,11 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         load_cell<STORE>(src, np, c, g, d.ref, 1);
         wr_f(B + k * RB, g);
     }
+    asm volatile("" ::"s"(warm0), "s"(warm1));    // (keeps the two reads above)
     __syncthreads();
 
     // ---- phase 2
-    float bsave[Q];                                // the cell's first boundary values, for phase 3
+    float bsave[Q];                                // phi_k - h of the cell's first boundary slot, for phase 3
     int bsave_k = -1;
     {
         float hc[Q], gx[Q], gy[Q];
