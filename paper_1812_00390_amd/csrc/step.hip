@@ -488,10 +488,12 @@ __device__ inline void wr_g(float4 *rec, const float gx[Q], const float gy[Q]) {
 // makes as many passes as its lane with the most boundary faces), in slot order.
 // SAVE: phi_k - h_c of the first boundary slot is kept (save, save_k) for the
 // cell's boundary flux, which forms the same values from the same state.
-template <int NF, bool SAVE>
+// STASH: phi_k - h_c of every boundary slot k also goes to stash[2k], stash[2k + 1]
+// (directions 1-4, 5-8), for a flux computed by another wave.
+template <int NF, bool SAVE, bool STASH>
 __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                               uint2 packed, uint32_t bm, const GroupDev *lg, float gx[Q], float gy[Q],
-                                              float save[Q], int &save_k) {
+                                              float save[Q], int &save_k, float4 *stash) {
     const Macro m = moments(hc, d.ref);
 #pragma unroll 1
     for (uint32_t b = bm; b != 0u; b &= b - 1u) {
@@ -511,6 +513,10 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
 #pragma unroll
             for (int a = 1; a < Q; a++) save[a] = df[a];
         }
+        if (STASH) {
+            stash[2 * k] = make_float4(df[1], df[2], df[3], df[4]);
+            stash[2 * k + 1] = make_float4(df[5], df[6], df[7], df[8]);
+        }
 #pragma unroll
         for (int a = 1; a < Q; a++) {
             gx[a] = fmaf(w.x, df[a], gx[a]);
@@ -523,10 +529,11 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
 // phi_k the staged value of local cell code[k] (interior slots first, then
 // boundary slots).  Local indices below `a_end` are region-A records, the rest
 // region B.
-template <int NF, bool SAVE>
+template <int NF, bool SAVE, bool STASH>
 __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                        const int (&code)[NF], uint2 packed, const float4 *A, const float4 *B, int a_end,
-                                       const GroupDev *lg, float gx[Q], float gy[Q], float save[Q], int &save_k) {
+                                       const GroupDev *lg, float gx[Q], float gy[Q], float save[Q], int &save_k,
+                                       float4 *stash) {
 #pragma unroll
     for (int a = 1; a < Q; a++) { gx[a] = 0.f; gy[a] = 0.f; }
     uint32_t bm = 0u;                     // boundary slots (padded slots have no face)
@@ -547,16 +554,17 @@ __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo
             gy[a] = fmaf(w.y, df, gy[a]);
         }
     }
-    if (bm) boundary_gradient_body<NF, SAVE>(d, geo, hc, packed, bm, lg, gx, gy, save, save_k);
+    if (bm) boundary_gradient_body<NF, SAVE, STASH>(d, geo, hc, packed, bm, lg, gx, gy, save, save_k, stash);
 }
 
 // Boundary-face terms of the flux sum of tile cell i (Eqs. 18, 23-26); bm as in
-// boundary_gradient_body; phi_k - h_i of slot save_k was formed in phase 2.
-template <int NF, int H>
+// boundary_gradient_body; phi_k - h_i of slot save_k was formed in phase 2, and
+// with STASH those of every slot (stash as in boundary_gradient_body).
+template <int NF, int H, bool STASH>
 __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const float gxi[Q], const float gyi[Q],
                                      const Macro &mi, uint2 packed, uint32_t bm,
                                      const CellGeo<NF> &geo, const CellFaces<NF> &cf, const GroupDev *lg,
-                                     const float save[Q], int save_k, float acc[Q]) {
+                                     const float save[Q], int save_k, const float4 *stash, float acc[Q]) {
 #pragma unroll 1
     for (uint32_t b = bm; b != 0u; b &= b - 1u) {
         const int k = __builtin_ctz(b);
@@ -569,6 +577,15 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
         if (k == save_k) {
 #pragma unroll
             for (int a = 1; a < Q; a++) dv[a] = save[a];
+        } else if (STASH) {
+            if (H != 1) {
+                const float4 x = stash[2 * k];
+                dv[1] = x.x; dv[2] = x.y; dv[3] = x.z; dv[4] = x.w;
+            }
+            if (H != 0) {
+                const float4 y = stash[2 * k + 1];
+                dv[5] = y.x; dv[6] = y.y; dv[7] = y.z; dv[8] = y.w;
+            }
         } else {          // (the normal direction from the slot offset, as in the gradient)
             boundary_delta(gr, hi, mi, pick2<NF>(geo.dk, k), d.ref, dv);
         }
@@ -599,11 +616,11 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
 // only the directions of that half (a base + coef RHS update), the other half
 // being another wave's; every per-direction value is the one the whole update
 // forms.
-template <int NF, int STORE, bool M0, int H>
+template <int NF, int STORE, bool M0, int H, bool STASH>
 __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, const float base[Q], bool sep_base,
                                             const int (&code)[NF], uint2 packed, const CellGeo<NF> &geo, const CellFaces<NF> &cf,
                                             const float4 *own, const float4 *A, const GroupDev *lg,
-                                            const float bsave[Q], int bsave_k) {
+                                            const float bsave[Q], int bsave_k, const float4 *stash) {
     float hi[Q], gxi[Q], gyi[Q];
     hi[0] = h0;
     rd_f(own, hi);
@@ -649,7 +666,7 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
             acc[a] = fmaf(en, up[a] ? own_v : nb_v, acc[a]);
         }
     }
-    if (bm) boundary_flux<NF, H>(d, hi, gxi, gyi, mi, packed, bm, geo, cf, lg, bsave, bsave_k, acc);
+    if (bm) boundary_flux<NF, H, STASH>(d, hi, gxi, gyi, mi, packed, bm, geo, cf, lg, bsave, bsave_k, stash, acc);
 
     // The BGK source moves no mass and no momentum: f_eq carries the density and
     // momentum of f (Eqs. 3, 5).  In FP32 the rounding of f_eq (terms near 0.05,
@@ -750,6 +767,10 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // With 64-cell tiles the halo wave also takes the diagonal directions of the
     // tile's phase-3 update (lane l: cell l), the tile's wave the others.
     constexpr bool SPLIT3 = RING && T == 64 && STORE != FVLBM_STORE_I16_DEV;
+    // SPLIT3: phi_k - h of the tile cells' boundary slots, formed in phase 2 by
+    // the tile's wave, staged for the halo wave's half of phase 3 (and for the
+    // tile wave's slots after the first)
+    __shared__ float4 lstash[SPLIT3 ? T * NF * 2 : 1];
     const bool ownw = !RING || __builtin_amdgcn_readfirstlane(tid) < T;   // (wave-uniform)
     const int rj = RING ? tid - T : tid;              // this thread's halo slot (< 0: none)
     const int i = tile * T + tid;
@@ -864,13 +885,14 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         if (valid) {
             hc[0] = h0;
             rd_f(A + tid * RA, hc);
-            gradient_staged<NF, true>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, bsave, bsave_k);
+            gradient_staged<NF, true, SPLIT3>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, bsave, bsave_k,
+                                              lstash + tid * NF * 2);
             wr_g(A + tid * RA, gx, gy);
         }
         if (c1 >= 0) {
             hc[0] = hf0;
             rd_f(A + (T + rj) * RA, hc);
-            gradient_staged<NF, false>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy, hc, no_k);
+            gradient_staged<NF, false, false>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy, hc, no_k, nullptr);
             wr_g(A + (T + rj) * RA, gx, gy);
         }
         for (int k = rin ? rj + RS : h1s; k < h1s; k += RS) {
@@ -889,17 +911,18 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
                 hc[0] = t[0];
             }
             rd_f(A + (T + k) * RA, hc);
-            gradient_staged<NF, false>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy, hc, no_k);
+            gradient_staged<NF, false, false>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy, hc, no_k, nullptr);
             wr_g(A + (T + k) * RA, gx, gy);
         }
     }
     __syncthreads();
     if (valid)
-        tile_update<NF, STORE, M0, SPLIT3 ? 0 : -1>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA, A, lg,
-                                                    bsave, bsave_k);
+        tile_update<NF, STORE, M0, SPLIT3 ? 0 : -1, SPLIT3>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA,
+                                                            A, lg, bsave, bsave_k, lstash + tid * NF * 2);
     if constexpr (SPLIT3)
         if (valid3)
-            tile_update<NF, STORE, M0, 1>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj * RA, A, lg, bsave, -1);
+            tile_update<NF, STORE, M0, 1, SPLIT3>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj * RA, A, lg,
+                                                  bsave, -1, lstash + rj * NF * 2);
 }
 
 // DIRECT: one instance whose unit b is tile b, the bases and sizes its loads
@@ -1022,7 +1045,8 @@ size_t stage_lds_limit() {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
         v = 65536;
-    return (size_t)v - sizeof(GroupDev) * MAX_GROUPS;   // less the staged group table
+    // less the staged group table and the boundary stash of 64-cell halo-wave tiles
+    return (size_t)v - sizeof(GroupDev) * MAX_GROUPS - sizeof(float4) * 64 * 4 * 2;
 }
 
 size_t stage_lds_bytes(int T, int h2max, int h1max) {
