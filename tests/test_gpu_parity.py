@@ -96,14 +96,15 @@ def test_rhs_matches_oracle(F, O, name, reorder, storage):
 
 
 def _run_pair(F, O, m, tau, scheme, steps, storage="fp32dev", cfl=0.5, u_ref=0.1, u0=(0.0, 0.0),
-              reorder=1, block=None, chunks=None):
+              reorder=1, block=None, chunks=None, form=0):
     o = O.Oracle(m, tau=tau, cfl=cfl, u_ref=u_ref, scheme=scheme)
     o.init(rho0=1.0, u0=u0)
     mesh = F.Mesh(m, reorder=reorder)
     s = F.Solver(mesh, F.make_params(tau=tau, dt=o.dt, scheme=scheme, storage=storage, u_ref=u_ref, u_dev=u0),
                  u=np.tile(np.asarray(u0, float), (m.n_cells, 1)))
     if block:
-        s.set_schedule(block, True)
+        s.set_schedule(block, True, form)
+        assert s.get_schedule()["persistent"] == form
     o.step(steps)
     for c in (chunks or [steps]):
         s.step(c)
@@ -160,6 +161,21 @@ def test_boundary_runs_match_oracle(F, O, name):
     m = make()
     u0 = (0.1, 0.0) if name != "hybrid" else (0.0, 0.0)
     (rg, ug, st), (ro, uo), o, s = _run_pair(F, O, m, tau, "rk4", 150, u0=u0, u_ref=0.2)
+    assert np.abs(ug - uo).max() <= 1e-5 * 0.1, np.abs(ug - uo).max()
+    assert np.abs(rg - ro).max() <= 1e-6
+
+
+@pytest.mark.parametrize("scheme", ["rk4", "euler"])
+@pytest.mark.parametrize("name", ["channel_ext", "channel_int_sym", "cylinder", "two_cylinders", "hybrid"])
+def test_halo_wave_form_boundary_runs_match_oracle(F, O, name, scheme):
+    # launch form 2 with 64-cell tiles: the boundary values of every kind (inlet,
+    # internal / external outlet, symmetry, moving and fixed walls; corner cells
+    # with two boundary faces) are formed once by the tile's wave and staged in
+    # LDS for both waves' halves of the update
+    make, tau = RHS_MESHES[name]
+    m = make()
+    u0 = (0.1, 0.0) if name != "hybrid" else (0.0, 0.0)
+    (rg, ug, st), (ro, uo), o, s = _run_pair(F, O, m, tau, scheme, 150, u0=u0, u_ref=0.2, block=64, form=2)
     assert np.abs(ug - uo).max() <= 1e-5 * 0.1, np.abs(ug - uo).max()
     assert np.abs(rg - ro).max() <= 1e-6
 
