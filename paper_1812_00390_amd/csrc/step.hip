@@ -266,17 +266,20 @@ __device__ inline Macro moments(const float h[Q], const RefDev &r) {
 
 // Eq. 3 as a deviation from the reference equilibrium, written with the momentum j = rho u:
 // f_eq(rho, u) - f_eq(rho0, u_dev) = w [ (rho - rho0) + 3 e.(j - j0) + (4.5 (e.j)^2 - 1.5 |j|^2)/rho - c0 ]
+// H >= 0: only the directions of half H (in_half), out[0] not formed.
+template <int H = -1>
 __device__ inline void heq(float drho, float rho, float jx, float jy, const RefDev &r, float out[Q]) {
     const float ir = frcp(rho);
     const float jj = 1.5f * (jx * jx + jy * jy);
     const float dx = jx - r.jx0, dy = jy - r.jy0;
-    out[0] = WT[0] * (drho + fmaf(3.f, 0.f, fmaf(fmaf(0.f, 0.f, -jj), ir, -r.c0[0])));
+    if (H < 0) out[0] = WT[0] * (drho + fmaf(3.f, 0.f, fmaf(fmaf(0.f, 0.f, -jj), ir, -r.c0[0])));
     // Opposite directions (e_b = -e_a) share (e.j)^2 and c0, and their e.(j - j0)
     // differ in sign only (every negation here is exact): one quadratic term per pair.
     constexpr int PA[4] = {1, 2, 5, 6}, PB[4] = {3, 4, 7, 8};
 #pragma unroll
     for (int p = 0; p < 4; p++) {
         const int a = PA[p], b = PB[p];
+        if (!in_half(H, a)) continue;
         const float ej = edot(a, jx, jy);
         const float ed = edot(a, dx, dy);
         const float quad = fmaf(fmaf(4.5f * ej, ej, -jj), ir, -r.c0[a]);
@@ -289,15 +292,17 @@ __device__ inline void heq(float drho, float rho, float jx, float jy, const RefD
 // cancel, and with D = j* - j, S = j* + j the quadratic terms factor,
 // (e.j*)^2 - (e.j)^2 = (e.D)(e.S) and |j*|^2 - |j|^2 = D.S, so the difference is
 // w [3 e.D + (4.5 (e.D)(e.S) - 1.5 D.S) / rho], formed without either equilibrium.
+template <int H>
 __device__ inline void eq_delta_same_rho(const Macro &m, float jsx, float jsy, float out[Q]) {
     const float Dx = jsx - m.jx, Dy = jsy - m.jy;
     const float Sx = jsx + m.jx, Sy = jsy + m.jy;
     const float C = 1.5f * fmaf(Dx, Sx, Dy * Sy);
-    out[0] = WT[0] * (-C * m.ir);
+    if (H < 0) out[0] = WT[0] * (-C * m.ir);
     constexpr int PA[4] = {1, 2, 5, 6}, PB[4] = {3, 4, 7, 8};   // opposite pairs, e_b = -e_a
 #pragma unroll
     for (int p = 0; p < 4; p++) {
         const int a = PA[p], b = PB[p];
+        if (!in_half(H, a)) continue;
         const float eD = edot(a, Dx, Dy);
         const float q = fmaf(4.5f * eD, edot(a, Sx, Sy), -C) * m.ir;   // the same for e_b
         out[a] = WT[a] * fmaf(3.f, eD, q);
@@ -308,16 +313,18 @@ __device__ inline void eq_delta_same_rho(const Macro &m, float jsx, float jsy, f
 // f_eq(rho*, j*) - f_eq(rho, j) (Eq. 3) for a density rho* = rho0 + drs: the
 // reference terms cancel, leaving
 // w [(rho* - rho) + 3 e.(j* - j) + (4.5 (e.j*)^2 - 1.5 |j*|^2) / rho* - (4.5 (e.j)^2 - 1.5 |j|^2) / rho].
+template <int H>
 __device__ inline void eq_delta(const Macro &m, float drs, float rs, float jsx, float jsy, float out[Q]) {
     const float irs = frcp(rs);
     const float jjs = 1.5f * fmaf(jsx, jsx, jsy * jsy), jj = 1.5f * fmaf(m.jx, m.jx, m.jy * m.jy);
     const float dd = drs - m.drho;
     const float dx = jsx - m.jx, dy = jsy - m.jy;
-    out[0] = WT[0] * (dd + fmaf(-jjs, irs, jj * m.ir));
+    if (H < 0) out[0] = WT[0] * (dd + fmaf(-jjs, irs, jj * m.ir));
     constexpr int PA[4] = {1, 2, 5, 6}, PB[4] = {3, 4, 7, 8};
 #pragma unroll
     for (int p = 0; p < 4; p++) {
         const int a = PA[p], b = PB[p];
+        if (!in_half(H, a)) continue;
         const float es = edot(a, jsx, jsy), ej = edot(a, m.jx, m.jy);
         const float q = fmaf(fmaf(4.5f * es, es, -jjs), irs, -(fmaf(4.5f * ej, ej, -jj) * m.ir));
         const float ed = edot(a, dx, dy);
@@ -330,16 +337,18 @@ __device__ inline void eq_delta(const Macro &m, float drs, float rs, float jsx, 
 // own value, phi_k - h.  A wall, an inlet and an internal-density outlet set
 // phi_k = f_eq(rho*, j*) + (h - f_eq(rho, j)), so the difference is that of two
 // equilibria, formed directly; a symmetry ghost is an equilibrium itself.
+// H >= 0: only the directions of half H (opposite directions share a half).
+template <int H = -1>
 __device__ inline void boundary_delta(const GroupDev &g, const float h[Q], const Macro &m, float2 gn,
                                       const RefDev &r, float out[Q]) {
     switch (g.kind) {
     case FVLBM_BC_WALL:                 // Eq. 18: rho* = rho_k, u* = u_w
-        eq_delta_same_rho(m, m.rho * g.ux, m.rho * g.uy, out);
+        eq_delta_same_rho<H>(m, m.rho * g.ux, m.rho * g.uy, out);
         break;
     case FVLBM_BC_INLET: {              // Eq. 19: rho* = rho_inf (external) or rho_k (internal)
         const float dr = g.internal ? m.drho : g.drho;
         const float rs = g.internal ? m.rho : g.rho;
-        eq_delta(m, dr, rs, rs * g.ux, rs * g.uy, out);
+        eq_delta<H>(m, dr, rs, rs * g.ux, rs * g.uy, out);
         break;
     }
     case FVLBM_BC_OUTLET:
@@ -347,16 +356,17 @@ __device__ inline void boundary_delta(const GroupDev &g, const float h[Q], const
 #pragma unroll
             for (int a = 0; a < Q; a++) out[a] = 0.f;
         } else {                        // Eq. 21: rho* = rho_inf, u* = u_i
-            eq_delta(m, g.drho, g.rho, g.rho * m.ux, g.rho * m.uy, out);
+            eq_delta<H>(m, g.drho, g.rho, g.rho * m.ux, g.rho * m.uy, out);
         }
         break;
     default: {                          // Eq. 22: mirrored normal velocity
         const float il = rsqrtf(gn.x * gn.x + gn.y * gn.y);
         const float nx = gn.x * il, ny = gn.y * il;
         const float jn = m.jx * nx + m.jy * ny;
-        heq(m.drho, m.rho, m.jx - 2.f * jn * nx, m.jy - 2.f * jn * ny, r, out);
+        heq<H>(m.drho, m.rho, m.jx - 2.f * jn * nx, m.jy - 2.f * jn * ny, r, out);
 #pragma unroll
-        for (int a = 0; a < Q; a++) out[a] -= h[a];
+        for (int a = 0; a < Q; a++)
+            if (a > 0 ? in_half(H, a) : H < 0) out[a] -= h[a];
         break;
     }
     }
@@ -386,6 +396,15 @@ __device__ inline int remap_block(int b, int nb, int xcd_remap) {
 }
 
 __device__ inline int unpack16(uint32_t w, int hi) { return (int)(int16_t)(hi ? (w >> 16) : (w & 0xffffu)); }
+
+// The 64-cell halo-wave form with per-value storage splits phase 2 and 3 by
+// directions over more waves.
+constexpr bool split_form(int T, int STORE, bool RING) { return RING && T == 64 && STORE != FVLBM_STORE_I16_DEV; }
+// Threads per workgroup of a stage kernel: the tile's cells, a wave for the halo
+// slots (RING), two waves for directions 5-8 of the gradients (split form).
+constexpr int tile_threads(int T, int STORE, bool RING) {
+    return T + (RING ? 64 : 0) + (split_form(T, STORE, RING) ? 128 : 0);
+}
 
 // v[k] from registers by selects (no dynamic register indexing; k may differ
 // between lanes)
@@ -475,11 +494,17 @@ __device__ inline void rd_g(const float4 *rec, float gx[Q], float gy[Q]) {
     gx[5] = c.x; gy[5] = c.y; gx[6] = c.z; gy[6] = c.w;
     gx[7] = d.x; gy[7] = d.y; gx[8] = d.z; gy[8] = d.w;
 }
+// H >= 0: the gradients of half H only (directions 1-4 or 5-8)
+template <int H = -1>
 __device__ inline void wr_g(float4 *rec, const float gx[Q], const float gy[Q]) {
-    rec[2] = make_float4(gx[1], gy[1], gx[2], gy[2]);
-    rec[3] = make_float4(gx[3], gy[3], gx[4], gy[4]);
-    rec[4] = make_float4(gx[5], gy[5], gx[6], gy[6]);
-    rec[5] = make_float4(gx[7], gy[7], gx[8], gy[8]);
+    if (H != 1) {
+        rec[2] = make_float4(gx[1], gy[1], gx[2], gy[2]);
+        rec[3] = make_float4(gx[3], gy[3], gx[4], gy[4]);
+    }
+    if (H != 0) {
+        rec[4] = make_float4(gx[5], gy[5], gx[6], gy[6]);
+        rec[5] = make_float4(gx[7], gy[7], gx[8], gy[8]);
+    }
 }
 
 // Boundary-slot terms of the gradient of cell c: phi_k is the wall / ghost
@@ -489,8 +514,9 @@ __device__ inline void wr_g(float4 *rec, const float gx[Q], const float gy[Q]) {
 // SAVE: phi_k - h_c of the first boundary slot is kept (save, save_k) for the
 // cell's boundary flux, which forms the same values from the same state.
 // STASH: phi_k - h_c of every boundary slot k also goes to stash[2k], stash[2k + 1]
-// (directions 1-4, 5-8), for a flux computed by another wave.
-template <int NF, bool SAVE, bool STASH>
+// (directions 1-4, 5-8), for a flux computed by another wave.  H >= 0: only the
+// directions of half H.
+template <int NF, bool SAVE, bool STASH, int H>
 __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                               uint2 packed, uint32_t bm, const GroupDev *lg, float gx[Q], float gy[Q],
                                               float save[Q], int &save_k, float4 *stash) {
@@ -507,18 +533,20 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
         const float2 gn = dk;
         const GroupDev g = lg[-1 - ck];
         float df[Q];
-        boundary_delta(g, hc, m, gn, d.ref, df);
+        boundary_delta<H>(g, hc, m, gn, d.ref, df);
         if (SAVE && save_k < 0) {
             save_k = k;
 #pragma unroll
-            for (int a = 1; a < Q; a++) save[a] = df[a];
+            for (int a = 1; a < Q; a++)
+                if (in_half(H, a)) save[a] = df[a];
         }
         if (STASH) {
-            stash[2 * k] = make_float4(df[1], df[2], df[3], df[4]);
-            stash[2 * k + 1] = make_float4(df[5], df[6], df[7], df[8]);
+            if (H != 1) stash[2 * k] = make_float4(df[1], df[2], df[3], df[4]);
+            if (H != 0) stash[2 * k + 1] = make_float4(df[5], df[6], df[7], df[8]);
         }
 #pragma unroll
         for (int a = 1; a < Q; a++) {
+            if (!in_half(H, a)) continue;
             gx[a] = fmaf(w.x, df[a], gx[a]);
             gy[a] = fmaf(w.y, df[a], gy[a]);
         }
@@ -528,8 +556,8 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
 // Gradient of cell c (Eq. 12) from staged values: sum_k M^-1 w_k d_k (phi_k - h_c),
 // phi_k the staged value of local cell code[k] (interior slots first, then
 // boundary slots).  Local indices below `a_end` are region-A records, the rest
-// region B.
-template <int NF, bool SAVE, bool STASH>
+// region B.  H >= 0: only the directions of half H.
+template <int NF, bool SAVE, bool STASH, int H>
 __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                        const int (&code)[NF], uint2 packed, const float4 *A, const float4 *B, int a_end,
                                        const GroupDev *lg, float gx[Q], float gy[Q], float save[Q], int &save_k,
@@ -549,12 +577,13 @@ __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo
         rd_f(l < a_end ? A + l * RA : B + (l - a_end) * RB, phi);
 #pragma unroll
         for (int a = 1; a < Q; a++) {
+            if (!in_half(H, a)) continue;
             const float df = phi[a] - hc[a];
             gx[a] = fmaf(w.x, df, gx[a]);
             gy[a] = fmaf(w.y, df, gy[a]);
         }
     }
-    if (bm) boundary_gradient_body<NF, SAVE, STASH>(d, geo, hc, packed, bm, lg, gx, gy, save, save_k, stash);
+    if (bm) boundary_gradient_body<NF, SAVE, STASH, H>(d, geo, hc, packed, bm, lg, gx, gy, save, save_k, stash);
 }
 
 // Boundary-face terms of the flux sum of tile cell i (Eqs. 18, 23-26); bm as in
@@ -764,17 +793,28 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // owns the halo slots, so halo loads and ring-1 gradients run beside the
     // tile's own; otherwise thread t owns tile cell t and halo slot t.
     constexpr int RS = RING ? 64 : T;                 // halo slots per pass
-    // With 64-cell tiles the halo wave also takes the diagonal directions of the
-    // tile's phase-3 update (lane l: cell l), the tile's wave the others.
-    constexpr bool SPLIT3 = RING && T == 64 && STORE != FVLBM_STORE_I16_DEV;
+    // With 64-cell tiles (SPLIT3) the halo wave also takes directions 5-8 of the
+    // tile's phase-3 update (lane l: cell l), the tile's wave the others; and two
+    // more waves form directions 5-8 of the phase-2 gradients, one for the tile's
+    // cells (thread T + 64 + l: cell l), one for the ring-1 slots (thread
+    // T + 128 + s: slot s), the tile and halo waves directions 1-4.  Opposite
+    // directions share a half, so every value is the one the whole pass forms.
+    constexpr bool SPLIT3 = split_form(T, STORE, RING);
+    constexpr int GA = SPLIT3 ? 0 : -1;               // gradient half of the tile and halo waves
     // SPLIT3: phi_k - h of the tile cells' boundary slots, formed in phase 2 by
-    // the tile's wave, staged for the halo wave's half of phase 3 (and for the
-    // tile wave's slots after the first)
+    // the tile's waves (each its half), staged for the halo wave's half of phase 3
+    // (and for the tile wave's slots after the first)
     __shared__ float4 lstash[SPLIT3 ? T * NF * 2 : 1];
-    const bool ownw = !RING || __builtin_amdgcn_readfirstlane(tid) < T;   // (wave-uniform)
-    const int rj = RING ? tid - T : tid;              // this thread's halo slot (< 0: none)
+    const int wtid = RING ? __builtin_amdgcn_readfirstlane(tid) : 0;   // (wave-uniform)
+    const bool ownw = !RING || wtid < T;                               // the tile's cells
+    const bool ownb = SPLIT3 && wtid >= T + 64 && wtid < T + 128;      // their directions 5-8
+    const bool halob = SPLIT3 && wtid >= T + 128;                      // ring-1 directions 5-8
+    const bool halow = RING && !ownw && !ownb && !halob;               // the halo slots
+    const int rj = !RING ? tid : halow ? tid - T : halob ? tid - T - 128 : -1;   // halo slot (< 0: none)
+    const int ob = tid - T - 64;                      // ownb: this thread's tile cell
     const int i = tile * T + tid;
     const bool valid = ownw && i < n_cells;
+    const bool validb = ownb && tile * T + ob < n_cells;
     const int a_end = T + h1s;                     // local indices below this are region A
     const int *hidx = halo_idx + (size_t)tile * (size_t)(h1s + h2s);
 
@@ -801,33 +841,46 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         geo.load(dxy, np, ic);
         cf.load(vxy, np, ic);
     }
-    if (RING && !ownw)
+    if (SPLIT3 && ownb) {                             // the cell's h0 and stencil
+        const int icb = validb ? tile * T + ob : 0;
+        load_cell<STORE>(src, np, icb, f, d.ref, 0, 1);
+        ln = ldo<uint2>(lnbr, (uint32_t)icb * 8u);
+        geo.load(dxy, np, icb);
+    }
+    if (halow)
         hraw1 = ldg(hidx, rj < hs ? rj : 0), hraw2 = ldg(hidx, h1s + rj < hs ? h1s + rj : 0);
+    if (SPLIT3 && halob) hraw1 = ldg(hidx, rj < hs ? rj : 0);
     const int i3 = tile * T + rj;                     // SPLIT3: this halo lane's tile cell
-    const bool valid3 = SPLIT3 && !ownw && i3 < n_cells;
-    if (SPLIT3 && !ownw) {                            // (one level, beside the halo chain)
+    const bool valid3 = SPLIT3 && halow && i3 < n_cells;
+    if (SPLIT3 && halow) {                            // (one level, beside the halo chain)
         const int ic3 = valid3 ? i3 : 0;
         load_cell<STORE>(src, np, ic3, f, d.ref, 0, 1);
         ln = ldo<uint2>(lnbr, (uint32_t)ic3 * 8u);
         geo.load(dxy, np, ic3);
         cf.load(vxy, np, ic3);
     }
+    const bool rin2 = rin && !halob;                  // this thread stages halo values
     const int c1 = rin && rj < h1s ? hraw1 : -1;
-    const int c2 = rin && rj < h2s ? hraw2 : -1;
+    const int c2 = rin2 && rj < h2s ? hraw2 : -1;
     int hcode[NF];
     float hf0 = 0.f, f1[Q], f2[Q];
     CellGeo<NF> hgeo;
     uint2 hl = make_uint2(0u, 0u);
-    if (!RING || !ownw) {
+    if (!RING || halow) {
         load_cell<STORE>(src, np, c1 >= 0 ? c1 : 0, f1, d.ref);
         hgeo.load(dxy, np, c1 >= 0 ? c1 : 0);
         load_cell<STORE>(src, np, c2 >= 0 ? c2 : 0, f2, d.ref, 1);
         hl = ldg(halo_code, (size_t)tile * h1s + (rin && rj < h1s ? rj : 0));
     }
+    if (SPLIT3 && halob) {                            // the ring-1 cell's h0 and stencil
+        load_cell<STORE>(src, np, c1 >= 0 ? c1 : 0, f1, d.ref, 0, 1);
+        hgeo.load(dxy, np, c1 >= 0 ? c1 : 0);
+        hl = ldg(halo_code, (size_t)tile * h1s + (rin && rj < h1s ? rj : 0));
+    }
     // the instance's boundary groups, staged in LDS for the boundary slots (read
     // whole, without waiting for the group count)
     __shared__ GroupDev lg[MAX_GROUPS];
-    constexpr int BS = T + (RING ? 64 : 0);           // threads per block
+    constexpr int BS = tile_threads(T, STORE, RING);  // threads per block
     constexpr int GW = MAX_GROUPS * (int)(sizeof(GroupDev) / sizeof(int));
     const int *gsrc = reinterpret_cast<const int *>(d.groups);
     const int gv0 = ldg(gsrc, tid < GW ? tid : 0);
@@ -841,17 +894,22 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
         geo.invert(code);
         cf.finish();
-    } else if (SPLIT3) {
+    } else if (SPLIT3 && halow) {
         if (sep_base) load_cell<STORE>(basep, np, valid3 ? i3 : 0, base, d.ref, 5, Q);
         h0 = f[0];
 #pragma unroll
         for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
         cf.finish();
+    } else if (SPLIT3 && ownb) {
+        h0 = f[0];
+#pragma unroll
+        for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
+        geo.invert(code);
     }
     if (valid) wr_f(A + tid * RA, f);
     if (c1 >= 0) {
         hf0 = f1[0];
-        wr_f(A + (T + rj) * RA, f1);
+        if (!halob) wr_f(A + (T + rj) * RA, f1);
 #pragma unroll
         for (int k = 0; k < NF; k++) hcode[k] = unpack16(k < 2 ? hl.x : hl.y, k & 1);
         hgeo.invert(hcode);
@@ -859,14 +917,14 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     if (c2 >= 0) wr_f(B + rj * RB, f2);
     if (tid < GW) reinterpret_cast<int *>(lg)[tid] = gv0;
     if (BS < GW && tid + BS < GW) reinterpret_cast<int *>(lg)[tid + BS] = gv1;
-    for (int k = rin ? rj + RS : h1s; k < h1s; k += RS) {   // ring 1 larger than a pass
+    for (int k = rin2 ? rj + RS : h1s; k < h1s; k += RS) {   // ring 1 larger than a pass
         const int c = ldg(hidx, k);
         if (c < 0) continue;
         float g[Q];
         load_cell<STORE>(src, np, c, g, d.ref, 1);
         wr_f(A + (T + k) * RA, g);
     }
-    for (int k = rin ? rj + RS : h2s; k < h2s; k += RS) {   // ring 2 larger than a pass
+    for (int k = rin2 ? rj + RS : h2s; k < h2s; k += RS) {   // ring 2 larger than a pass
         const int c = ldg(hidx, h1s + k);
         if (c < 0) continue;
         float g[Q];
@@ -885,15 +943,30 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         if (valid) {
             hc[0] = h0;
             rd_f(A + tid * RA, hc);
-            gradient_staged<NF, true, SPLIT3>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, bsave, bsave_k,
-                                              lstash + tid * NF * 2);
-            wr_g(A + tid * RA, gx, gy);
+            gradient_staged<NF, true, SPLIT3, GA>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, bsave, bsave_k,
+                                                  lstash + tid * NF * 2);
+            wr_g<GA>(A + tid * RA, gx, gy);
         }
+        if constexpr (SPLIT3)
+            if (validb) {
+                hc[0] = h0;
+                rd_f(A + ob * RA, hc);
+                gradient_staged<NF, false, true, 1>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, hc, no_k,
+                                                    lstash + ob * NF * 2);
+                wr_g<1>(A + ob * RA, gx, gy);
+            }
         if (c1 >= 0) {
             hc[0] = hf0;
             rd_f(A + (T + rj) * RA, hc);
-            gradient_staged<NF, false, false>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy, hc, no_k, nullptr);
-            wr_g(A + (T + rj) * RA, gx, gy);
+            if (SPLIT3 && halob) {
+                gradient_staged<NF, false, false, 1>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy, hc, no_k,
+                                                     nullptr);
+                wr_g<1>(A + (T + rj) * RA, gx, gy);
+            } else {
+                gradient_staged<NF, false, false, GA>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy, hc, no_k,
+                                                      nullptr);
+                wr_g<GA>(A + (T + rj) * RA, gx, gy);
+            }
         }
         for (int k = rin ? rj + RS : h1s; k < h1s; k += RS) {
             const int c = ldg(hidx, k);
@@ -907,12 +980,17 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
             g2.invert(cc);
             {
                 float t[Q];
-                load_cell<STORE>(src, np, c, t, d.ref);
+                load_cell<STORE>(src, np, c, t, d.ref, 0, 1);
                 hc[0] = t[0];
             }
             rd_f(A + (T + k) * RA, hc);
-            gradient_staged<NF, false, false>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy, hc, no_k, nullptr);
-            wr_g(A + (T + k) * RA, gx, gy);
+            if (SPLIT3 && halob) {
+                gradient_staged<NF, false, false, 1>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy, hc, no_k, nullptr);
+                wr_g<1>(A + (T + k) * RA, gx, gy);
+            } else {
+                gradient_staged<NF, false, false, GA>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy, hc, no_k, nullptr);
+                wr_g<GA>(A + (T + k) * RA, gx, gy);
+            }
         }
     }
     __syncthreads();
@@ -937,7 +1015,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
 // (Arguments in the order the kernel needs them: the first sixteen dwords arrive in
 // scalar registers.)
 template <int NF, int STORE, int T, bool DIRECT, bool M0, bool RING>
-__global__ void __launch_bounds__(T + (RING ? 64 : 0)) k_tile(const int *hot_halo_idx, const void *hot_src, const uint2 *hot_lnbr,
+__global__ void __launch_bounds__(tile_threads(T, STORE, RING)) k_tile(const int *hot_halo_idx, const void *hot_src, const uint2 *hot_lnbr,
                                             const float2 *hot_dxy, const float2 *hot_vxy, int hot_h12, int hot_np,
                                             int hot_n_cells, int units_x, const uint2 *hot_halo_code, const void *hot_base,
                                             const InstDesc *__restrict__ descs, int nA,
@@ -1069,7 +1147,7 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
         hipError_t e = hipFuncSetAttribute(fn_ptr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    return hipLaunchKernel(fn_ptr, dim3(grid_blocks(ut, persistent, nf, storage, lds)), dim3(ut.block + (ring ? 64 : 0)),
+    return hipLaunchKernel(fn_ptr, dim3(grid_blocks(ut, persistent, nf, storage, lds)), dim3(tile_threads(ut.block, storage, ring)),
                            args, lds, stream);
 }
 
@@ -1096,7 +1174,7 @@ hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode
         if (e != hipSuccess) return e;
     }
     p.gridDim = dim3(grid_blocks(ut, persistent, nf, storage, lds));
-    p.blockDim = dim3(ut.block + (ring ? 64 : 0));
+    p.blockDim = dim3(tile_threads(ut.block, storage, ring));
     p.sharedMemBytes = (unsigned)lds;
     p.kernelParams = kp;
     p.extra = nullptr;
