@@ -473,22 +473,25 @@ struct CellFaces {
 };
 
 // LDS records.  Region A holds tile and ring-1 cells, 24 floats each:
-// h1..h8, (gx1,gy1)..(gx8,gy8); region B holds ring-2 cells, 8 floats each:
-// h1..h8.  Records are 16-byte aligned and read with 128-bit LDS loads.
+// h1..h8, (gx1,gy1)..(gx8,gy8), as six float4 planes (float4 c of record l at
+// A[c nA + l]), so that the lanes of a wave reading their own records touch
+// consecutive addresses (no bank conflicts); region B holds ring-2 cells, 8
+// floats each: h1..h8, as consecutive float4 (read at random positions only).
+// Every access is a 128-bit LDS load or store; s is the record's float4 stride.
 constexpr int RA = 6;   // float4 per region-A record
 constexpr int RB = 2;   // float4 per region-B record
 
-__device__ inline void rd_f(const float4 *rec, float f[Q]) {
-    const float4 x = rec[0], y = rec[1];
+__device__ inline void rd_f(const float4 *rec, int s, float f[Q]) {
+    const float4 x = rec[0], y = rec[s];
     f[1] = x.x; f[2] = x.y; f[3] = x.z; f[4] = x.w;
     f[5] = y.x; f[6] = y.y; f[7] = y.z; f[8] = y.w;
 }
-__device__ inline void wr_f(float4 *rec, const float f[Q]) {
+__device__ inline void wr_f(float4 *rec, int s, const float f[Q]) {
     rec[0] = make_float4(f[1], f[2], f[3], f[4]);
-    rec[1] = make_float4(f[5], f[6], f[7], f[8]);
+    rec[s] = make_float4(f[5], f[6], f[7], f[8]);
 }
-__device__ inline void rd_g(const float4 *rec, float gx[Q], float gy[Q]) {
-    const float4 a = rec[2], b = rec[3], c = rec[4], d = rec[5];
+__device__ inline void rd_g(const float4 *rec, int s, float gx[Q], float gy[Q]) {
+    const float4 a = rec[2 * s], b = rec[3 * s], c = rec[4 * s], d = rec[5 * s];
     gx[1] = a.x; gy[1] = a.y; gx[2] = a.z; gy[2] = a.w;
     gx[3] = b.x; gy[3] = b.y; gx[4] = b.z; gy[4] = b.w;
     gx[5] = c.x; gy[5] = c.y; gx[6] = c.z; gy[6] = c.w;
@@ -496,14 +499,14 @@ __device__ inline void rd_g(const float4 *rec, float gx[Q], float gy[Q]) {
 }
 // H >= 0: the gradients of half H only (directions 1-4 or 5-8)
 template <int H = -1>
-__device__ inline void wr_g(float4 *rec, const float gx[Q], const float gy[Q]) {
+__device__ inline void wr_g(float4 *rec, int s, const float gx[Q], const float gy[Q]) {
     if (H != 1) {
-        rec[2] = make_float4(gx[1], gy[1], gx[2], gy[2]);
-        rec[3] = make_float4(gx[3], gy[3], gx[4], gy[4]);
+        rec[2 * s] = make_float4(gx[1], gy[1], gx[2], gy[2]);
+        rec[3 * s] = make_float4(gx[3], gy[3], gx[4], gy[4]);
     }
     if (H != 0) {
-        rec[4] = make_float4(gx[5], gy[5], gx[6], gy[6]);
-        rec[5] = make_float4(gx[7], gy[7], gx[8], gy[8]);
+        rec[4 * s] = make_float4(gx[5], gy[5], gx[6], gy[6]);
+        rec[5 * s] = make_float4(gx[7], gy[7], gx[8], gy[8]);
     }
 }
 
@@ -513,13 +516,13 @@ __device__ inline void wr_g(float4 *rec, const float gx[Q], const float gy[Q]) {
 // makes as many passes as its lane with the most boundary faces), in slot order.
 // SAVE: phi_k - h_c of the first boundary slot is kept (save, save_k) for the
 // cell's boundary flux, which forms the same values from the same state.
-// STASH: phi_k - h_c of every boundary slot k also goes to stash[2k], stash[2k + 1]
-// (directions 1-4, 5-8), for a flux computed by another wave.  H >= 0: only the
-// directions of half H.
+// STASH: phi_k - h_c of every boundary slot k also goes to stash[2k ss],
+// stash[(2k + 1) ss] (directions 1-4, 5-8), for a flux computed by another wave.
+// H >= 0: only the directions of half H.
 template <int NF, bool SAVE, bool STASH, int H>
 __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                               uint2 packed, uint32_t bm, const GroupDev *lg, float gx[Q], float gy[Q],
-                                              float save[Q], int &save_k, float4 *stash) {
+                                              float save[Q], int &save_k, float4 *stash, int ss) {
     const Macro m = moments(hc, d.ref);
 #pragma unroll 1
     for (uint32_t b = bm; b != 0u; b &= b - 1u) {
@@ -541,8 +544,8 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
                 if (in_half(H, a)) save[a] = df[a];
         }
         if (STASH) {
-            if (H != 1) stash[2 * k] = make_float4(df[1], df[2], df[3], df[4]);
-            if (H != 0) stash[2 * k + 1] = make_float4(df[5], df[6], df[7], df[8]);
+            if (H != 1) stash[2 * k * ss] = make_float4(df[1], df[2], df[3], df[4]);
+            if (H != 0) stash[(2 * k + 1) * ss] = make_float4(df[5], df[6], df[7], df[8]);
         }
 #pragma unroll
         for (int a = 1; a < Q; a++) {
@@ -555,13 +558,13 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
 
 // Gradient of cell c (Eq. 12) from staged values: sum_k M^-1 w_k d_k (phi_k - h_c),
 // phi_k the staged value of local cell code[k] (interior slots first, then
-// boundary slots).  Local indices below `a_end` are region-A records, the rest
-// region B.  H >= 0: only the directions of half H.
+// boundary slots).  Local indices below `a_end` are region-A records (plane
+// stride sa), the rest region B.  H >= 0: only the directions of half H.
 template <int NF, bool SAVE, bool STASH, int H>
 __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                        const int (&code)[NF], uint2 packed, const float4 *A, const float4 *B, int a_end,
                                        const GroupDev *lg, float gx[Q], float gy[Q], float save[Q], int &save_k,
-                                       float4 *stash) {
+                                       float4 *stash, int ss, int sa) {
 #pragma unroll
     for (int a = 1; a < Q; a++) { gx[a] = 0.f; gy[a] = 0.f; }
     uint32_t bm = 0u;                     // boundary slots (padded slots have no face)
@@ -574,7 +577,7 @@ __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo
         const float2 w = lsq_coef(geo.dk[k], geo.m11, geo.m12, geo.m22);
         const int l = code[k];
         float phi[Q];
-        rd_f(l < a_end ? A + l * RA : B + (l - a_end) * RB, phi);
+        rd_f(l < a_end ? A + l : B + (l - a_end) * RB, l < a_end ? sa : 1, phi);
 #pragma unroll
         for (int a = 1; a < Q; a++) {
             if (!in_half(H, a)) continue;
@@ -583,7 +586,7 @@ __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo
             gy[a] = fmaf(w.y, df, gy[a]);
         }
     }
-    if (bm) boundary_gradient_body<NF, SAVE, STASH, H>(d, geo, hc, packed, bm, lg, gx, gy, save, save_k, stash);
+    if (bm) boundary_gradient_body<NF, SAVE, STASH, H>(d, geo, hc, packed, bm, lg, gx, gy, save, save_k, stash, ss);
 }
 
 // Boundary-face terms of the flux sum of tile cell i (Eqs. 18, 23-26); bm as in
@@ -593,7 +596,7 @@ template <int NF, int H, bool STASH>
 __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const float gxi[Q], const float gyi[Q],
                                      const Macro &mi, uint2 packed, uint32_t bm,
                                      const CellGeo<NF> &geo, const CellFaces<NF> &cf, const GroupDev *lg,
-                                     const float save[Q], int save_k, const float4 *stash, float acc[Q]) {
+                                     const float save[Q], int save_k, const float4 *stash, int ss, float acc[Q]) {
 #pragma unroll 1
     for (uint32_t b = bm; b != 0u; b &= b - 1u) {
         const int k = __builtin_ctz(b);
@@ -608,11 +611,11 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
             for (int a = 1; a < Q; a++) dv[a] = save[a];
         } else if (STASH) {
             if (H != 1) {
-                const float4 x = stash[2 * k];
+                const float4 x = stash[2 * k * ss];
                 dv[1] = x.x; dv[2] = x.y; dv[3] = x.z; dv[4] = x.w;
             }
             if (H != 0) {
-                const float4 y = stash[2 * k + 1];
+                const float4 y = stash[(2 * k + 1) * ss];
                 dv[5] = y.x; dv[6] = y.y; dv[7] = y.z; dv[8] = y.w;
             }
         } else {          // (the normal direction from the slot offset, as in the gradient)
@@ -648,12 +651,12 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
 template <int NF, int STORE, bool M0, int H, bool STASH>
 __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, const float base[Q], bool sep_base,
                                             const int (&code)[NF], uint2 packed, const CellGeo<NF> &geo, const CellFaces<NF> &cf,
-                                            const float4 *own, const float4 *A, const GroupDev *lg,
-                                            const float bsave[Q], int bsave_k, const float4 *stash) {
+                                            const float4 *own, const float4 *A, int sa, const GroupDev *lg,
+                                            const float bsave[Q], int bsave_k, const float4 *stash, int ss) {
     float hi[Q], gxi[Q], gyi[Q];
     hi[0] = h0;
-    rd_f(own, hi);
-    rd_g(own, gxi, gyi);
+    rd_f(own, sa, hi);
+    rd_g(own, sa, gxi, gyi);
     const Macro mi = moments(hi, d.ref);
     float hei[Q];
     heq(mi.drho, mi.rho, mi.jx, mi.jy, d.ref, hei);
@@ -671,10 +674,10 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
         const float2 g = scaled_normal(v0, v1, cf.inva);
         const float2 r = make_float2(0.5f * (v0.x + v1.x), 0.5f * (v0.y + v1.y));   // x_f - x_i
         const float2 q = make_float2(r.x - geo.dk[k].x, r.y - geo.dk[k].y);       // x_f - x_j
-        const float4 *rec = A + code[k] * RA;                                     // neighbours are in region A
+        const float4 *rec = A + code[k];                                          // neighbours are in region A
         float hj[Q], gxj[Q], gyj[Q];
-        rd_f(rec, hj);
-        rd_g(rec, gxj, gyj);
+        rd_f(rec, sa, hj);
+        rd_g(rec, sa, gxj, gyj);
         // upwind side (Eq. 11): one comparison per pair of opposite directions, whose
         // e.n differ in sign only (where e.n = 0 the choice is multiplied by zero)
         bool up[Q];
@@ -695,7 +698,7 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
             acc[a] = fmaf(en, up[a] ? own_v : nb_v, acc[a]);
         }
     }
-    if (bm) boundary_flux<NF, H, STASH>(d, hi, gxi, gyi, mi, packed, bm, geo, cf, lg, bsave, bsave_k, stash, acc);
+    if (bm) boundary_flux<NF, H, STASH>(d, hi, gxi, gyi, mi, packed, bm, geo, cf, lg, bsave, bsave_k, stash, ss, acc);
 
     // The BGK source moves no mass and no momentum: f_eq carries the density and
     // momentum of f (Eqs. 3, 5).  In FP32 the rounding of f_eq (terms near 0.05,
@@ -770,7 +773,7 @@ struct Hot {
 // region-B records for the largest ring-2 slot count (sized by the launcher).
 template <int NF, int STORE, int T, bool DIRECT, bool M0, bool RING>
 __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, int2 u, const Hot &hot, float4 *A,
-                                          float4 *B) {
+                                          int sa, float4 *B) {
     const InstDesc &d = descs[u.x];
     // Two descriptor lines (reference state and update coefficients) are first
     // needed in phases 2 and 3; one word of each is read here, so that their
@@ -803,7 +806,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     constexpr int GA = SPLIT3 ? 0 : -1;               // gradient half of the tile and halo waves
     // SPLIT3: phi_k - h of the tile cells' boundary slots, formed in phase 2 by
     // the tile's waves (each its half), staged for the halo wave's half of phase 3
-    // (and for the tile wave's slots after the first)
+    // (and for the tile wave's slots after the first): float4 planes of T cells
     __shared__ float4 lstash[SPLIT3 ? T * NF * 2 : 1];
     const int wtid = RING ? __builtin_amdgcn_readfirstlane(tid) : 0;   // (wave-uniform)
     const bool ownw = !RING || wtid < T;                               // the tile's cells
@@ -906,15 +909,15 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
         geo.invert(code);
     }
-    if (valid) wr_f(A + tid * RA, f);
+    if (valid) wr_f(A + tid, sa, f);
     if (c1 >= 0) {
         hf0 = f1[0];
-        if (!halob) wr_f(A + (T + rj) * RA, f1);
+        if (!halob) wr_f(A + T + rj, sa, f1);
 #pragma unroll
         for (int k = 0; k < NF; k++) hcode[k] = unpack16(k < 2 ? hl.x : hl.y, k & 1);
         hgeo.invert(hcode);
     }
-    if (c2 >= 0) wr_f(B + rj * RB, f2);
+    if (c2 >= 0) wr_f(B + rj * RB, 1, f2);
     if (tid < GW) reinterpret_cast<int *>(lg)[tid] = gv0;
     if (BS < GW && tid + BS < GW) reinterpret_cast<int *>(lg)[tid + BS] = gv1;
     for (int k = rin2 ? rj + RS : h1s; k < h1s; k += RS) {   // ring 1 larger than a pass
@@ -922,14 +925,14 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         if (c < 0) continue;
         float g[Q];
         load_cell<STORE>(src, np, c, g, d.ref, 1);
-        wr_f(A + (T + k) * RA, g);
+        wr_f(A + T + k, sa, g);
     }
     for (int k = rin2 ? rj + RS : h2s; k < h2s; k += RS) {   // ring 2 larger than a pass
         const int c = ldg(hidx, h1s + k);
         if (c < 0) continue;
         float g[Q];
         load_cell<STORE>(src, np, c, g, d.ref, 1);
-        wr_f(B + k * RB, g);
+        wr_f(B + k * RB, 1, g);
     }
     asm volatile("" ::"s"(warm0), "s"(warm1));    // (keeps the two reads above)
     __syncthreads();
@@ -942,30 +945,30 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         int no_k = 0;
         if (valid) {
             hc[0] = h0;
-            rd_f(A + tid * RA, hc);
+            rd_f(A + tid, sa, hc);
             gradient_staged<NF, true, SPLIT3, GA>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, bsave, bsave_k,
-                                                  lstash + tid * NF * 2);
-            wr_g<GA>(A + tid * RA, gx, gy);
+                                                  lstash + tid, T, sa);
+            wr_g<GA>(A + tid, sa, gx, gy);
         }
         if constexpr (SPLIT3)
             if (validb) {
                 hc[0] = h0;
-                rd_f(A + ob * RA, hc);
+                rd_f(A + ob, sa, hc);
                 gradient_staged<NF, false, true, 1>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, hc, no_k,
-                                                    lstash + ob * NF * 2);
-                wr_g<1>(A + ob * RA, gx, gy);
+                                                    lstash + ob, T, sa);
+                wr_g<1>(A + ob, sa, gx, gy);
             }
         if (c1 >= 0) {
             hc[0] = hf0;
-            rd_f(A + (T + rj) * RA, hc);
+            rd_f(A + T + rj, sa, hc);
             if (SPLIT3 && halob) {
                 gradient_staged<NF, false, false, 1>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy, hc, no_k,
-                                                     nullptr);
-                wr_g<1>(A + (T + rj) * RA, gx, gy);
+                                                     nullptr, 0, sa);
+                wr_g<1>(A + T + rj, sa, gx, gy);
             } else {
                 gradient_staged<NF, false, false, GA>(d, hgeo, hc, hcode, hl, A, B, a_end, lg, gx, gy, hc, no_k,
-                                                      nullptr);
-                wr_g<GA>(A + (T + rj) * RA, gx, gy);
+                                                      nullptr, 0, sa);
+                wr_g<GA>(A + T + rj, sa, gx, gy);
             }
         }
         for (int k = rin ? rj + RS : h1s; k < h1s; k += RS) {
@@ -983,24 +986,26 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
                 load_cell<STORE>(src, np, c, t, d.ref, 0, 1);
                 hc[0] = t[0];
             }
-            rd_f(A + (T + k) * RA, hc);
+            rd_f(A + T + k, sa, hc);
             if (SPLIT3 && halob) {
-                gradient_staged<NF, false, false, 1>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy, hc, no_k, nullptr);
-                wr_g<1>(A + (T + k) * RA, gx, gy);
+                gradient_staged<NF, false, false, 1>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy, hc, no_k, nullptr, 0,
+                                                     sa);
+                wr_g<1>(A + T + k, sa, gx, gy);
             } else {
-                gradient_staged<NF, false, false, GA>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy, hc, no_k, nullptr);
-                wr_g<GA>(A + (T + k) * RA, gx, gy);
+                gradient_staged<NF, false, false, GA>(d, g2, hc, cc, hl2, A, B, a_end, lg, gx, gy, hc, no_k, nullptr,
+                                                      0, sa);
+                wr_g<GA>(A + T + k, sa, gx, gy);
             }
         }
     }
     __syncthreads();
     if (valid)
-        tile_update<NF, STORE, M0, SPLIT3 ? 0 : -1, SPLIT3>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid * RA,
-                                                            A, lg, bsave, bsave_k, lstash + tid * NF * 2);
+        tile_update<NF, STORE, M0, SPLIT3 ? 0 : -1, SPLIT3>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid,
+                                                            A, sa, lg, bsave, bsave_k, lstash + tid, T);
     if constexpr (SPLIT3)
         if (valid3)
-            tile_update<NF, STORE, M0, 1, SPLIT3>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj * RA, A, lg,
-                                                  bsave, -1, lstash + rj * NF * 2);
+            tile_update<NF, STORE, M0, 1, SPLIT3>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj, A, sa, lg,
+                                                  bsave, -1, lstash + rj, T);
 }
 
 // DIRECT: one instance whose unit b is tile b, the bases and sizes its loads
@@ -1025,7 +1030,7 @@ __global__ void __launch_bounds__(tile_threads(T, STORE, RING)) k_tile(const int
     const Hot hot{hot_src, hot_base, hot_halo_idx, hot_halo_code, hot_lnbr, hot_dxy, hot_vxy,
                   hot_np, hot_n_cells, hot_h12 & 0xffff, hot_h12 >> 16};
     tile_body<NF, STORE, T, DIRECT, M0, RING>(descs, (DIRECT || !units) ? make_int2(0, ub) : units[ub], hot, lds4,
-                                             lds4 + nA * RA);
+                                             nA, lds4 + nA * RA);
 }
 
 // (units null: a single instance whose unit b is tile b.)
@@ -1041,7 +1046,8 @@ __global__ void __launch_bounds__(T) k_tile_persistent(const int *, const void *
     const int n_units = units_x >> 1, xcd_remap = units_x & 1;
     for (int b = blockIdx.x; b < n_units; b += gridDim.x) {
         const int ub = remap_block(b, n_units, xcd_remap);
-        tile_body<NF, STORE, T, false, M0, false>(descs, units ? units[ub] : make_int2(0, ub), hot, lds4, lds4 + nA * RA);
+        tile_body<NF, STORE, T, false, M0, false>(descs, units ? units[ub] : make_int2(0, ub), hot, lds4, nA,
+                                                  lds4 + nA * RA);
         __syncthreads();             // the next unit reuses the LDS records
     }
 }
