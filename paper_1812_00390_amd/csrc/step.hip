@@ -207,11 +207,34 @@ __device__ inline void store_cell(void *buf, size_t np, int c, const float b[Q],
     }
 }
 
-// Direction halves of a split update: H = -1 all, 0 the rest and axis
-// directions (0-4), 1 the diagonal ones (5-8).
-__device__ constexpr bool in_half(int H, int a) { return H < 0 || (H == 0 ? a <= 4 : a >= 5); }
+// Direction sets of a split pass: H = -1 all; the halves 0 (directions 0-4)
+// and 1 (5-8); the quarters 2 (0, 1, 3), 3 (2, 4), 4 (5, 7) and 5 (6, 8).
+// Opposite directions always share a set.
+__device__ constexpr bool in_set(int H, int a) {
+    return H < 0 ? true
+         : H == 0 ? a <= 4
+         : H == 1 ? a >= 5
+         : H == 2 ? (a == 0 || a == 1 || a == 3)
+         : H == 3 ? (a == 2 || a == 4)
+         : H == 4 ? (a == 5 || a == 7)
+                  : (a == 6 || a == 8);
+}
+// the set holds directions among 1-4 / among 5-8
+__device__ constexpr bool has_lo(int H) { return H < 0 || H == 0 || H == 2 || H == 3; }
+__device__ constexpr bool has_hi(int H) { return H < 0 || H == 1 || H == 4 || H == 5; }
 
-// store_cell for the directions of half H (per-value storage modes only)
+// The values of the direction set H of cell c (per-value storage modes).
+template <int STORE, int H>
+__device__ inline void load_set(const void *buf, size_t np, int c, float f[Q], const RefDev &r) {
+    static_assert(STORE != FVLBM_STORE_I16_DEV, "the block-scaled format loads a cell whole");
+    using S = Storage<STORE>;
+    const uint32_t off = (uint32_t)c * S::SZ;
+#pragma unroll
+    for (int a = 0; a < Q; a++)
+        if (in_set(H, a)) f[a] = S::load(plane(buf, np * S::SZ, a), off, a, r);
+}
+
+// store_cell for the directions of set H (per-value storage modes only)
 template <int STORE, int H>
 __device__ inline void store_half(void *buf, size_t np, int c, const float b[Q], const float inc[Q], const RefDev &r,
                                   uint32_t key0) {
@@ -220,7 +243,7 @@ __device__ inline void store_half(void *buf, size_t np, int c, const float b[Q],
     const uint32_t off = (uint32_t)c * S::SZ;
 #pragma unroll
     for (int a = 0; a < Q; a++)
-        if (in_half(H, a)) S::store(plane(buf, np * S::SZ, a), off, a, b[a], inc[a], r, key0);
+        if (in_set(H, a)) S::store(plane(buf, np * S::SZ, a), off, a, b[a], inc[a], r, key0);
 }
 
 // e_a . (x, y) for the D2Q9 velocities, folded per direction (no products by 0)
@@ -266,7 +289,7 @@ __device__ inline Macro moments(const float h[Q], const RefDev &r) {
 
 // Eq. 3 as a deviation from the reference equilibrium, written with the momentum j = rho u:
 // f_eq(rho, u) - f_eq(rho0, u_dev) = w [ (rho - rho0) + 3 e.(j - j0) + (4.5 (e.j)^2 - 1.5 |j|^2)/rho - c0 ]
-// H >= 0: only the directions of half H (in_half), out[0] not formed.
+// H >= 0: only the directions of set H (in_set), out[0] not formed.
 template <int H = -1>
 __device__ inline void heq(float drho, float rho, float jx, float jy, const RefDev &r, float out[Q]) {
     const float ir = frcp(rho);
@@ -279,7 +302,7 @@ __device__ inline void heq(float drho, float rho, float jx, float jy, const RefD
 #pragma unroll
     for (int p = 0; p < 4; p++) {
         const int a = PA[p], b = PB[p];
-        if (!in_half(H, a)) continue;
+        if (!in_set(H, a)) continue;
         const float ej = edot(a, jx, jy);
         const float ed = edot(a, dx, dy);
         const float quad = fmaf(fmaf(4.5f * ej, ej, -jj), ir, -r.c0[a]);
@@ -302,7 +325,7 @@ __device__ inline void eq_delta_same_rho(const Macro &m, float jsx, float jsy, f
 #pragma unroll
     for (int p = 0; p < 4; p++) {
         const int a = PA[p], b = PB[p];
-        if (!in_half(H, a)) continue;
+        if (!in_set(H, a)) continue;
         const float eD = edot(a, Dx, Dy);
         const float q = fmaf(4.5f * eD, edot(a, Sx, Sy), -C) * m.ir;   // the same for e_b
         out[a] = WT[a] * fmaf(3.f, eD, q);
@@ -324,7 +347,7 @@ __device__ inline void eq_delta(const Macro &m, float drs, float rs, float jsx, 
 #pragma unroll
     for (int p = 0; p < 4; p++) {
         const int a = PA[p], b = PB[p];
-        if (!in_half(H, a)) continue;
+        if (!in_set(H, a)) continue;
         const float es = edot(a, jsx, jsy), ej = edot(a, m.jx, m.jy);
         const float q = fmaf(fmaf(4.5f * es, es, -jjs), irs, -(fmaf(4.5f * ej, ej, -jj) * m.ir));
         const float ed = edot(a, dx, dy);
@@ -337,7 +360,7 @@ __device__ inline void eq_delta(const Macro &m, float drs, float rs, float jsx, 
 // own value, phi_k - h.  A wall, an inlet and an internal-density outlet set
 // phi_k = f_eq(rho*, j*) + (h - f_eq(rho, j)), so the difference is that of two
 // equilibria, formed directly; a symmetry ghost is an equilibrium itself.
-// H >= 0: only the directions of half H (opposite directions share a half).
+// H >= 0: only the directions of set H (opposite directions share a set).
 template <int H = -1>
 __device__ inline void boundary_delta(const GroupDev &g, const float h[Q], const Macro &m, float2 gn,
                                       const RefDev &r, float out[Q]) {
@@ -366,7 +389,7 @@ __device__ inline void boundary_delta(const GroupDev &g, const float h[Q], const
         heq<H>(m.drho, m.rho, m.jx - 2.f * jn * nx, m.jy - 2.f * jn * ny, r, out);
 #pragma unroll
         for (int a = 0; a < Q; a++)
-            if (a > 0 ? in_half(H, a) : H < 0) out[a] -= h[a];
+            if (a > 0 ? in_set(H, a) : H < 0) out[a] -= h[a];
         break;
     }
     }
@@ -500,11 +523,11 @@ __device__ inline void rd_g(const float4 *rec, int s, float gx[Q], float gy[Q]) 
 // H >= 0: the gradients of half H only (directions 1-4 or 5-8)
 template <int H = -1>
 __device__ inline void wr_g(float4 *rec, int s, const float gx[Q], const float gy[Q]) {
-    if (H != 1) {
+    if (has_lo(H)) {
         rec[2 * s] = make_float4(gx[1], gy[1], gx[2], gy[2]);
         rec[3 * s] = make_float4(gx[3], gy[3], gx[4], gy[4]);
     }
-    if (H != 0) {
+    if (has_hi(H)) {
         rec[4 * s] = make_float4(gx[5], gy[5], gx[6], gy[6]);
         rec[5 * s] = make_float4(gx[7], gy[7], gx[8], gy[8]);
     }
@@ -518,7 +541,7 @@ __device__ inline void wr_g(float4 *rec, int s, const float gx[Q], const float g
 // cell's boundary flux, which forms the same values from the same state.
 // STASH: phi_k - h_c of every boundary slot k also goes to stash[2k ss],
 // stash[(2k + 1) ss] (directions 1-4, 5-8), for a flux computed by another wave.
-// H >= 0: only the directions of half H.
+// H >= 0: only the directions of set H.
 template <int NF, bool SAVE, bool STASH, int H>
 __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                               uint2 packed, uint32_t bm, const GroupDev *lg, float gx[Q], float gy[Q],
@@ -541,15 +564,15 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
             save_k = k;
 #pragma unroll
             for (int a = 1; a < Q; a++)
-                if (in_half(H, a)) save[a] = df[a];
+                if (in_set(H, a)) save[a] = df[a];
         }
         if (STASH) {
-            if (H != 1) stash[2 * k * ss] = make_float4(df[1], df[2], df[3], df[4]);
-            if (H != 0) stash[(2 * k + 1) * ss] = make_float4(df[5], df[6], df[7], df[8]);
+            if (has_lo(H)) stash[2 * k * ss] = make_float4(df[1], df[2], df[3], df[4]);
+            if (has_hi(H)) stash[(2 * k + 1) * ss] = make_float4(df[5], df[6], df[7], df[8]);
         }
 #pragma unroll
         for (int a = 1; a < Q; a++) {
-            if (!in_half(H, a)) continue;
+            if (!in_set(H, a)) continue;
             gx[a] = fmaf(w.x, df[a], gx[a]);
             gy[a] = fmaf(w.y, df[a], gy[a]);
         }
@@ -559,7 +582,7 @@ __device__ inline void boundary_gradient_body(const InstDesc &d, const CellGeo<N
 // Gradient of cell c (Eq. 12) from staged values: sum_k M^-1 w_k d_k (phi_k - h_c),
 // phi_k the staged value of local cell code[k] (interior slots first, then
 // boundary slots).  Local indices below `a_end` are region-A records (plane
-// stride sa), the rest region B.  H >= 0: only the directions of half H.
+// stride sa), the rest region B.  H >= 0: only the directions of set H.
 template <int NF, bool SAVE, bool STASH, int H>
 __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo, const float hc[Q],
                                        const int (&code)[NF], uint2 packed, const float4 *A, const float4 *B, int a_end,
@@ -580,7 +603,7 @@ __device__ inline void gradient_staged(const InstDesc &d, const CellGeo<NF> &geo
         rd_f(l < a_end ? A + l : B + (l - a_end) * RB, l < a_end ? sa : 1, phi);
 #pragma unroll
         for (int a = 1; a < Q; a++) {
-            if (!in_half(H, a)) continue;
+            if (!in_set(H, a)) continue;
             const float df = phi[a] - hc[a];
             gx[a] = fmaf(w.x, df, gx[a]);
             gy[a] = fmaf(w.y, df, gy[a]);
@@ -610,11 +633,11 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
 #pragma unroll
             for (int a = 1; a < Q; a++) dv[a] = save[a];
         } else if (STASH) {
-            if (H != 1) {
+            if (has_lo(H)) {
                 const float4 x = stash[2 * k * ss];
                 dv[1] = x.x; dv[2] = x.y; dv[3] = x.z; dv[4] = x.w;
             }
-            if (H != 0) {
+            if (has_hi(H)) {
                 const float4 y = stash[(2 * k + 1) * ss];
                 dv[5] = y.x; dv[6] = y.y; dv[7] = y.z; dv[8] = y.w;
             }
@@ -625,7 +648,7 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
         const bool upwind = kind == FVLBM_BC_INLET || (kind == FVLBM_BC_OUTLET && gr.internal);
 #pragma unroll
         for (int a = 1; a < Q; a++) {
-            if (!in_half(H, a)) continue;
+            if (!in_set(H, a)) continue;
             const float en = edot(a, g.x, g.y);
             const float bv = hi[a] + dv[a];
             float phi;
@@ -645,9 +668,8 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
 
 // Phase 3 for one tile cell: face values, flux sum, BGK source, update, store.
 // base[] holds f(0) of the update when it is not the evaluated state.  H >= 0:
-// only the directions of that half (a base + coef RHS update), the other half
-// being another wave's; every per-direction value is the one the whole update
-// forms.
+// only the directions of set H (a base + coef RHS update), the others being
+// other waves'; every per-direction value is the one the whole update forms.
 template <int NF, int STORE, bool M0, int H, bool STASH>
 __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, const float base[Q], bool sep_base,
                                             const int (&code)[NF], uint2 packed, const CellGeo<NF> &geo, const CellFaces<NF> &cf,
@@ -691,7 +713,7 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
         up[8] = !up[6];
 #pragma unroll
         for (int a = 1; a < Q; a++) {
-            if (!in_half(H, a)) continue;
+            if (!in_set(H, a)) continue;
             const float en = edot(a, g.x, g.y);
             const float own_v = fmaf(gyi[a], r.y, fmaf(gxi[a], r.x, hi[a]));
             const float nb_v = fmaf(gyj[a], q.y, fmaf(gxj[a], q.x, hj[a]));
@@ -796,18 +818,24 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // owns the halo slots, so halo loads and ring-1 gradients run beside the
     // tile's own; otherwise thread t owns tile cell t and halo slot t.
     constexpr int RS = RING ? 64 : T;                 // halo slots per pass
-    // With 64-cell tiles (SPLIT3) the halo wave also takes directions 5-8 of the
-    // tile's phase-3 update (lane l: cell l), the tile's wave the others; and two
-    // more waves form directions 5-8 of the phase-2 gradients, one for the tile's
-    // cells (thread T + 64 + l: cell l), one for the ring-1 slots (thread
-    // T + 128 + s: slot s), the tile and halo waves directions 1-4.  Opposite
-    // directions share a half, so every value is the one the whole pass forms.
+    // With 64-cell tiles (SPLIT3) two more waves form directions 5-8 of the
+    // phase-2 gradients, one for the tile's cells (thread T + 64 + l: cell l), one
+    // for the ring-1 slots (thread T + 128 + s: slot s), the tile and halo waves
+    // directions 1-4; phase 3 is split over the four waves by direction sets
+    // (0, 1, 3 | 2, 4 | 5, 7 | 6, 8), lane l of each taking tile cell l.
+    // Opposite directions share a set, so every value is the one the whole pass
+    // forms.
     constexpr bool SPLIT3 = split_form(T, STORE, RING);
     constexpr int GA = SPLIT3 ? 0 : -1;               // gradient half of the tile and halo waves
     // SPLIT3: phi_k - h of the tile cells' boundary slots, formed in phase 2 by
     // the tile's waves (each its half), staged for the halo wave's half of phase 3
     // (and for the tile wave's slots after the first): float4 planes of T cells
     __shared__ float4 lstash[SPLIT3 ? T * NF * 2 : 1];
+    // SPLIT3: the tile cells' phase-3 geometry (neighbour codes, h0, 1/A, stencil
+    // offsets, corners), written by the tile's wave in phase 1 for the waves that
+    // take the other direction sets: GP float4 planes of T cells
+    constexpr int GP = 5;
+    __shared__ float4 lgeo[SPLIT3 ? T * GP : 1];
     const int wtid = RING ? __builtin_amdgcn_readfirstlane(tid) : 0;   // (wave-uniform)
     const bool ownw = !RING || wtid < T;                               // the tile's cells
     const bool ownb = SPLIT3 && wtid >= T + 64 && wtid < T + 128;      // their directions 5-8
@@ -854,14 +882,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         hraw1 = ldg(hidx, rj < hs ? rj : 0), hraw2 = ldg(hidx, h1s + rj < hs ? h1s + rj : 0);
     if (SPLIT3 && halob) hraw1 = ldg(hidx, rj < hs ? rj : 0);
     const int i3 = tile * T + rj;                     // SPLIT3: this halo lane's tile cell
-    const bool valid3 = SPLIT3 && halow && i3 < n_cells;
-    if (SPLIT3 && halow) {                            // (one level, beside the halo chain)
-        const int ic3 = valid3 ? i3 : 0;
-        load_cell<STORE>(src, np, ic3, f, d.ref, 0, 1);
-        ln = ldo<uint2>(lnbr, (uint32_t)ic3 * 8u);
-        geo.load(dxy, np, ic3);
-        cf.load(vxy, np, ic3);
-    }
+    const bool valid3 = SPLIT3 && (halow || halob) && i3 < n_cells;
     const bool rin2 = rin && !halob;                  // this thread stages halo values
     const int c1 = rin && rj < h1s ? hraw1 : -1;
     const int c2 = rin2 && rj < h2s ? hraw2 : -1;
@@ -890,26 +911,40 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     const int gv1 = ldg(gsrc, BS < GW && tid + BS < GW ? tid + BS : 0);
     const void *basep = DIRECT ? hot.base : d.base;
     const bool sep_base = (M0 || d.mode == 0) && basep != src;
+    // update bases: the planes of this wave's phase-3 set
     if (ownw) {
-        if (sep_base) load_cell<STORE>(basep, np, ic, base, d.ref, 0, SPLIT3 ? 5 : Q);
+        if (sep_base) {
+            if constexpr (SPLIT3) load_set<STORE, 2>(basep, np, ic, base, d.ref);
+            else load_cell<STORE>(basep, np, ic, base, d.ref);
+        }
         h0 = f[0];
 #pragma unroll
         for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
         geo.invert(code);
         cf.finish();
-    } else if (SPLIT3 && halow) {
-        if (sep_base) load_cell<STORE>(basep, np, valid3 ? i3 : 0, base, d.ref, 5, Q);
-        h0 = f[0];
+    } else if constexpr (SPLIT3) {
+        if (halow) {
+            if (sep_base) load_set<STORE, 3>(basep, np, valid3 ? i3 : 0, base, d.ref);
+        } else if (halob) {
+            if (sep_base) load_set<STORE, 5>(basep, np, valid3 ? i3 : 0, base, d.ref);
+        } else if (ownb) {
+            if (sep_base) load_set<STORE, 4>(basep, np, validb ? tile * T + ob : 0, base, d.ref);
+            h0 = f[0];
 #pragma unroll
-        for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
-        cf.finish();
-    } else if (SPLIT3 && ownb) {
-        h0 = f[0];
-#pragma unroll
-        for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
-        geo.invert(code);
+            for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
+            geo.invert(code);
+        }
     }
     if (valid) wr_f(A + tid, sa, f);
+    if constexpr (SPLIT3)
+        if (valid) {
+            float4 *g = lgeo + tid;
+            g[0] = make_float4(__uint_as_float(ln.x), __uint_as_float(ln.y), h0, cf.inva);
+            g[T] = make_float4(geo.dk[0].x, geo.dk[0].y, geo.dk[1].x, geo.dk[1].y);
+            g[2 * T] = make_float4(geo.dk[2].x, geo.dk[2].y, geo.dk[NF - 1].x, geo.dk[NF - 1].y);
+            g[3 * T] = make_float4(cf.v[0].x, cf.v[0].y, cf.v[1].x, cf.v[1].y);
+            g[4 * T] = make_float4(cf.v[2].x, cf.v[2].y, cf.v[NF - 1].x, cf.v[NF - 1].y);
+        }
     if (c1 >= 0) {
         hf0 = f1[0];
         if (!halob) wr_f(A + T + rj, sa, f1);
@@ -954,8 +989,8 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
             if (validb) {
                 hc[0] = h0;
                 rd_f(A + ob, sa, hc);
-                gradient_staged<NF, false, true, 1>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, hc, no_k,
-                                                    lstash + ob, T, sa);
+                gradient_staged<NF, true, true, 1>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, bsave, bsave_k,
+                                                   lstash + ob, T, sa);
                 wr_g<1>(A + ob, sa, gx, gy);
             }
         if (c1 >= 0) {
@@ -1000,12 +1035,40 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     }
     __syncthreads();
     if (valid)
-        tile_update<NF, STORE, M0, SPLIT3 ? 0 : -1, SPLIT3>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid,
+        tile_update<NF, STORE, M0, SPLIT3 ? 2 : -1, SPLIT3>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid,
                                                             A, sa, lg, bsave, bsave_k, lstash + tid, T);
-    if constexpr (SPLIT3)
-        if (valid3)
-            tile_update<NF, STORE, M0, 1, SPLIT3>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj, A, sa, lg,
-                                                  bsave, -1, lstash + rj, T);
+    if constexpr (SPLIT3) {
+        // the other waves' cells: their phase-3 geometry from the tile's wave
+        const int gc = ownb ? ob : rj;
+        if (validb || valid3) {
+            const float4 *g = lgeo + gc;
+            const float4 g0 = g[0], g1 = g[T], g2 = g[2 * T], g3 = g[3 * T], g4 = g[4 * T];
+            cf.v[0] = make_float2(g3.x, g3.y);
+            cf.v[1] = make_float2(g3.z, g3.w);
+            cf.v[2] = make_float2(g4.x, g4.y);
+            cf.v[NF - 1] = make_float2(g4.z, g4.w);
+            cf.inva = g0.w;
+            if (!ownb) {
+                ln = make_uint2(__float_as_uint(g0.x), __float_as_uint(g0.y));
+                h0 = g0.z;
+                geo.dk[0] = make_float2(g1.x, g1.y);
+                geo.dk[1] = make_float2(g1.z, g1.w);
+                geo.dk[2] = make_float2(g2.x, g2.y);
+                geo.dk[NF - 1] = make_float2(g2.z, g2.w);
+#pragma unroll
+                for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
+            }
+        }
+        if (validb)
+            tile_update<NF, STORE, M0, 4, true>(d, tile * T + ob, h0, base, sep_base, code, ln, geo, cf, A + ob, A,
+                                                sa, lg, bsave, bsave_k, lstash + ob, T);
+        if (valid3 && halow)
+            tile_update<NF, STORE, M0, 3, true>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj, A, sa, lg,
+                                                bsave, -1, lstash + rj, T);
+        if (valid3 && halob)
+            tile_update<NF, STORE, M0, 5, true>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj, A, sa, lg,
+                                                bsave, -1, lstash + rj, T);
+    }
 }
 
 // DIRECT: one instance whose unit b is tile b, the bases and sizes its loads
@@ -1129,8 +1192,9 @@ size_t stage_lds_limit() {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
         v = 65536;
-    // less the staged group table and the boundary stash of 64-cell halo-wave tiles
-    return (size_t)v - sizeof(GroupDev) * MAX_GROUPS - sizeof(float4) * 64 * 4 * 2;
+    // less the staged group table, and the boundary stash (up to 4 slots x 2
+    // float4) and phase-3 geometry (5 float4) of 64-cell halo-wave tiles
+    return (size_t)v - sizeof(GroupDev) * MAX_GROUPS - sizeof(float4) * 64 * (4 * 2 + 5);
 }
 
 size_t stage_lds_bytes(int T, int h2max, int h1max) {
