@@ -1092,8 +1092,11 @@ __global__ void __launch_bounds__(tile_threads(T, STORE, RING)) k_tile(const int
     const int ub = remap_block(blockIdx.x, units_x >> 1, units_x & 1);
     const Hot hot{hot_src, hot_base, hot_halo_idx, hot_halo_code, hot_lnbr, hot_dxy, hot_vxy,
                   hot_np, hot_n_cells, hot_h12 & 0xffff, hot_h12 >> 16};
+    // region-A records: T + h1s for a single instance (preloaded, so the first LDS
+    // writes wait on no argument load), else the largest over the instances
+    const int sa = DIRECT ? T + (hot_h12 & 0xffff) : nA;
     tile_body<NF, STORE, T, DIRECT, M0, RING>(descs, (DIRECT || !units) ? make_int2(0, ub) : units[ub], hot, lds4,
-                                             nA, lds4 + nA * RA);
+                                             sa, lds4 + sa * RA);
 }
 
 // (units null: a single instance whose unit b is tile b.)
@@ -1172,7 +1175,8 @@ StageArgs stage_args(const InstDesc *descs_dev, const UnitTable &ut, int xcd_rem
     a.u = ut.units;
     a.ux = 2 * ut.n_units + (xcd_remap ? 1 : 0);
     a.nA = ut.block + h1max;
-    a.direct = ut.direct && host_desc && !persistent;
+    // (a single-instance launch sizes region A from its own ring-1 slot count)
+    a.direct = ut.direct && host_desc && !persistent && a.nA == ut.block + host_desc->h1s;
     if (a.direct) {
         a.src = host_desc->src;
         a.base = host_desc->base;
