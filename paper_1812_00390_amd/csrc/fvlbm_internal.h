@@ -183,8 +183,8 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
 size_t stage_lds_bytes(int T, int h2max, int h1max);
 // Dynamic LDS a stage workgroup may use on the current device: the device's
 // per-workgroup LDS (160 KiB on gfx950) less the kernels' static LDS (the group
-// table, and the boundary stash and phase-3 geometry of the 64-cell halo-wave
-// form).
+// table, and the boundary stash, phase-3 geometry and collision terms of the
+// 64-cell halo-wave form).
 size_t stage_lds_limit();
 // Same as a kernel node for a graph.
 // argbuf: argbuf[0] holds a StageArgs, argbuf[1..14] receive the argument pointers.

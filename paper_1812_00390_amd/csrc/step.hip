@@ -666,22 +666,43 @@ __device__ inline void boundary_flux(const InstDesc &d, const float hi[Q], const
     }
 }
 
+// The BGK collision term f_eq - f of one cell (Eqs. 3-5, deviation form).
+// The BGK source moves no mass and no momentum: f_eq carries the density and
+// momentum of f.  In FP32 the rounding of f_eq (terms near 0.05, an ulp near
+// 4e-9, divided by tau) leaves residual moments that act as a steady momentum
+// source and add up over a run.  They are projected out of f_eq - f
+// (subtracting w_a (m0 + 3 e_a.m), an identity in exact arithmetic).
+__device__ inline void collision_neq(const float h[Q], const RefDev &r, float neq[Q]) {
+    const Macro m = moments(h, r);
+    float he[Q];
+    heq(m.drho, m.rho, m.jx, m.jy, r, he);
+#pragma unroll
+    for (int a = 0; a < Q; a++) neq[a] = he[a] - h[a];
+    const float m0 = ((neq[0] + neq[1]) + (neq[2] + neq[3])) + ((neq[4] + neq[5]) + (neq[6] + neq[7])) + neq[8];
+    const float mx = ((neq[1] - neq[3]) + (neq[5] - neq[6])) + (neq[8] - neq[7]);
+    const float my = ((neq[2] - neq[4]) + (neq[5] + neq[6])) - (neq[7] + neq[8]);
+    neq[0] = fmaf(-WT[0], m0, neq[0]);
+#pragma unroll
+    for (int a = 1; a < Q; a++) neq[a] = fmaf(-WT[a], fmaf(3.f, edot(a, mx, my), m0), neq[a]);
+}
+
 // Phase 3 for one tile cell: face values, flux sum, BGK source, update, store.
 // base[] holds f(0) of the update when it is not the evaluated state.  H >= 0:
 // only the directions of set H (a base + coef RHS update), the others being
 // other waves'; every per-direction value is the one the whole update forms.
-template <int NF, int STORE, bool M0, int H, bool STASH>
+// NEQ: the cell's collision term was formed in phase 1 and staged at lneq
+// (float4 planes of stride ss: directions 0-3, 4-7, 8).
+template <int NF, int STORE, bool M0, int H, bool STASH, bool NEQ>
 __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, const float base[Q], bool sep_base,
                                             const int (&code)[NF], uint2 packed, const CellGeo<NF> &geo, const CellFaces<NF> &cf,
                                             const float4 *own, const float4 *A, int sa, const GroupDev *lg,
-                                            const float bsave[Q], int bsave_k, const float4 *stash, int ss) {
+                                            const float bsave[Q], int bsave_k, const float4 *stash, int ss,
+                                            const float4 *lneq) {
     float hi[Q], gxi[Q], gyi[Q];
     hi[0] = h0;
     rd_f(own, sa, hi);
     rd_g(own, sa, gxi, gyi);
-    const Macro mi = moments(hi, d.ref);
-    float hei[Q];
-    heq(mi.drho, mi.rho, mi.jx, mi.jy, d.ref, hei);
+    const Macro mi = NEQ ? Macro{} : moments(hi, d.ref);   // (boundary values come staged with NEQ)
     float acc[Q];
 #pragma unroll
     for (int a = 0; a < Q; a++) acc[a] = 0.f;
@@ -722,21 +743,14 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
     }
     if (bm) boundary_flux<NF, H, STASH>(d, hi, gxi, gyi, mi, packed, bm, geo, cf, lg, bsave, bsave_k, stash, ss, acc);
 
-    // The BGK source moves no mass and no momentum: f_eq carries the density and
-    // momentum of f (Eqs. 3, 5).  In FP32 the rounding of f_eq (terms near 0.05,
-    // an ulp near 4e-9, divided by tau) leaves residual moments that act as a steady
-    // momentum source and add up over a run.  They are projected out of f_eq - f
-    // (subtracting w_a (m0 + 3 e_a.m), an identity in exact arithmetic).
     float neq[Q];
-#pragma unroll
-    for (int a = 0; a < Q; a++) neq[a] = hei[a] - hi[a];
-    {
-        const float m0 = ((neq[0] + neq[1]) + (neq[2] + neq[3])) + ((neq[4] + neq[5]) + (neq[6] + neq[7])) + neq[8];
-        const float mx = ((neq[1] - neq[3]) + (neq[5] - neq[6])) + (neq[8] - neq[7]);
-        const float my = ((neq[2] - neq[4]) + (neq[5] + neq[6])) - (neq[7] + neq[8]);
-        neq[0] = fmaf(-WT[0], m0, neq[0]);
-#pragma unroll
-        for (int a = 1; a < Q; a++) neq[a] = fmaf(-WT[a], fmaf(3.f, edot(a, mx, my), m0), neq[a]);
+    if constexpr (NEQ) {
+        const float4 n0 = lneq[0], n1 = lneq[ss], n2 = lneq[2 * ss];
+        neq[0] = n0.x; neq[1] = n0.y; neq[2] = n0.z; neq[3] = n0.w;
+        neq[4] = n1.x; neq[5] = n1.y; neq[6] = n1.z; neq[7] = n1.w;
+        neq[8] = n2.x;
+    } else {
+        collision_neq(hi, d.ref, neq);
     }
 
     // RHS = -sum (e.n dl/A) phi - (f - f_eq)/tau  (Eq. 10), then the update.
@@ -836,6 +850,9 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // take the other direction sets: GP float4 planes of T cells
     constexpr int GP = 5;
     __shared__ float4 lgeo[SPLIT3 ? T * GP : 1];
+    // SPLIT3: the tile cells' collision term f_eq - f (a function of the cell's
+    // own state), formed once by the tile's wave in phase 1: 3 float4 planes
+    __shared__ float4 lneq[SPLIT3 ? T * 3 : 1];
     const int wtid = RING ? __builtin_amdgcn_readfirstlane(tid) : 0;   // (wave-uniform)
     const bool ownw = !RING || wtid < T;                               // the tile's cells
     const bool ownb = SPLIT3 && wtid >= T + 64 && wtid < T + 128;      // their directions 5-8
@@ -944,6 +961,12 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
             g[2 * T] = make_float4(geo.dk[2].x, geo.dk[2].y, geo.dk[NF - 1].x, geo.dk[NF - 1].y);
             g[3 * T] = make_float4(cf.v[0].x, cf.v[0].y, cf.v[1].x, cf.v[1].y);
             g[4 * T] = make_float4(cf.v[2].x, cf.v[2].y, cf.v[NF - 1].x, cf.v[NF - 1].y);
+            float nq[Q];
+            collision_neq(f, d.ref, nq);
+            float4 *n = lneq + tid;
+            n[0] = make_float4(nq[0], nq[1], nq[2], nq[3]);
+            n[T] = make_float4(nq[4], nq[5], nq[6], nq[7]);
+            n[2 * T] = make_float4(nq[8], 0.f, 0.f, 0.f);
         }
     if (c1 >= 0) {
         hf0 = f1[0];
@@ -1035,8 +1058,9 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     }
     __syncthreads();
     if (valid)
-        tile_update<NF, STORE, M0, SPLIT3 ? 2 : -1, SPLIT3>(d, i, h0, base, sep_base, code, ln, geo, cf, A + tid,
-                                                            A, sa, lg, bsave, bsave_k, lstash + tid, T);
+        tile_update<NF, STORE, M0, SPLIT3 ? 2 : -1, SPLIT3, SPLIT3>(d, i, h0, base, sep_base, code, ln, geo, cf,
+                                                                    A + tid, A, sa, lg, bsave, bsave_k, lstash + tid,
+                                                                    T, lneq + tid);
     if constexpr (SPLIT3) {
         // the other waves' cells: their phase-3 geometry from the tile's wave
         const int gc = ownb ? ob : rj;
@@ -1060,14 +1084,14 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
             }
         }
         if (validb)
-            tile_update<NF, STORE, M0, 4, true>(d, tile * T + ob, h0, base, sep_base, code, ln, geo, cf, A + ob, A,
-                                                sa, lg, bsave, bsave_k, lstash + ob, T);
+            tile_update<NF, STORE, M0, 4, true, true>(d, tile * T + ob, h0, base, sep_base, code, ln, geo, cf, A + ob,
+                                                      A, sa, lg, bsave, bsave_k, lstash + ob, T, lneq + ob);
         if (valid3 && halow)
-            tile_update<NF, STORE, M0, 3, true>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj, A, sa, lg,
-                                                bsave, -1, lstash + rj, T);
+            tile_update<NF, STORE, M0, 3, true, true>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj, A, sa, lg,
+                                                      bsave, -1, lstash + rj, T, lneq + rj);
         if (valid3 && halob)
-            tile_update<NF, STORE, M0, 5, true>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj, A, sa, lg,
-                                                bsave, -1, lstash + rj, T);
+            tile_update<NF, STORE, M0, 5, true, true>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj, A, sa, lg,
+                                                      bsave, -1, lstash + rj, T, lneq + rj);
     }
 }
 
@@ -1197,8 +1221,9 @@ size_t stage_lds_limit() {
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
         v = 65536;
     // less the staged group table, and the boundary stash (up to 4 slots x 2
-    // float4) and phase-3 geometry (5 float4) of 64-cell halo-wave tiles
-    return (size_t)v - sizeof(GroupDev) * MAX_GROUPS - sizeof(float4) * 64 * (4 * 2 + 5);
+    // float4), phase-3 geometry (5 float4) and collision terms (3 float4) of
+    // 64-cell halo-wave tiles
+    return (size_t)v - sizeof(GroupDev) * MAX_GROUPS - sizeof(float4) * 64 * (4 * 2 + 5 + 3);
 }
 
 size_t stage_lds_bytes(int T, int h2max, int h1max) {
