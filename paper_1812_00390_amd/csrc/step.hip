@@ -812,8 +812,9 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
                                           int sa, float4 *B) {
     const InstDesc &d = descs[u.x];
     // Two descriptor lines (reference state and update coefficients) are first
-    // needed in phases 2 and 3; one word of each is read here, so that their
-    // trip to the scalar cache overlaps the phase-1 loads.
+    // needed at the end of phase 1 (the split form's collision terms) or in
+    // phases 2 and 3; one word of each is read here, so that their trip to the
+    // scalar cache overlaps the phase-1 loads.
     const float warm0 = d.ref.rho0, warm1 = d.ref.c0[1];
     // the values the first loads depend on: kernel arguments for a single instance
     // (no descriptor load on the path to the first loads), else the descriptor
@@ -842,8 +843,9 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     constexpr bool SPLIT3 = split_form(T, STORE, RING);
     constexpr int GA = SPLIT3 ? 0 : -1;               // gradient half of the tile and halo waves
     // SPLIT3: phi_k - h of the tile cells' boundary slots, formed in phase 2 by
-    // the tile's waves (each its half), staged for the halo wave's half of phase 3
-    // (and for the tile wave's slots after the first): float4 planes of T cells
+    // the tile's two waves (each its half of the directions), staged for the
+    // phase-3 direction sets of every wave (the first slot of each also stays in
+    // registers): float4 planes of T cells
     __shared__ float4 lstash[SPLIT3 ? T * NF * 2 : 1];
     // SPLIT3: the tile cells' phase-3 geometry (neighbour codes, h0, 1/A, stencil
     // offsets, corners), written by the tile's wave in phase 1 for the waves that
