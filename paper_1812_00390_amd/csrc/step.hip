@@ -853,7 +853,8 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     constexpr int GP = 5;
     __shared__ float4 lgeo[SPLIT3 ? T * GP : 1];
     // SPLIT3: the tile cells' collision term f_eq - f (a function of the cell's
-    // own state), formed once by the tile's wave in phase 1: 3 float4 planes
+    // own state), formed once in phase 1 by the wave for directions 5-8 of the
+    // tile cells (which waits at the barrier longest): 3 float4 planes
     __shared__ float4 lneq[SPLIT3 ? T * 3 : 1];
     const int wtid = RING ? __builtin_amdgcn_readfirstlane(tid) : 0;   // (wave-uniform)
     const bool ownw = !RING || wtid < T;                               // the tile's cells
@@ -891,9 +892,9 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         geo.load(dxy, np, ic);
         cf.load(vxy, np, ic);
     }
-    if (SPLIT3 && ownb) {                             // the cell's h0 and stencil
+    if (SPLIT3 && ownb) {                             // the cell's state and stencil
         const int icb = validb ? tile * T + ob : 0;
-        load_cell<STORE>(src, np, icb, f, d.ref, 0, 1);
+        load_cell<STORE>(src, np, icb, f, d.ref);
         ln = ldo<uint2>(lnbr, (uint32_t)icb * 8u);
         geo.load(dxy, np, icb);
     }
@@ -963,9 +964,12 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
             g[2 * T] = make_float4(geo.dk[2].x, geo.dk[2].y, geo.dk[NF - 1].x, geo.dk[NF - 1].y);
             g[3 * T] = make_float4(cf.v[0].x, cf.v[0].y, cf.v[1].x, cf.v[1].y);
             g[4 * T] = make_float4(cf.v[2].x, cf.v[2].y, cf.v[NF - 1].x, cf.v[NF - 1].y);
+        }
+    if constexpr (SPLIT3)
+        if (validb) {
             float nq[Q];
             collision_neq(f, d.ref, nq);
-            float4 *n = lneq + tid;
+            float4 *n = lneq + ob;
             n[0] = make_float4(nq[0], nq[1], nq[2], nq[3]);
             n[T] = make_float4(nq[4], nq[5], nq[6], nq[7]);
             n[2 * T] = make_float4(nq[8], 0.f, 0.f, 0.f);
@@ -1012,8 +1016,8 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         }
         if constexpr (SPLIT3)
             if (validb) {
-                hc[0] = h0;
-                rd_f(A + ob, sa, hc);
+#pragma unroll
+                for (int a = 0; a < Q; a++) hc[a] = f[a];   // (this wave loaded the cell's state)
                 gradient_staged<NF, true, true, 1>(d, geo, hc, code, ln, A, B, a_end, lg, gx, gy, bsave, bsave_k,
                                                    lstash + ob, T, sa);
                 wr_g<1>(A + ob, sa, gx, gy);
