@@ -1000,6 +1000,31 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     }
     asm volatile("" ::"s"(warm0), "s"(warm1));    // (keeps the two reads above)
     __syncthreads();
+    if constexpr (SPLIT3) {
+        // the other waves' phase-3 cells: their geometry from the tile's wave,
+        // read now so that it has arrived when phase 3 starts (these registers
+        // are not used in phase 2 by the waves that read them)
+        const int gc = ownb ? ob : rj;
+        if (validb || valid3) {
+            const float4 *g = lgeo + gc;
+            const float4 g0 = g[0], g1 = g[T], g2 = g[2 * T], g3 = g[3 * T], g4 = g[4 * T];
+            cf.v[0] = make_float2(g3.x, g3.y);
+            cf.v[1] = make_float2(g3.z, g3.w);
+            cf.v[2] = make_float2(g4.x, g4.y);
+            cf.v[NF - 1] = make_float2(g4.z, g4.w);
+            cf.inva = g0.w;
+            if (!ownb) {
+                ln = make_uint2(__float_as_uint(g0.x), __float_as_uint(g0.y));
+                h0 = g0.z;
+                geo.dk[0] = make_float2(g1.x, g1.y);
+                geo.dk[1] = make_float2(g1.z, g1.w);
+                geo.dk[2] = make_float2(g2.x, g2.y);
+                geo.dk[NF - 1] = make_float2(g2.z, g2.w);
+#pragma unroll
+                for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
+            }
+        }
+    }
 
     // ---- phase 2
     float bsave[Q];                                // phi_k - h of the cell's first boundary slot, for phase 3
@@ -1068,27 +1093,6 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
                                                                     A + tid, A, sa, lg, bsave, bsave_k, lstash + tid,
                                                                     T, lneq + tid);
     if constexpr (SPLIT3) {
-        // the other waves' cells: their phase-3 geometry from the tile's wave
-        const int gc = ownb ? ob : rj;
-        if (validb || valid3) {
-            const float4 *g = lgeo + gc;
-            const float4 g0 = g[0], g1 = g[T], g2 = g[2 * T], g3 = g[3 * T], g4 = g[4 * T];
-            cf.v[0] = make_float2(g3.x, g3.y);
-            cf.v[1] = make_float2(g3.z, g3.w);
-            cf.v[2] = make_float2(g4.x, g4.y);
-            cf.v[NF - 1] = make_float2(g4.z, g4.w);
-            cf.inva = g0.w;
-            if (!ownb) {
-                ln = make_uint2(__float_as_uint(g0.x), __float_as_uint(g0.y));
-                h0 = g0.z;
-                geo.dk[0] = make_float2(g1.x, g1.y);
-                geo.dk[1] = make_float2(g1.z, g1.w);
-                geo.dk[2] = make_float2(g2.x, g2.y);
-                geo.dk[NF - 1] = make_float2(g2.z, g2.w);
-#pragma unroll
-                for (int k = 0; k < NF; k++) code[k] = unpack16(k < 2 ? ln.x : ln.y, k & 1);
-            }
-        }
         if (validb)
             tile_update<NF, STORE, M0, 4, true, true>(d, tile * T + ob, h0, base, sep_base, code, ln, geo, cf, A + ob,
                                                       A, sa, lg, bsave, bsave_k, lstash + ob, T, lneq + ob);
