@@ -113,6 +113,11 @@ def _run_pair(F, O, m, tau, scheme, steps, storage="fp32dev", cfl=0.5, u_ref=0.1
     return (rho_g, u_g, st), (rho_o, u_o), o, s
 
 
+# The launch configuration the benchmark's autotuner picks on the 20k cavity:
+# 64-cell tiles, XCD remap, launch form 2 (the halo wave; with per-value storage
+# the four-wave split form).
+BENCH_SCHEDULE = (64, True, 2)
+
 # FP16 deviation storage: the 1e-3 U target is narrowly missed (measured
 # 1.2e-3 to 1.3e-3 U on the cavity after 300-2000 steps and on the cylinder
 # after 100 steps: the 11-bit mantissa on deviations of about 0.3 w, rounded
@@ -382,26 +387,32 @@ def test_cavity_cfg2_full_size_one_rhs_and_short_run(F, O):
     tol = 64 * EPS32 * _rhs_scale(O, o, f, tau)
     assert np.all(np.abs(got - ref).max(axis=1) <= tol)
     o.init(); s2 = F.Solver(mesh, F.make_params(tau=tau, dt=o.dt, scheme="rk4"))
+    s2.set_schedule(*BENCH_SCHEDULE)
+    assert s2.get_schedule()["persistent"] == BENCH_SCHEDULE[2]
     o.step(20); s2.step(20)
     assert np.abs(s2.macros()[1] - o.macros()[1]).max() <= 1e-5 * 0.1
 
 
-def test_cavity_cfg2_full_run_vs_stored_oracle(F):
+@pytest.mark.parametrize("schedule", [None, BENCH_SCHEDULE])
+def test_cavity_cfg2_full_run_vs_stored_oracle(F, schedule):
     ref = np.load(os.path.join(GOLDEN, "oracle_cavity100_rk4_2000.npz"))
     m = mg.cavity(n=100, ratio=1.08, jitter=0.2, seed=0, lid_u=0.1)
     mesh = F.Mesh(m)
     for storage, utol in (("fp32", 1e-5), ("fp32dev", 1e-5), ("fp16dev", FP16_CAVITY_UTOL), ("i16dev", I16_UTOL)):
         s = F.Solver(mesh, F.make_params(tau=float(ref["tau"]), dt=float(ref["dt"]), scheme="rk4", storage=storage))
+        if schedule:
+            s.set_schedule(*schedule)
         s.step(int(ref["steps"]))
         rho, u, _ = s.macros()
         idx = ref["idx"]
         err = np.abs(u[idx] - ref["u"]).max()
-        print(f"cavity 20k tri RK4 2000 steps {storage}: max|u-u_ref| = {err:.3e} (U = 0.1)")
+        print(f"cavity 20k tri RK4 2000 steps {storage} {schedule}: max|u-u_ref| = {err:.3e} (U = 0.1)")
         assert err <= utol * 0.1
         assert np.abs(rho[idx] - ref["rho"]).max() <= utol * 0.1
 
 
-def test_cylinder_cfg3_full_size_vs_stored_oracle(F):
+@pytest.mark.parametrize("schedule", [None, BENCH_SCHEDULE])
+def test_cylinder_cfg3_full_size_vs_stored_oracle(F, schedule):
     ref = np.load(os.path.join(GOLDEN, "oracle_cylinder256_rk4_100.npz"))
     m = mg.cylinder(nr=256, nt=384)
     mesh = F.Mesh(m)
@@ -409,11 +420,13 @@ def test_cylinder_cfg3_full_size_vs_stored_oracle(F):
         s = F.Solver(mesh, F.make_params(tau=float(ref["tau"]), dt=float(ref["dt"]), scheme="rk4",
                                          storage=storage, u_ref=0.2, u_dev=(0.1, 0.0)),
                      u=np.tile([0.1, 0.0], (m.n_cells, 1)))
+        if schedule:
+            s.set_schedule(*schedule)
         s.step(int(ref["steps"]))
         rho, u, _ = s.macros()
         idx = ref["idx"]
         err = np.abs(u[idx] - ref["u"]).max()
-        print(f"cylinder 98k quads RK4 100 steps {storage}: max|u-u_ref| = {err:.3e}")
+        print(f"cylinder 98k quads RK4 100 steps {storage} {schedule}: max|u-u_ref| = {err:.3e}")
         assert err <= utol * 0.1
 
 
