@@ -499,6 +499,10 @@ def test_tiny_meshes_and_degenerate_calls(F, O):
     U = 0.1
     for m in [mg.cavity(n=1, ratio=1.0, jitter=0.0, tri=False), mg.cavity(n=1, ratio=1.0, jitter=0.0, tri=True),
               mg.cavity(n=2, ratio=1.0, jitter=0.0, tri=True), mg.couette(1, 2, U=U)]:
+        # the halo-wave split form on the same meshes (no halo, up to four boundary faces per cell)
+        (rg, ug, st), (ro, uo), o, s = _run_pair(F, O, m, 0.01, "rk4", 20, storage="fp32dev", block=64, form=2)
+        assert np.abs(ug - uo).max() <= 1e-5 * U and np.abs(rg - ro).max() <= 1e-6
+        s.close()
         (rg, ug, st), (ro, uo), o, s = _run_pair(F, O, m, 0.01, "rk4", 20, storage="fp32dev")
         assert np.abs(ug - uo).max() <= 1e-5 * U and np.abs(rg - ro).max() <= 1e-6
         f0 = s.f
