@@ -196,7 +196,9 @@ void fvlbm_batch_destroy(fvlbm_batch *b);
  * the resident capacity walks the tile list; 2 one workgroup per tile with one
  * more wave that loads the tile's halo and forms the ring-1 gradients beside
  * the tile's own (single solvers, tiles of 64 or 128 cells, Euler and RK
- * stages; elsewhere it acts as 0).  A batch takes 0 or 1.  A schedule never
+ * stages; elsewhere it acts as 0); with 64-cell tiles and per-value storage
+ * two more waves take half of each cell's directions, so a workgroup runs four
+ * waves of 64.  A batch takes 0 or 1.  A schedule never
  * changes the per-cell arithmetic: results are bitwise identical under every
  * schedule.
  * Errors: FVLBM_E_ARG (unsupported tile size, or tile plus halo do not fit
