@@ -121,7 +121,7 @@ double fvlbm_mesh_cfl_length(const fvlbm_mesh *mesh);
 size_t fvlbm_state_bytes(const fvlbm_mesh *mesh, const fvlbm_params *params);
 
 /*
- * Step 0 (Section 2.5): f = f_eq(rho, u) per cell.  rho0_cells [n_cells] and
+ * Step 0 (Section 2.4.2): f = f_eq(rho, u) per cell.  rho0_cells [n_cells] and
  * u0_cells [2*n_cells] may be NULL for the uniform values params->rho0 and (0,0).
  * device_buf must hold fvlbm_state_bytes() bytes, 256-byte aligned, and outlive
  * the solver.  The solver keeps a reference to mesh (destroy solvers first).
@@ -134,7 +134,7 @@ fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const doub
 /* Time step actually used (after the Eq. 14/15 rule), or -1 on a null solver. */
 double fvlbm_solver_dt(const fvlbm_solver *s);
 
-/* Steps 1-5 repeated n_steps times (Section 2.5), enqueued on the solver's stream;
+/* Steps 1-5 repeated n_steps times (Section 2.4.2), enqueued on the solver's stream;
  * does not sync.  Errors: FVLBM_E_ARG (n_steps < 0), FVLBM_E_STATE, FVLBM_E_DEVICE. */
 fvlbm_status fvlbm_step(fvlbm_solver *s, int64_t n_steps);
 

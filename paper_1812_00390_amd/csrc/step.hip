@@ -2,7 +2,7 @@
 //
 // A workgroup owns a tile of consecutive cells (one thread per cell, all nine
 // directions per thread) and stages the tile and two rings of face-neighbour
-// halo in LDS.  Per RHS evaluation (paper Section 2.5, Steps 1-5):
+// halo in LDS.  Per RHS evaluation (paper Section 2.4.2, Steps 1-5):
 //   Step 1/3  wall value f_P and ghost values f_GC of a cell's boundary
 //             slots (Eqs. 18-22), from that cell's own current-stage state;
 //   Step 2    least-squares gradient (Eq. 12) as sum_k M^-1 w_k d_k (phi_k - f_i)

@@ -612,6 +612,73 @@ def test_outlet_face_values(oracle_mod, internal):
             assert np.allclose(phi[c, k][inc], oracle_mod.feq(1.0, *u)[inc], rtol=0, atol=1e-15)
 
 
+def _linear_density_channel(oracle_mod, inlet_internal, nx=8, ny=4, Lx=2.0, Ly=1.0, rho0=1.0, slope=0.05):
+    """Unjittered quad channel, symmetry planes top and bottom, state
+    f = f_eq(rho(x), u_inf) with rho linear in x.  The inlet (left) and the
+    pressure outlet (right) are given the densities that continue the line to
+    their ghost points, which sit at the mirror images of the border centres
+    (x = -h/2 and x = Lx + h/2)."""
+    u = (0.1, 0.0)
+    h = Lx / nx
+    rho = lambda x: rho0 + slope * x
+    m = mg.channel(nx, ny, u_in=u, top="symmetry", bottom="symmetry", jitter=0.0, tri=False, Lx=Lx, Ly=Ly)
+    m.groups[0] = mg.BCGroup(mg.INLET, u, rho(-0.5 * h), inlet_internal)
+    m.groups[1] = mg.BCGroup(mg.OUTLET, u, rho(Lx + 0.5 * h), 1)
+    o = oracle_mod.Oracle(m, tau=0.01, dt=1e-3)
+    g = o.geometry()
+    o.init(rho=rho(g["cx"]), u=np.tile(u, (o.n, 1)))
+    return m, o, u, rho, h
+
+
+def test_inlet_and_pressure_outlet_outgoing_face_values_on_linear_state(oracle_mod):
+    """Eqs. (23), (24), outgoing directions (e.n > 0): the face value is the
+    border cell's second-order reconstruction f_k + grad f_k . (x_f - x_k).
+    On f = f_eq(rho(x), u_inf) with rho linear and ghost densities that continue
+    the line, every stencil value of the border cells is exact, so the
+    reconstruction is f_eq(rho(x_f), u_inf) at the face.  A first-order f_k, or
+    the ghost value on every direction, misses it by f_eq of a density offset of
+    about slope h / 2.  Incoming directions carry the ghost value (Eqs. 19, 21)."""
+    m, o, u, rho, h = _linear_density_channel(oracle_mod, inlet_internal=0)
+    phi = o.face_values(o.f)
+    ex, ey, _ = oracle_mod.lattice()
+    n_out = 0
+    for kind, rho_ghost in ((mg.INLET, m.groups[0].rho), (mg.OUTLET, m.groups[1].rho)):
+        faces, fc = _boundary_faces(o, m, kind)
+        assert len(faces) == 4
+        for c, k, grp in faces:
+            en = ex * fc["nx"][c, k] + ey * fc["ny"][c, k]
+            out = en > 0
+            exact = oracle_mod.feq(rho(fc["fx"][c, k]), *u)
+            assert np.allclose(phi[c, k][out], exact[out], rtol=0, atol=1e-15)
+            assert np.allclose(phi[c, k][en < 0], oracle_mod.feq(rho_ghost, *u)[en < 0], rtol=0, atol=1e-15)
+            # the two wrong readings are far from it
+            assert np.all(np.abs(o.f[c][out] - exact[out]) > 1e-4)
+            n_out += int(out.sum())
+    assert n_out == 2 * 4 * 3
+
+
+def test_velocity_inlet_outgoing_face_value_closed_form(oracle_mod):
+    """Eq. (23) at a velocity inlet (internal flow, rho* = rho_k): on the linear
+    state the ghost carries f_k itself (Eq. 19), so the border cell's stencil is
+    its right neighbour at +h (value f_eq(rho_k + slope h)), the ghost at -h
+    (value f_k) and the two symmetry ghosts at +-h_y (value f_k).  Eq. (12) with
+    w = 1/|d|^2 then gives d f/dx = slope f_eq'(rho) / 2 exactly, and the
+    outgoing face value at x_f = x_k - h/2 is f_eq(rho_k - slope h / 4, u_inf)."""
+    m, o, u, rho, h = _linear_density_channel(oracle_mod, inlet_internal=1)
+    phi = o.face_values(o.f)
+    ex, ey, _ = oracle_mod.lattice()
+    g = o.geometry()
+    faces, fc = _boundary_faces(o, m, mg.INLET)
+    assert len(faces) == 4
+    for c, k, grp in faces:
+        en = ex * fc["nx"][c, k] + ey * fc["ny"][c, k]
+        out = en > 0
+        assert out.sum() == 3
+        exact = oracle_mod.feq(rho(g["cx"][c]) - 0.05 * h / 4, *u)
+        assert np.allclose(phi[c, k][out], exact[out], rtol=0, atol=1e-15)
+        assert np.allclose(phi[c, k][en < 0], o.f[c][en < 0], rtol=0, atol=1e-15)   # f_GC = f_k here
+
+
 def test_symmetry_face_mirrors_normal_velocity(oracle_mod):
     """Eqs. (22), (26): on a horizontal symmetry plane the ghost is f_eq(rho, u, -v)
     and the face value is the mean of the cell value and the ghost."""
