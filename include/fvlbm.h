@@ -159,6 +159,13 @@ size_t fvlbm_checkpoint_bytes(const fvlbm_solver *s);
 fvlbm_status fvlbm_checkpoint(fvlbm_solver *s, void *host_buf, size_t bytes);
 fvlbm_status fvlbm_restore(fvlbm_solver *s, const void *host_buf, size_t bytes);
 
+/* Release a solver (its caller-owned state buffer is not touched) or a mesh.
+ * Either order is safe: a mesh destroyed while solvers still use it stays
+ * alive until the last of them is destroyed, and a solver destroyed while a
+ * batch holds it stays alive until that batch is destroyed (the batch then
+ * refuses to step, FVLBM_E_STATE).  A second destroy of the same handle is a
+ * no-op until the memory is released; after that the handle is invalid.
+ * The solver's stream is synchronized before anything is freed. */
 void fvlbm_solver_destroy(fvlbm_solver *s);
 void fvlbm_mesh_destroy(fvlbm_mesh *mesh);
 
@@ -187,6 +194,8 @@ fvlbm_status fvlbm_wall_force(fvlbm_solver *s, int32_t group, double force[2], i
  */
 fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_batch **out);
 fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps);
+/* Destroys the batch (not its members, which stay usable alone) and frees members
+ * that were destroyed while the batch held them. */
 void fvlbm_batch_destroy(fvlbm_batch *b);
 
 /* Launch schedule: tile size in cells (one workgroup per tile: 64, 128, 256 or
@@ -206,6 +215,9 @@ void fvlbm_batch_destroy(fvlbm_batch *b);
 fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap, int32_t persistent);
 fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap, int32_t *persistent);
 fvlbm_status fvlbm_batch_set_schedule(fvlbm_batch *b, int32_t block, int32_t xcd_remap, int32_t persistent);
+/* The schedule a batch launches with (after fvlbm_batch_set_schedule, fvlbm_batch_autotune, or the
+ * one fvlbm_batch_create chose).  Errors: FVLBM_E_ARG. */
+fvlbm_status fvlbm_batch_get_schedule(const fvlbm_batch *b, int32_t *block, int32_t *xcd_remap, int32_t *persistent);
 
 /* Autotuner: times every supported schedule for trial_steps steps (HIP
  * events on the solver's or batch's stream), keeps the fastest, and restores

@@ -63,7 +63,8 @@ bool mode0(int k) { return k <= R4; }
 
 struct fvlbm_mesh {
     MeshDev dev;
-    int refs = 0;
+    int refs = 0;              // solvers holding the mesh
+    bool destroyed = false;    // fvlbm_mesh_destroy was called while solvers held it: freed with the last one
 };
 
 struct fvlbm_solver {
@@ -82,6 +83,8 @@ struct fvlbm_solver {
     bool have_prev = false;    // AB2 history valid
     int lag = 1000;
     bool failed = false;
+    int batch_refs = 0;        // batches holding the solver
+    bool destroyed = false;    // fvlbm_solver_destroy was called while a batch held it: freed with the last one
     InstDesc *desc_dev = nullptr;   // [N_KINDS]
     InstDesc desc_host[N_KINDS];    // host copies (a single instance's first-load values go as kernel arguments)
     UnitTable ut;
@@ -347,12 +350,22 @@ fvlbm_status fvlbm_mesh_info(const fvlbm_mesh *mesh, int64_t out[4]) {
 
 double fvlbm_mesh_cfl_length(const fvlbm_mesh *mesh) { return mesh ? mesh->dev.cfl_length : -1.0; }
 
-void fvlbm_mesh_destroy(fvlbm_mesh *mesh) {
-    if (!mesh) return;
+namespace {
+void mesh_free(fvlbm_mesh *mesh) {
     hipDeviceSynchronize();          // solvers on any stream may still read the mesh arrays
     free_tiles(mesh->dev);
     if (mesh->dev.block) hipFree(mesh->dev.block);
     delete mesh;
+}
+}  // namespace
+
+void fvlbm_mesh_destroy(fvlbm_mesh *mesh) {
+    if (!mesh || mesh->destroyed) return;
+    if (mesh->refs > 0) {            // solvers still read it: the last solver destroyed frees it
+        mesh->destroyed = true;
+        return;
+    }
+    mesh_free(mesh);
 }
 
 size_t fvlbm_state_bytes(const fvlbm_mesh *mesh, const fvlbm_params *p) {
@@ -433,15 +446,26 @@ fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const doub
 
 double fvlbm_solver_dt(const fvlbm_solver *s) { return s ? s->dt : -1.0; }
 
+namespace {
+void solver_free(fvlbm_solver *s) {
+    fvlbm_mesh *m = s->mesh;
+    delete s;                        // (syncs the solver's stream)
+    if (m && --m->refs == 0 && m->destroyed) mesh_free(m);
+}
+}  // namespace
+
 void fvlbm_solver_destroy(fvlbm_solver *s) {
-    if (!s) return;
-    if (s->mesh) s->mesh->refs--;
-    delete s;
+    if (!s || s->destroyed) return;
+    if (s->batch_refs > 0) {         // a batch still holds it: the batch frees it when destroyed
+        s->destroyed = true;
+        return;
+    }
+    solver_free(s);
 }
 
 fvlbm_status fvlbm_step(fvlbm_solver *s, int64_t n_steps) {
     if (!s || n_steps < 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_step");
-    if (s->failed) return fail(FVLBM_E_STATE, "solver is in an error state");
+    if (s->failed || s->destroyed) return fail(FVLBM_E_STATE, "solver is in an error state or destroyed");
     if (s->snap_cur < 0 && s->steps % s->lag == 0) {
         if (take_snapshot(s) != hipSuccess) { s->failed = true; return fail(FVLBM_E_DEVICE, "snapshot failed"); }
     }
@@ -461,7 +485,7 @@ fvlbm_status fvlbm_step(fvlbm_solver *s, int64_t n_steps) {
 
 fvlbm_status fvlbm_macros(fvlbm_solver *s, double *rho, double *u, double *stats) {
     if (!s) return fail(FVLBM_E_ARG, "null solver");
-    if (s->failed) return fail(FVLBM_E_STATE, "solver is in an error state");
+    if (s->failed || s->destroyed) return fail(FVLBM_E_STATE, "solver is in an error state or destroyed");
     const MeshDev &m = s->mesh->dev;
     double *out = reinterpret_cast<double *>(s->buf + s->L.out);
     double *scal = reinterpret_cast<double *>(s->buf + s->L.scal);
@@ -685,7 +709,7 @@ fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_b
     b->sched = solvers[0]->sched;
     for (int i = 0; i < n; i++) {
         fvlbm_solver *s = solvers[i];
-        if (!s || s->failed) return fail(FVLBM_E_ARG, "null or failed solver in batch");
+        if (!s || s->failed || s->destroyed) return fail(FVLBM_E_ARG, "null, failed or destroyed solver in batch");
         if (s->p.scheme != b->scheme || s->p.storage != b->storage) return fail(FVLBM_E_PARAM, "batch members must share scheme and storage");
         if (s->stream != b->stream) return fail(FVLBM_E_PARAM, "batch members must share a stream");
         if (s->p.scheme != FVLBM_SCHEME_RK4 && s->cur != solvers[0]->cur) return fail(FVLBM_E_PARAM, "batch members must be at the same buffer parity");
@@ -701,7 +725,16 @@ fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_b
         if (st != FVLBM_E_ARG) break;
     }
     if (st != FVLBM_OK) return st;
+    for (fvlbm_solver *s : b->members) s->batch_refs++;
     *out = b.release();
+    return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_batch_get_schedule(const fvlbm_batch *b, int32_t *block, int32_t *xcd_remap, int32_t *persistent) {
+    if (!b || !block || !xcd_remap || !persistent) return fail(FVLBM_E_ARG, "null argument");
+    *block = b->sched.block;
+    *xcd_remap = b->sched.xcd_remap;
+    *persistent = b->sched.persistent;
     return FVLBM_OK;
 }
 
@@ -872,8 +905,20 @@ const int TUNE_BLOCKS[] = {64, 128, 256, 512};
 
 extern "C" {
 
+namespace {
+fvlbm_status batch_usable(const fvlbm_batch *b) {
+    for (const fvlbm_solver *s : b->members) {
+        if (s->destroyed) return fail(FVLBM_E_STATE, "a batch member was destroyed; destroy the batch");
+        if (s->failed) return fail(FVLBM_E_STATE, "a batch member is in an error state");
+    }
+    return FVLBM_OK;
+}
+}  // namespace
+
 fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps) {
     if (!b || n_steps < 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_batch_step");
+    fvlbm_status st = batch_usable(b);
+    if (st != FVLBM_OK) return st;
     return batch_enqueue(b, n_steps, true);
 }
 
@@ -901,6 +946,8 @@ fvlbm_status fvlbm_autotune(fvlbm_solver *s, int32_t trial_steps, double *best_m
 
 fvlbm_status fvlbm_batch_autotune(fvlbm_batch *b, int32_t trial_steps, double *best_ms) {
     if (!b || trial_steps <= 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_batch_autotune");
+    fvlbm_status ust = batch_usable(b);
+    if (ust != FVLBM_OK) return ust;
     std::vector<Saved> saved(b->members.size());
     for (size_t i = 0; i < b->members.size(); i++) {
         fvlbm_status st = save_state(b->members[i], saved[i]);
@@ -931,7 +978,11 @@ void fvlbm_batch_destroy(fvlbm_batch *b) {
     free_graphs(b->graphs);
     if (b->desc_dev) hipFree(b->desc_dev);
     for (auto &u : b->ut) if (u.units) hipFree(u.units);
+    std::vector<fvlbm_solver *> members = std::move(b->members);
     delete b;
+    // members destroyed while the batch held them are freed now
+    for (fvlbm_solver *s : members)
+        if (--s->batch_refs == 0 && s->destroyed) solver_free(s);
 }
 
 }  // extern "C"

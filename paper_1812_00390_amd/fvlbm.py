@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -75,6 +76,7 @@ SIGNATURES = {
     "fvlbm_set_schedule": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
     "fvlbm_get_schedule": (C.c_int, [_vp, _ip, _ip, _ip]),
     "fvlbm_batch_set_schedule": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
+    "fvlbm_batch_get_schedule": (C.c_int, [_vp, _ip, _ip, _ip]),
     "fvlbm_autotune": (C.c_int, [_vp, C.c_int32, _dp]),
     "fvlbm_batch_autotune": (C.c_int, [_vp, C.c_int32, _dp]),
     "fvlbm_last_error": (C.c_char_p, []),
@@ -156,6 +158,7 @@ class Mesh:
                                    int(raw.periodic.shape[0]), _iptr(per), _dptr(sh), int(reorder),
                                    _stream_handle(stream), C.byref(h)))
         self.h = h
+        self._solvers = weakref.WeakSet()     # solvers on this mesh, closed before it
 
     def info(self) -> dict:
         out = (C.c_int64 * 4)()
@@ -167,7 +170,12 @@ class Mesh:
         return lib().fvlbm_mesh_cfl_length(self.h)
 
     def close(self):
+        """Release the mesh; solvers still open on it are closed first.  (The
+        library also keeps a mesh alive while solvers use it, so either order
+        of destruction is safe, including under the cycle collector.)"""
         if getattr(self, "h", None):
+            for s in list(getattr(self, "_solvers", ())):
+                s.close()
             lib().fvlbm_mesh_destroy(self.h)
             self.h = None
 
@@ -219,6 +227,7 @@ class Solver:
         _check(L.fvlbm_init(mesh.h, C.byref(params), _dptr(r), _dptr(v), C.c_void_p(self.buf_ptr),
                             nbytes, _stream_handle(stream), C.byref(h)))
         self.h = h
+        mesh._solvers.add(self)
 
     @property
     def dt(self) -> float:
@@ -317,11 +326,12 @@ class Batch:
 
     def set_schedule(self, block: int, xcd_remap: bool = True, persistent: bool = False):
         _check(lib().fvlbm_batch_set_schedule(self.h, int(block), int(bool(xcd_remap)), int(bool(persistent))))
-        self._schedule = dict(block=int(block), xcd_remap=bool(xcd_remap), persistent=bool(persistent))
 
     def get_schedule(self) -> dict:
-        return dict(self._schedule) if getattr(self, "_schedule", None) else \
-            dict(block=self.solvers[0].get_schedule()["block"], xcd_remap=True, persistent=False)
+        """The schedule the batch launches with (as the library holds it)."""
+        b, x, p = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().fvlbm_batch_get_schedule(self.h, C.byref(b), C.byref(x), C.byref(p)))
+        return dict(block=b.value, xcd_remap=bool(x.value), persistent=bool(p.value))
 
     def autotune(self, trial_steps: int = 64) -> float:
         """Pick the fastest launch schedule for the whole batch (states restored); ms per step."""

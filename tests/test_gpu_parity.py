@@ -303,7 +303,7 @@ def test_schedules_do_not_change_results(F, scheme):
     m = mg.cavity(n=22, jitter=0.2, seed=13)
     outs = []
     for block, x, p in [(256, True, False), (64, False, True), (128, True, True), (256, False, False),
-                        (64, True, 2), (128, False, 2)]:
+                        (64, True, 2), (128, False, 2), (512, True, False), (512, False, True)]:
         mesh = F.Mesh(m)
         s = F.Solver(mesh, F.make_params(tau=3e-4, scheme=scheme))
         s.set_schedule(block, x, p)
@@ -393,7 +393,7 @@ def test_cavity_cfg2_full_size_one_rhs_and_short_run(F, O):
     assert np.abs(s2.macros()[1] - o.macros()[1]).max() <= 1e-5 * 0.1
 
 
-@pytest.mark.parametrize("schedule", [None, BENCH_SCHEDULE])
+@pytest.mark.parametrize("schedule", [None, BENCH_SCHEDULE, (512, True, 0)])
 def test_cavity_cfg2_full_run_vs_stored_oracle(F, schedule):
     ref = np.load(os.path.join(GOLDEN, "oracle_cavity100_rk4_2000.npz"))
     m = mg.cavity(n=100, ratio=1.08, jitter=0.2, seed=0, lid_u=0.1)
@@ -411,7 +411,7 @@ def test_cavity_cfg2_full_run_vs_stored_oracle(F, schedule):
         assert np.abs(rho[idx] - ref["rho"]).max() <= utol * 0.1
 
 
-@pytest.mark.parametrize("schedule", [None, BENCH_SCHEDULE])
+@pytest.mark.parametrize("schedule", [None, BENCH_SCHEDULE, (512, True, 0), (128, False, 1)])
 def test_cylinder_cfg3_full_size_vs_stored_oracle(F, schedule):
     ref = np.load(os.path.join(GOLDEN, "oracle_cylinder256_rk4_100.npz"))
     m = mg.cylinder(nr=256, nt=384)
