@@ -42,11 +42,14 @@ MESH_BYTES = {3: 60, 4: 72}
 STATE_VALUES = {"euler": 18, "rk4": 99}   # stored values moved per cell-update
 # bytes per stored value: the 16-bit block-scaled format adds one exponent byte per nine values
 STORE_BYTES = {"fp32": 4.0, "fp32dev": 4.0, "fp16dev": 2.0, "i16dev": 19.0 / 9.0}
+# FP16 deviations also carry each cell's mass and momentum rounding residual
+# (three FP16 values), read and rewritten once per step by its last stage
+CARRY_BYTES = {"fp16dev": 12.0}
 
 
-def alg_bytes_per_update(nf: int, scheme: str, sbytes: int) -> float:
+def alg_bytes_per_update(nf: int, scheme: str, storage: str) -> float:
     n_rhs = 4 if scheme == "rk4" else 1
-    return STATE_VALUES[scheme] * sbytes + n_rhs * MESH_BYTES[nf]
+    return STATE_VALUES[scheme] * STORE_BYTES[storage] + CARRY_BYTES.get(storage, 0.0) + n_rhs * MESH_BYTES[nf]
 
 
 def measured_traffic(schedule):
@@ -116,7 +119,7 @@ def streaming(F, W, stream, schedule=None):
         el = events_time(stream, lambda: s.step(k))
         n_launch = k * (4 if scheme == "rk4" else 1)
         t_launch = el / n_launch
-        alg = alg_bytes_per_update(nf, scheme, STORE_BYTES[storage]) / (4 if scheme == "rk4" else 1) * m.n_cells
+        alg = alg_bytes_per_update(nf, scheme, storage) / (4 if scheme == "rk4" else 1) * m.n_cells
         out[f"{scheme}_{storage}"] = dict(cells=m.n_cells, steps=k,
                                           M_cell_updates_per_s=round(m.n_cells * k / el / 1e6, 1),
                                           launch_ms=round(t_launch * 1e3, 4), achieved_GBs=round(alg / t_launch / 1e9, 1),
@@ -233,9 +236,8 @@ def main():
         s.step(args.warmup)
         el = events_time(stream, lambda: s.step(args.steps))
         n = inst.n_cells
-        sbytes = STORE_BYTES[args.storage]
         t_launch = el / (4 * args.steps)
-        alg_launch = alg_bytes_per_update(nf, "rk4", sbytes) / 4 * n
+        alg_launch = alg_bytes_per_update(nf, "rk4", args.storage) / 4 * n
         rho, u, st = s.macros()
         rec.update({
             "metric": "M cell-updates/s (D2Q9, FP32)",

@@ -72,7 +72,13 @@ typedef struct {
     int32_t scheme;        /* FVLBM_SCHEME_* */
     int32_t storage;       /* FVLBM_STORE_*: f as FP32, h = f - f_eq(rho0, u_dev) as FP32, h/(w S) as FP16,
                               or h as 16-bit block-scaled values (per cell nine int16 mantissas and one
-                              exponent byte: 19 bytes per cell, 15 bits for the largest deviation) */
+                              exponent byte: 19 bytes per cell, 15 bits for the largest deviation).
+                              FP16: a cell's nine values are rounded together so that its mass and
+                              momentum lose as little as the format allows, and what is left (three FP16
+                              values per cell, 6 bytes) is carried to the next step's update: the state is
+                              the stored values less that carry.  fvlbm_macros and the residual include
+                              it; fvlbm_get_f, fvlbm_rhs and fvlbm_wall_force see the stored values;
+                              fvlbm_set_f and Step 0 set it from their own rounding */
     double rho0;           /* reference density of the deviation storage (and of Step 0 when no field is given) */
     double fp16_scale;     /* S of the FP16 deviation storage; 0 = 3 |u_ref| (or 0.3 if u_ref = 0) */
     int32_t residual_lag;  /* steps between velocity snapshots for the residual (Eq. 32); 0 = 1000 */

@@ -35,8 +35,11 @@ int n_fbufs(int scheme) { return scheme == FVLBM_SCHEME_RK4 ? 3 : 2; }
 constexpr double BETA[4] = {0.25, 1.0 / 3.0, 0.5, 1.0};
 
 struct Layout {
-    size_t fbuf[3], r32, snap[2], partial, scal, flag, out, total;
+    size_t fbuf[3], r32, mc, snap[2], partial, scal, flag, out, total;
 };
+
+// FP16 storage's moment carry: 3 FP16 planes of np (see the step kernel's ConsF16)
+size_t carry_bytes(int storage, int np) { return storage == FVLBM_STORE_FP16_DEV ? (size_t)3 * np * 2 : 0; }
 
 Layout layout(int n, int np, const fvlbm_params &p) {
     Layout L{};
@@ -45,6 +48,7 @@ Layout layout(int n, int np, const fvlbm_params &p) {
     size_t fb = state_copy_bytes(p.storage, np);
     for (int k = 0; k < 3; k++) L.fbuf[k] = k < n_fbufs(p.scheme) ? take(fb) : 0;
     L.r32 = take((size_t)Q * np * sizeof(float));
+    L.mc = take(carry_bytes(p.storage, np));
     L.snap[0] = take((size_t)2 * n * sizeof(double));
     L.snap[1] = take((size_t)2 * n * sizeof(double));
     L.partial = take((size_t)2 * reduce_blocks(n * MAX_NF) * sizeof(double));   // also wall-face sums
@@ -133,6 +137,9 @@ fvlbm_status make_units(const std::vector<std::pair<int, int>> &inst, int block,
 }
 
 void *fptr(fvlbm_solver *s, int k) { return s->buf + s->L.fbuf[k]; }
+__half *carry_ptr(fvlbm_solver *s) {
+    return s->p.storage == FVLBM_STORE_FP16_DEV ? reinterpret_cast<__half *>(s->buf + s->L.mc) : nullptr;
+}
 
 InstDesc base_desc(fvlbm_solver *s, const TileTables *tt) {
     const MeshDev &m = s->mesh->dev;
@@ -154,6 +161,7 @@ InstDesc base_desc(fvlbm_solver *s, const TileTables *tt) {
         d.groups[g].rho = (float)b.rho;
     }
     d.rhs_prev = reinterpret_cast<float *>(s->buf + s->L.r32);
+    d.mcarry = nullptr;
     return d;
 }
 
@@ -186,6 +194,8 @@ void fill_descs(fvlbm_solver *s, const TileTables *tt, InstDesc out[N_KINDS]) {
     set(RH0, 0, 0, -1, 0, 3);
     set(RH1, 1, 1, -1, 0, 3);
     set(RH2, 2, 2, -1, 0, 3);
+    // the stage that ends a step adds the carried moment residual back and rewrites it
+    for (int k : {E0, E1, R4, F0, F1, A0, A1}) out[k].mcarry = carry_ptr(s);
 }
 
 // The sequence of stage kinds of one step, given the solver's position.
@@ -209,7 +219,7 @@ hipError_t take_snapshot(fvlbm_solver *s) {
     const double *snap_old = s->snap_cur < 0 ? nullptr : reinterpret_cast<double *>(s->buf + s->L.snap[s->snap_cur]);
     double *partial = reinterpret_cast<double *>(s->buf + s->L.partial);
     double *scal = reinterpret_cast<double *>(s->buf + s->L.scal);
-    hipError_t e = launch_snapshot(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref,
+    hipError_t e = launch_snapshot(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref, carry_ptr(s),
                                    snap_new, snap_old, partial, s->stream);
     if (e == hipSuccess && snap_old) e = launch_finish_sums(partial, reduce_blocks(m.n_cells), scal, 1, s->stream);
     s->snap_cur = nxt;
@@ -436,7 +446,7 @@ fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const doub
     }
     if (e == hipSuccess)
         e = launch_init_eq(fptr(s.get(), 0), p.storage, m.n_cells, m.np, s->ref, rho_dev, u_dev,
-                           m.perm_dev, p.rho0, s->stream);
+                           m.perm_dev, p.rho0, carry_ptr(s.get()), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("init failed: ") + hipGetErrorString(e));
     mesh->refs++;
@@ -494,7 +504,7 @@ fvlbm_status fvlbm_macros(fvlbm_solver *s, double *rho, double *u, double *stats
     int zero = 0;
     hipError_t e = hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
-        e = launch_macros(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref, m.area, m.perm_dev,
+        e = launch_macros(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref, carry_ptr(s), m.area, m.perm_dev,
                           out, out + m.n_cells, partial, flag, s->stream);
     if (e == hipSuccess) e = launch_finish_sums(partial, reduce_blocks(m.n_cells), scal, 0, s->stream);
     double sc[2] = {0, -1};
@@ -559,7 +569,8 @@ fvlbm_status fvlbm_set_f(fvlbm_solver *s, const double *f) {
     const MeshDev &m = s->mesh->dev;
     double *stage = reinterpret_cast<double *>(s->buf + s->L.out);
     hipError_t e = hipMemcpyAsync(stage, f, (size_t)Q * m.n_cells * sizeof(double), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = launch_set_f(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref, m.perm_dev, stage, s->stream);
+    if (e == hipSuccess)
+        e = launch_set_f(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref, m.perm_dev, stage, carry_ptr(s), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
     s->have_prev = false;
@@ -590,7 +601,7 @@ size_t fvlbm_checkpoint_bytes(const fvlbm_solver *s) {
     const MeshDev &m = s->mesh->dev;
     size_t fb = state_copy_bytes(s->p.storage, m.np);
     size_t extra = s->p.scheme == FVLBM_SCHEME_AB2 ? (size_t)Q * m.np * sizeof(float) : 0;
-    return 64 + fb + extra;
+    return 64 + fb + extra + carry_bytes(s->p.storage, m.np);
 }
 
 fvlbm_status fvlbm_checkpoint(fvlbm_solver *s, void *host_buf, size_t bytes) {
@@ -600,8 +611,12 @@ fvlbm_status fvlbm_checkpoint(fvlbm_solver *s, void *host_buf, size_t bytes) {
     int64_t hdr[8] = {0x46564c424d31LL, s->steps, s->p.storage, s->p.scheme, m.n_cells, s->have_prev, 0, 0};
     std::memcpy(host_buf, hdr, 64);
     hipError_t e = hipMemcpyAsync((char *)host_buf + 64, fptr(s, s->cur), fb, hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess && s->p.scheme == FVLBM_SCHEME_AB2)
-        e = hipMemcpyAsync((char *)host_buf + 64 + fb, s->buf + s->L.r32, (size_t)Q * m.np * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+    const size_t rb = s->p.scheme == FVLBM_SCHEME_AB2 ? (size_t)Q * m.np * sizeof(float) : 0;
+    if (e == hipSuccess && rb)
+        e = hipMemcpyAsync((char *)host_buf + 64 + fb, s->buf + s->L.r32, rb, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && carry_ptr(s))
+        e = hipMemcpyAsync((char *)host_buf + 64 + fb + rb, carry_ptr(s), carry_bytes(s->p.storage, m.np),
+                           hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
     return FVLBM_OK;
@@ -617,8 +632,12 @@ fvlbm_status fvlbm_restore(fvlbm_solver *s, const void *host_buf, size_t bytes) 
     size_t fb = state_copy_bytes(s->p.storage, m.np);
     s->cur = 0;
     hipError_t e = hipMemcpyAsync(fptr(s, 0), (const char *)host_buf + 64, fb, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess && s->p.scheme == FVLBM_SCHEME_AB2)
-        e = hipMemcpyAsync(s->buf + s->L.r32, (const char *)host_buf + 64 + fb, (size_t)Q * m.np * sizeof(float), hipMemcpyHostToDevice, s->stream);
+    const size_t rb = s->p.scheme == FVLBM_SCHEME_AB2 ? (size_t)Q * m.np * sizeof(float) : 0;
+    if (e == hipSuccess && rb)
+        e = hipMemcpyAsync(s->buf + s->L.r32, (const char *)host_buf + 64 + fb, rb, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess && carry_ptr(s))
+        e = hipMemcpyAsync(carry_ptr(s), (const char *)host_buf + 64 + fb + rb, carry_bytes(s->p.storage, m.np),
+                           hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
     s->steps = hdr[1];
@@ -846,7 +865,7 @@ fvlbm_status batch_enqueue(fvlbm_batch *b, int64_t n_steps, bool snapshots) {
 struct Saved {
     fvlbm_solver *s = nullptr;
     char *dev = nullptr;
-    size_t fb = 0, rb = 0;
+    size_t fb = 0, rb = 0, cb = 0;
     int cur = 0;
     int64_t steps = 0;
     bool have_prev = false;
@@ -857,9 +876,11 @@ fvlbm_status save_state(fvlbm_solver *s, Saved &sv) {
     sv.s = s;
     sv.fb = state_copy_bytes(s->p.storage, m.np);
     sv.rb = s->p.scheme == FVLBM_SCHEME_AB2 ? (size_t)Q * m.np * sizeof(float) : 0;
-    if (hipMalloc(&sv.dev, sv.fb + sv.rb) != hipSuccess) return fail(FVLBM_E_NOMEM, "autotune state copy allocation failed");
+    sv.cb = carry_bytes(s->p.storage, m.np);
+    if (hipMalloc(&sv.dev, sv.fb + sv.rb + sv.cb) != hipSuccess) return fail(FVLBM_E_NOMEM, "autotune state copy allocation failed");
     hipError_t e = hipMemcpyAsync(sv.dev, fptr(s, s->cur), sv.fb, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess && sv.rb) e = hipMemcpyAsync(sv.dev + sv.fb, s->buf + s->L.r32, sv.rb, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && sv.cb) e = hipMemcpyAsync(sv.dev + sv.fb + sv.rb, carry_ptr(s), sv.cb, hipMemcpyDeviceToDevice, s->stream);
     if (e != hipSuccess) return fail(FVLBM_E_DEVICE, "autotune state copy failed");
     sv.cur = s->cur;
     sv.steps = s->steps;
@@ -871,6 +892,7 @@ fvlbm_status restore_state(Saved &sv) {
     fvlbm_solver *s = sv.s;
     hipError_t e = hipMemcpyAsync(fptr(s, sv.cur), sv.dev, sv.fb, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess && sv.rb) e = hipMemcpyAsync(s->buf + s->L.r32, sv.dev + sv.fb, sv.rb, hipMemcpyDeviceToDevice, s->stream);
+    if (e == hipSuccess && sv.cb) e = hipMemcpyAsync(carry_ptr(s), sv.dev + sv.fb + sv.rb, sv.cb, hipMemcpyDeviceToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     hipFree(sv.dev);
     sv.dev = nullptr;

@@ -35,8 +35,23 @@ __device__ inline void load_cell_dev(const void *p, int storage, int np, int i, 
     }
 }
 
-// round-to-nearest narrowing of FP64 deviations into cell i's storage
-__device__ inline void store_cell_dev(void *p, int storage, int np, int i, const double h[Q], const RefDev &r) {
+// FP16 storage: the cell's carried moment residual R (mass, momentum less the
+// exact ones, units of S; 3 FP16 planes scaled by 2^20, as the step kernel
+// writes them) taken out of the deviations as the equilibrium-shaped change
+// -S w_a (R_0 + 3 e_a . R).
+constexpr double CARRY_SCALE = 1048576.0;
+__device__ inline void uncarry(const __half *carry, int np, int i, const RefDev &r, double h[Q]) {
+    if (!carry) return;
+    double R[3];
+    for (int k = 0; k < 3; k++) R[k] = (double)__half2float(carry[(size_t)k * np + i]) / CARRY_SCALE;
+    for (int a = 0; a < Q; a++) h[a] -= (double)r.scale * WD[a] * (R[0] + 3.0 * (EXd[a] * R[1] + EYd[a] * R[2]));
+}
+
+// round-to-nearest narrowing of FP64 deviations into cell i's storage (FP16
+// storage with a carry: the rounding residual of the cell's mass and momentum
+// is written to it)
+__device__ inline void store_cell_dev(void *p, int storage, int np, int i, const double h[Q], const RefDev &r,
+                                      __half *carry = nullptr) {
     if (storage == FVLBM_STORE_I16_DEV) {
         double m = 0.0;
         for (int a = 0; a < Q; a++) m = fmax(m, fabs(h[a]));
@@ -50,17 +65,26 @@ __device__ inline void store_cell_dev(void *p, int storage, int np, int i, const
         static_cast<uint8_t *>(p)[(size_t)np * 18 + i] = (uint8_t)sb;
         return;
     }
+    double R[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < Q; a++) {
         const size_t idx = (size_t)a * np + i;
         if (storage == FVLBM_STORE_FP32) static_cast<float *>(p)[idx] = (float)(wref(a, r) + h[a]);
         else if (storage == FVLBM_STORE_FP32_DEV) static_cast<float *>(p)[idx] = (float)h[a];
-        else static_cast<__half *>(p)[idx] = __float2half_rn((float)(h[a] / (double)(WF[a] * r.scale)));
+        else {
+            const __half q = __float2half_rn((float)(h[a] / (double)(WF[a] * r.scale)));
+            static_cast<__half *>(p)[idx] = q;
+            const double e = ((double)__half2float(q) * (double)(WF[a] * r.scale) - h[a]) / (double)r.scale;
+            R[0] += e; R[1] += EXd[a] * e; R[2] += EYd[a] * e;
+        }
     }
+    if (carry && storage == FVLBM_STORE_FP16_DEV)
+        for (int k = 0; k < 3; k++)
+            carry[(size_t)k * np + i] = __float2half_rn((float)fmin(fmax(R[k] * CARRY_SCALE, -65504.0), 65504.0));
 }
 
 // Step 0: f = f_eq(rho, u) (Eq. 3), written as deviations from the reference equilibrium.
 __global__ void k_init_eq(void *dst, int storage, int n, int np, RefDev ref,
-                          const double *rho, const double *u, const int *perm, double rho_u) {
+                          const double *rho, const double *u, const int *perm, double rho_u, __half *carry) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int c = perm[i];
@@ -73,7 +97,7 @@ __global__ void k_init_eq(void *dst, int storage, int n, int np, RefDev ref,
         double feq = WD[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
         h[a] = feq - wref(a, ref);
     }
-    store_cell_dev(dst, storage, np, i, h, ref);
+    store_cell_dev(dst, storage, np, i, h, ref, carry);
 }
 
 __global__ void k_get_f(const void *src, int storage, int n, int np, RefDev ref,
@@ -87,13 +111,13 @@ __global__ void k_get_f(const void *src, int storage, int n, int np, RefDev ref,
 }
 
 __global__ void k_set_f(void *dst, int storage, int n, int np, RefDev ref,
-                        const int *perm, const double *f) {
+                        const int *perm, const double *f, __half *carry) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int c = perm[i];
     double h[Q];
     for (int a = 0; a < Q; a++) h[a] = f[(size_t)c * Q + a] - wref(a, ref);
-    store_cell_dev(dst, storage, np, i, h, ref);
+    store_cell_dev(dst, storage, np, i, h, ref, carry);
 }
 
 __global__ void k_rhs_out(const float *rhs, int n, int np, const int *perm, double *out) {
@@ -116,7 +140,7 @@ __device__ inline void block_sum2(double a, double b, double *partial) {
 }
 
 // Step 6 (Eq. 5) in FP64 from the stored state; mass = sum A rho; flag on non-finite values.
-__global__ void k_macros(const void *src, int storage, int n, int np, RefDev ref,
+__global__ void k_macros(const void *src, int storage, int n, int np, RefDev ref, const __half *carry,
                          const double *area, const int *perm, double *rho_out, double *u_out,
                          double *partial, int *flag) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,6 +148,7 @@ __global__ void k_macros(const void *src, int storage, int n, int np, RefDev ref
     if (i < n) {
         double r = 0, mx = 0, my = 0, h[Q];
         load_cell_dev(src, storage, np, i, ref, h);
+        uncarry(carry, np, i, ref, h);
         for (int a = 0; a < Q; a++) {
             double f = wref(a, ref) + h[a];
             r += f;
@@ -141,13 +166,14 @@ __global__ void k_macros(const void *src, int storage, int n, int np, RefDev ref
 }
 
 // Velocity snapshot for the residual; partial sums of |u - u_old|^2 and |u_old|^2.
-__global__ void k_snapshot(const void *src, int storage, int n, int np, RefDev ref,
+__global__ void k_snapshot(const void *src, int storage, int n, int np, RefDev ref, const __half *carry,
                            double *snap_new, const double *snap_old, double *partial) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     double num = 0, den = 0;
     if (i < n) {
         double r = 0, mx = 0, my = 0, h[Q];
         load_cell_dev(src, storage, np, i, ref, h);
+        uncarry(carry, np, i, ref, h);
         for (int a = 0; a < Q; a++) {
             double f = wref(a, ref) + h[a];
             r += f; mx += EXd[a] * f; my += EYd[a] * f;
@@ -249,8 +275,9 @@ RefDev make_ref(double rho0, double ux, double uy, double scale) {
 
 hipError_t launch_init_eq(void *dst, int storage, int n, int np, const RefDev &ref,
                           const double *rho_dev, const double *u_dev, const int *perm_dev,
-                          double rho_u, hipStream_t stream) {
-    hipLaunchKernelGGL(k_init_eq, grid(n), dim3(RB), 0, stream, dst, storage, n, np, ref, rho_dev, u_dev, perm_dev, rho_u);
+                          double rho_u, __half *carry, hipStream_t stream) {
+    hipLaunchKernelGGL(k_init_eq, grid(n), dim3(RB), 0, stream, dst, storage, n, np, ref, rho_dev, u_dev, perm_dev, rho_u,
+                       carry);
     return hipGetLastError();
 }
 
@@ -261,8 +288,8 @@ hipError_t launch_get_f(const void *src, int storage, int n, int np, const RefDe
 }
 
 hipError_t launch_set_f(void *dst, int storage, int n, int np, const RefDev &ref,
-                        const int *perm_dev, const double *f_dev, hipStream_t stream) {
-    hipLaunchKernelGGL(k_set_f, grid(n), dim3(RB), 0, stream, dst, storage, n, np, ref, perm_dev, f_dev);
+                        const int *perm_dev, const double *f_dev, __half *carry, hipStream_t stream) {
+    hipLaunchKernelGGL(k_set_f, grid(n), dim3(RB), 0, stream, dst, storage, n, np, ref, perm_dev, f_dev, carry);
     return hipGetLastError();
 }
 
@@ -272,10 +299,11 @@ hipError_t launch_rhs_out(const float *rhs32, int n, int np, const int *perm_dev
     return hipGetLastError();
 }
 
-hipError_t launch_macros(const void *src, int storage, int n, int np, const RefDev &ref,
+hipError_t launch_macros(const void *src, int storage, int n, int np, const RefDev &ref, const __half *carry,
                          const double *area, const int *perm_dev, double *rho_out, double *u_out,
                          double *partial, int *flag, hipStream_t stream) {
-    hipLaunchKernelGGL(k_macros, grid(n), dim3(RB), 0, stream, src, storage, n, np, ref, area, perm_dev, rho_out, u_out, partial, flag);
+    hipLaunchKernelGGL(k_macros, grid(n), dim3(RB), 0, stream, src, storage, n, np, ref, carry, area, perm_dev, rho_out,
+                       u_out, partial, flag);
     return hipGetLastError();
 }
 
@@ -287,10 +315,11 @@ hipError_t launch_wall_force(const void *src, int storage, int np, const RefDev 
     return hipGetLastError();
 }
 
-hipError_t launch_snapshot(const void *src, int storage, int n, int np, const RefDev &ref,
+hipError_t launch_snapshot(const void *src, int storage, int n, int np, const RefDev &ref, const __half *carry,
                            double *snap_new, const double *snap_old, double *partial,
                            hipStream_t stream) {
-    hipLaunchKernelGGL(k_snapshot, grid(n), dim3(RB), 0, stream, src, storage, n, np, ref, snap_new, snap_old, partial);
+    hipLaunchKernelGGL(k_snapshot, grid(n), dim3(RB), 0, stream, src, storage, n, np, ref, carry, snap_new, snap_old,
+                       partial);
     return hipGetLastError();
 }
 

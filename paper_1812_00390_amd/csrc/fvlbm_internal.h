@@ -143,6 +143,9 @@ struct InstDesc {
     const void *base;     // f(0) of the update (== src for Euler / AB2)
     void *dst;
     float *rhs_prev;      // AB2 history (FP32 planes), or null
+    __half *mcarry;       // FP16 storage, the last stage of a step: the rounding residual of each cell's
+                          // mass and momentum (3 FP16 planes of 2^12 x the residual in units of S), added
+                          // back to the update's base and rewritten by the store; null elsewhere
     int n_cells, np;
     float coef;           // dst = base + coef * RHS   (AB2: dt)
     float inv_tau;
@@ -210,21 +213,25 @@ hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode
                           const InstDesc *host_desc = nullptr);
 
 // Step 0 and conversions (FP64 host data in input order <-> device storage).
+// carry: FP16 storage's moment carry (3 planes of np), written with the rounding residual of
+// each cell's mass and momentum (null for the other storages).
 hipError_t launch_init_eq(void *dst, int storage, int n, int np, const RefDev &ref,
                           const double *rho_dev, const double *u_dev, const int *perm_dev,
-                          double rho_u, hipStream_t stream);
+                          double rho_u, __half *carry, hipStream_t stream);
 hipError_t launch_get_f(const void *src, int storage, int n, int np, const RefDev &ref,
                         const int *perm_dev, double *f_dev, hipStream_t stream);
 hipError_t launch_set_f(void *dst, int storage, int n, int np, const RefDev &ref,
-                        const int *perm_dev, const double *f_dev, hipStream_t stream);
+                        const int *perm_dev, const double *f_dev, __half *carry, hipStream_t stream);
 hipError_t launch_rhs_out(const float *rhs32, int n, int np, const int *perm_dev, double *out_dev,
                           hipStream_t stream);
 
 // Step 6 + FP64 reductions.  Writes rho/u (input order, FP64) and partial sums.
-hipError_t launch_macros(const void *src, int storage, int n, int np, const RefDev &ref,
+// carry: FP16 storage's moment carry (the state is the stored values less the carried
+// residual of each cell's mass and momentum), or null.
+hipError_t launch_macros(const void *src, int storage, int n, int np, const RefDev &ref, const __half *carry,
                          const double *area, const int *perm_dev, double *rho_out, double *u_out,
                          double *partial, int *flag, hipStream_t stream);
-hipError_t launch_snapshot(const void *src, int storage, int n, int np, const RefDev &ref,
+hipError_t launch_snapshot(const void *src, int storage, int n, int np, const RefDev &ref, const __half *carry,
                            double *snap_new, const double *snap_old, double *partial,
                            hipStream_t stream);
 // partial: [nblk][2] -> out[0] = sum col0, out[1] = sum col1 (fixed order)

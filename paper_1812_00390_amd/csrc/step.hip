@@ -109,6 +109,105 @@ __device__ inline __half round_fp16(float v, float p, uint32_t key, int a) {
     return __float2half_rz(__uint_as_float((b & 0x80000000u) | mag));
 }
 
+// FP16 deviations x_a = h_a / (w_a S), rounded so that the stored cell keeps
+// its mass and momentum.  Each value is rounded without bias (round_fp16), but
+// nine independent roundings leave an error in the cell's conserved moments,
+// which the collision does not relax, so it adds up from step to step as a
+// random walk.  The values are therefore rounded one after another, each
+// target corrected for the moment error of the values rounded before it
+// (errors e_a = (q_a - x_a) w_a, in units of S):
+//   cardinals by opposite pairs: 1, then 3 carrying 1's error (the pair's
+//   momentum e_1 (E_1 - E_3) then keeps only 3's rounding); 2, then 4;
+//   the pairs' remaining momentum error R goes to the diagonals as the
+//   least-norm change that carries no mass, x_d - (e_d . R) / (4 w_d);
+//   diagonals by opposite pairs the same way: 5, then 7; 6, then 8;
+//   the mass error of all eight moving values goes to the rest value,
+//   x_0 - sum_a e_a / w_0.
+// The momentum error left is the rounding of one diagonal per diagonal axis
+// (a quarter of a cardinal's weight), and the mass error that of the rest
+// value (its deviation is small, second order in the velocity).  Every target
+// is the exact value plus zero-mean corrections and every rounding is
+// unbiased, so the expected stored value is still the exact one.
+// res receives what is left: the stored cell's mass and momentum less the
+// exact ones, in units of S.  The last stage of a step stores it beside the
+// state and the next step's last stage adds it back to its base (see
+// carry_correction), so the conserved moments carry no rounding from step to
+// step; only the non-conserved moments keep a rounding error, which the
+// collision relaxes.
+// e_a . (x, y) for the D2Q9 velocities, folded per direction (no products by 0)
+__device__ __forceinline__ float edot(int a, float x, float y) {
+    switch (a) {
+    case 0: return 0.f;
+    case 1: return x;
+    case 2: return y;
+    case 3: return -x;
+    case 4: return -y;
+    case 5: return x + y;
+    case 6: return y - x;
+    case 7: return -x - y;
+    default: return x - y;
+    }
+}
+
+struct ConsF16 {
+    __device__ static void store(void *buf, size_t np, int c, const float b[Q], const float inc[Q], const RefDev &r,
+                                 uint32_t key0, float res[3]) {
+        const uint32_t off = (uint32_t)c * 2u;
+        float x[Q], e[Q];
+        __half q[Q];
+#pragma unroll
+        for (int a = 0; a < Q; a++) x[a] = (b[a] + inc[a]) * r.inv_unit[a];
+        // rounds value a to target t; returns its rounding error (q - t) w_a and sets e_a = (q - x_a) w_a
+        auto rnd = [&](int a, float t) {
+            q[a] = round_fp16(t, inc[a], key0, a);
+            const float qf = __half2float(q[a]);
+            e[a] = (qf - x[a]) * WT[a];
+            return (qf - t) * WT[a];
+        };
+        // cardinal pairs (1, 3) and (2, 4): the second carries the first's rounding (weights equal)
+        rnd(3, x[3] + rnd(1, x[1]) * 9.f);                  // 1 / w = 9
+        rnd(4, x[4] + rnd(2, x[2]) * 9.f);
+        const float rx = e[1] - e[3], ry = e[2] - e[4];
+        // diagonal pairs (5, 7) and (6, 8): least-norm share of R, then the pair carry
+        const float s57 = rx + ry, s68 = ry - rx;           // e_5 . R, e_6 . R (e_7 = -e_5, e_8 = -e_6)
+        const float r5 = rnd(5, fmaf(-9.f, s57, x[5]));      // 1 / (4 w_d) = 9
+        rnd(7, fmaf(36.f, r5, fmaf(9.f, s57, x[7])));       // 1 / w_d = 36
+        const float r6 = rnd(6, fmaf(-9.f, s68, x[6]));
+        rnd(8, fmaf(36.f, r6, fmaf(9.f, s68, x[8])));
+        const float rm = ((e[1] + e[2]) + (e[3] + e[4])) + ((e[5] + e[6]) + (e[7] + e[8]));
+        rnd(0, fmaf(-2.25f, rm, x[0]));                       // 1 / w_0 = 9/4
+#pragma unroll
+        for (int a = 0; a < Q; a++) sto<__half>(plane(buf, np * 2, a), off, q[a]);
+        res[0] = e[0] + rm;
+        res[1] = ((e[1] - e[3]) + (e[5] - e[7])) + (e[8] - e[6]);
+        res[2] = ((e[2] - e[4]) + (e[5] - e[7])) + (e[6] - e[8]);
+    }
+};
+
+// The moment carry of FP16 storage: 3 planes of np FP16 values, 2^20 x the
+// residual (mass, x- and y-momentum, units of S) of a cell's last store.  The
+// scale keeps residuals from 6e-14 to 6e-2 S representable (a residual is at
+// most a few ulps of a value times its weight); larger ones, which only a
+// diverged state makes, saturate instead of overflowing.
+constexpr float CARRY_SCALE = 1048576.f;
+__device__ inline void load_carry(const __half *cp, size_t np, int c, float cr[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) cr[k] = __half2float(ldo<__half>(plane(cp, np * 2, k), (uint32_t)c * 2u)) * (1.f / CARRY_SCALE);
+}
+__device__ inline void store_carry(__half *cp, size_t np, int c, const float res[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        sto<__half>(plane(cp, np * 2, k), (uint32_t)c * 2u,
+                    __float2half_rn(fminf(fmaxf(res[k] * CARRY_SCALE, -65504.f), 65504.f)));
+}
+// The exact state is the stored one less the carried residual R: the
+// equilibrium-shaped change -S w_a (R_0 + 3 e_a . (R_x, R_y)) carries exactly
+// -S R in mass and momentum (sum w = 1, sum w e e = I/3) and nothing else the
+// collision does not relax.
+__device__ inline float carry_correction(int a, const float cr[3], float S) {
+    return -S * WT[a] * fmaf(3.f, edot(a, cr[1], cr[2]), cr[0]);
+}
+
 // A storage format: load(plane base, byte offset, direction) returns the
 // deviation h; store(.., b, inc, ..) writes b + inc (b a deviation).
 template <int STORE>
@@ -138,9 +237,7 @@ struct Storage<FVLBM_STORE_FP16_DEV> {
     __device__ static float load(const void *p, uint32_t off, int a, const RefDev &r) {
         return __half2float(ldo<__half>(p, off)) * (WT[a] * r.scale);
     }
-    __device__ static void store(void *p, uint32_t off, int a, float b, float inc, const RefDev &r, uint32_t key) {
-        sto<__half>(p, off, round_fp16((b + inc) * r.inv_unit[a], inc, key, a));
-    }
+    // (stores go through ConsF16: a cell's nine values are rounded together)
 };
 
 // 16-bit block-scaled deviations: per cell nine int16 mantissas and one
@@ -196,9 +293,13 @@ __device__ inline void load_cell(const void *buf, size_t np, int c, float f[Q], 
 }
 template <int STORE>
 __device__ inline void store_cell(void *buf, size_t np, int c, const float b[Q], const float inc[Q], const RefDev &r,
-                                  uint32_t key0) {
+                                  uint32_t key0, __half *carry = nullptr) {
     if constexpr (STORE == FVLBM_STORE_I16_DEV) {
         BlockI16::store(buf, np, c, b, inc, key0);
+    } else if constexpr (STORE == FVLBM_STORE_FP16_DEV) {
+        float res[3];
+        ConsF16::store(buf, np, c, b, inc, r, key0, res);
+        if (carry) store_carry(carry, np, c, res);
     } else {
         using S = Storage<STORE>;
         const uint32_t off = (uint32_t)c * S::SZ;
@@ -238,27 +339,13 @@ __device__ inline void load_set(const void *buf, size_t np, int c, float f[Q], c
 template <int STORE, int H>
 __device__ inline void store_half(void *buf, size_t np, int c, const float b[Q], const float inc[Q], const RefDev &r,
                                   uint32_t key0) {
-    static_assert(STORE != FVLBM_STORE_I16_DEV, "the block-scaled format stores a cell whole");
+    static_assert(STORE != FVLBM_STORE_I16_DEV && STORE != FVLBM_STORE_FP16_DEV,
+                  "the block-scaled and FP16 formats store a cell whole");
     using S = Storage<STORE>;
     const uint32_t off = (uint32_t)c * S::SZ;
 #pragma unroll
     for (int a = 0; a < Q; a++)
         if (in_set(H, a)) S::store(plane(buf, np * S::SZ, a), off, a, b[a], inc[a], r, key0);
-}
-
-// e_a . (x, y) for the D2Q9 velocities, folded per direction (no products by 0)
-__device__ __forceinline__ float edot(int a, float x, float y) {
-    switch (a) {
-    case 0: return 0.f;
-    case 1: return x;
-    case 2: return y;
-    case 3: return -x;
-    case 4: return -y;
-    case 5: return x + y;
-    case 6: return y - x;
-    case 7: return -x - y;
-    default: return x - y;
-    }
 }
 
 struct Macro {
@@ -420,9 +507,12 @@ __device__ inline int remap_block(int b, int nb, int xcd_remap) {
 
 __device__ inline int unpack16(uint32_t w, int hi) { return (int)(int16_t)(hi ? (w >> 16) : (w & 0xffffu)); }
 
-// The 64-cell halo-wave form with per-value storage splits phase 2 and 3 by
-// directions over more waves.
-constexpr bool split_form(int T, int STORE, bool RING) { return RING && T == 64 && STORE != FVLBM_STORE_I16_DEV; }
+// The 64-cell halo-wave form with FP32 storage splits phase 2 and 3 by
+// directions over more waves (the 16-bit formats round a cell's nine values
+// together, so one thread stores the whole cell).
+constexpr bool split_form(int T, int STORE, bool RING) {
+    return RING && T == 64 && STORE != FVLBM_STORE_I16_DEV && STORE != FVLBM_STORE_FP16_DEV;
+}
 // Threads per workgroup of a stage kernel: the tile's cells, a wave for the halo
 // slots (RING), two waves for directions 5-8 of the gradients (split form).
 constexpr int tile_threads(int T, int STORE, bool RING) {
@@ -697,7 +787,7 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
                                             const int (&code)[NF], uint2 packed, const CellGeo<NF> &geo, const CellFaces<NF> &cf,
                                             const float4 *own, const float4 *A, int sa, const GroupDev *lg,
                                             const float bsave[Q], int bsave_k, const float4 *stash, int ss,
-                                            const float4 *lneq) {
+                                            const float4 *lneq, const float (&cr)[3]) {
     float hi[Q], gxi[Q], gyi[Q];
     hi[0] = h0;
     rd_f(own, sa, hi);
@@ -778,10 +868,19 @@ __device__ __forceinline__ void tile_update(const InstDesc &d, int i, float h0, 
             sto<float>(plane(d.rhs_prev, pb4, a), o4, rhs);
         }
     }
+    if constexpr (STORE == FVLBM_STORE_FP16_DEV) {
+        // the last stage of a step: the exact base is the stored one less the carried
+        // rounding residual of its conserved moments (loaded in phase 1 into cr)
+        if (d.mcarry) {
+#pragma unroll
+            for (int a = 0; a < Q; a++) bv[a] += carry_correction(a, cr, d.ref.scale);
+        }
+    }
     if constexpr (H >= 0)
         store_half<STORE, H>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i);
     else if (mode != 3)
-        store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i);
+        store_cell<STORE>(d.dst, (size_t)d.np, i, bv, inc, d.ref, (uint32_t)i,
+                          STORE == FVLBM_STORE_FP16_DEV ? d.mcarry : nullptr);
 }
 
 // The values a tile's loads depend on (kernel arguments for a single instance).
@@ -931,6 +1030,10 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     const int gv1 = ldg(gsrc, BS < GW && tid + BS < GW ? tid + BS : 0);
     const void *basep = DIRECT ? hot.base : d.base;
     const bool sep_base = (M0 || d.mode == 0) && basep != src;
+    // FP16 storage, the last stage of a step: the cell's carried moment residual
+    float cr[3] = {0.f, 0.f, 0.f};
+    if constexpr (STORE == FVLBM_STORE_FP16_DEV)
+        if (ownw && d.mcarry) load_carry(d.mcarry, np, ic, cr);
     // update bases: the planes of this wave's phase-3 set
     if (ownw) {
         if (sep_base) {
@@ -1091,17 +1194,17 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     if (valid)
         tile_update<NF, STORE, M0, SPLIT3 ? 2 : -1, SPLIT3, SPLIT3>(d, i, h0, base, sep_base, code, ln, geo, cf,
                                                                     A + tid, A, sa, lg, bsave, bsave_k, lstash + tid,
-                                                                    T, lneq + tid);
+                                                                    T, lneq + tid, cr);
     if constexpr (SPLIT3) {
         if (validb)
             tile_update<NF, STORE, M0, 4, true, true>(d, tile * T + ob, h0, base, sep_base, code, ln, geo, cf, A + ob,
-                                                      A, sa, lg, bsave, bsave_k, lstash + ob, T, lneq + ob);
+                                                      A, sa, lg, bsave, bsave_k, lstash + ob, T, lneq + ob, cr);
         if (valid3 && halow)
             tile_update<NF, STORE, M0, 3, true, true>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj, A, sa, lg,
-                                                      bsave, -1, lstash + rj, T, lneq + rj);
+                                                      bsave, -1, lstash + rj, T, lneq + rj, cr);
         if (valid3 && halob)
             tile_update<NF, STORE, M0, 5, true, true>(d, i3, h0, base, sep_base, code, ln, geo, cf, A + rj, A, sa, lg,
-                                                      bsave, -1, lstash + rj, T, lneq + rj);
+                                                      bsave, -1, lstash + rj, T, lneq + rj, cr);
     }
 }
 

@@ -14,7 +14,7 @@ Tolerances:
     device's own snapshots' fields to 1e-12 relative, and the oracle's value to
     the bound the field differences give (see _residual_bound);
   * batched and served fields: the tolerances of a single solve of the same
-    storage (1e-5 U for FP32 deviations, 1e-3 U for 16-bit block-scaled).
+    storage (1e-5 U for FP32 deviations, 1e-3 U for the 16-bit formats).
 """
 import numpy as np
 import pytest
@@ -68,7 +68,7 @@ def _residual_bound(u_g, uo_g, u_o, uo_o):
     return (np.linalg.norm(a_g - a_o) + r_o * np.linalg.norm(uo_g - uo_o)) / np.linalg.norm(uo_g)
 
 
-@pytest.mark.parametrize("storage", ["fp32dev", "i16dev"])
+@pytest.mark.parametrize("storage", ["fp32dev", "i16dev", "fp16dev"])
 def test_mass_and_residual_match_oracle(F, O, storage):
     """A closed cavity (mass conserved) and an open channel (mass changes through
     the inlet and outlet), with a residual lag of 60 steps."""
@@ -84,7 +84,10 @@ def test_mass_and_residual_match_oracle(F, O, storage):
                                          residual_lag=lag), u=np.tile(np.asarray(u0, float), (m.n_cells, 1)))
         area = o.geometry()["area"]
         mass0_o = o.mass()
-        assert s.stats()["mass"] == pytest.approx(mass0_o, rel=1e-13)
+        # Step 0's equilibrium differs from the storage reference (rounded to FP32) by
+        # about 1e-9 w; FP16 deviations hold that in the moment carry, itself an FP16
+        # value (11 significant bits): 1e-11 relative
+        assert s.stats()["mass"] == pytest.approx(mass0_o, rel=1e-11 if storage == "fp16dev" else 1e-13)
         o.step(2 * lag)
         s.step(2 * lag)
         rho_g1, u_g1, _ = s.macros()
@@ -107,7 +110,7 @@ def test_mass_and_residual_match_oracle(F, O, storage):
         mesh.close()
 
 
-@pytest.mark.parametrize("storage,utol", [("fp32dev", 1e-5), ("i16dev", 1e-3)])
+@pytest.mark.parametrize("storage,utol", [("fp32dev", 1e-5), ("i16dev", 1e-3), ("fp16dev", 1e-3)])
 def test_batched_members_match_their_oracle_runs(F, O, storage, utol):
     """Triangles, quads and a hybrid mesh with different tau and dt, advanced by
     shared launches; every member against its own FP64 run."""
@@ -138,7 +141,7 @@ def test_batched_members_match_their_oracle_runs(F, O, storage, utol):
         assert np.abs(rho_g - rho_o).max() <= utol * U
 
 
-@pytest.mark.parametrize("storage,utol", [("fp32dev", 1e-5), ("i16dev", 1e-3)])
+@pytest.mark.parametrize("storage,utol", [("fp32dev", 1e-5), ("i16dev", 1e-3), ("fp16dev", 1e-3)])
 def test_served_request_matches_its_oracle_run(F, O, storage, utol):
     from paper_1812_00390_amd import workloads as W
     from paper_1812_00390_amd.serve import GpuBackend, Request, Server
