@@ -1,25 +1,33 @@
 """Throughput benchmark of the FVLBM time step on one MI355X.
 
-Headline workload (the metric's configuration): lid-driven cavity, Re = 1000,
-U = 0.1, 20,000 jittered triangles from a 100 x 100 tanh-clustered grid
-(growth 1.08, seed 0), four-stage RK, FP32 storage (deviations from the rest
-equilibrium), dt from CFL 0.5.  One step = one full RK step (four RHS
-evaluations) over all cells; the metric is M cell-updates/s.
+Headline workload (the largest single-GPU FP32 configuration): flow past a
+circular cylinder, Re = 100, u_inf = 0.1, body-fitted O-grid of 256 radial x
+384 circumferential quadrilaterals (98,304 cells, first cell 0.005 D, far
+field at 30 D), four-stage RK, dt from CFL 0.5, FP32 storage of the
+deviations from the free-stream equilibrium.  One step = one full RK step
+(four RHS evaluations) over all cells; the metric is M cell-updates/s.
 
 Prints one JSON line.  Besides the contract fields:
   roofline      the RK stage kernel against the HBM peak: algorithmic bytes per
                 launch (see the design notes) / average launch duration, timed
                 with HIP events on the solver's stream over the timed region
-  cpu_baseline  the FP64 oracle on a bounded sample of the same workload
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload, on
+                one host thread and on all the job's host threads (its OpenMP
+                build, bitwise the same results), with the host CPU's model
+  cavity20k     the lid-driven cavity, Re 1000, 20,000 jittered triangles
+                (100 x 100 tanh grid, growth 1.08, seed 0), four-stage RK:
+                the paper's cavity class, small enough to sit in the on-chip
+                caches (a latency-bound launch)
   streaming     the same kernel on 8.4M triangles (larger than the on-chip
                 caches): the honest HBM fraction, Euler and four-stage RK
   batched       64 seeded instances (2k-200k cells) advanced together by the
                 batched, graph-replayed, autotuned path with FP16-deviation
-                storage, next to the same instances run one at a time on the
-                plain single-instance FP32 path
+                storage, each instance's error against its stored FP64 oracle
+                run, next to the same instances run one at a time (FP16 and
+                FP32 deviations) and batched with FP32 deviations
   precision     each storage mode's velocity error against stored FP64 oracle runs
-  served        Poisson-arrival serving at 0.5 and 1.0 x the measured capacity:
-                p50/p99 latency and aggregate throughput
+  served        Poisson-arrival serving at a reduced size (the serving module
+                runs the full sweep): p50/p99 latency and aggregate throughput
 """
 from __future__ import annotations
 
@@ -52,13 +60,13 @@ def alg_bytes_per_update(nf: int, scheme: str, storage: str) -> float:
     return STATE_VALUES[scheme] * STORE_BYTES[storage] + CARRY_BYTES.get(storage, 0.0) + n_rhs * MESH_BYTES[nf]
 
 
-def measured_traffic(schedule):
+def measured_traffic(workload, schedule):
     """HBM bytes per launch of the stage kernel from the committed counter runs
     (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain copy of
     known size), or None when the kernel sources changed since they were taken
     or the timed schedule is not one they were taken with."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_tile_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"k_tile_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -84,16 +92,36 @@ def events_time(stream, fn):
     return a.elapsed_time(b) / 1e3
 
 
-def cpu_baseline(inst, scheme="rk4", target_s=12.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(inst, label, scheme="rk4", target_s=10.0):
+    """The FP64 oracle on the host: one thread, then its OpenMP build on every
+    thread this job has (OMP_NUM_THREADS, else the visible cores)."""
     from oracle import oracle as O
-    o = O.Oracle(inst.mesh, tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme=scheme)
-    o.init()
-    t0 = time.perf_counter(); o.step(1); t1 = time.perf_counter()
-    n = max(2, int(target_s / max(t1 - t0, 1e-4)))
-    t0 = time.perf_counter(); o.step(n); t1 = time.perf_counter()
-    return dict(value=round(inst.n_cells * n / (t1 - t0) / 1e6, 4), unit="M cell-updates/s", cores=1,
-                kind="oracle",
-                sample=f"{n} four-stage RK steps of the same {inst.n_cells}-cell cavity (FP64, one thread)")
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    out = {}
+    for key, th in (("one", 1), ("all", threads)):
+        o = O.Oracle(inst.mesh, tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme=scheme, threads=th)
+        o.init(u0=inst.u0)
+        t0 = time.perf_counter(); o.step(1); t1 = time.perf_counter()
+        n = max(2, int(target_s / max(t1 - t0, 1e-4)))
+        t0 = time.perf_counter(); o.step(n); t1 = time.perf_counter()
+        out[key] = (inst.n_cells * n / (t1 - t0) / 1e6, n, o.threads)
+        del o
+    v_all, n_all, th_all = out["all"]
+    v_one, n_one, _ = out["one"]
+    return dict(value=round(v_all, 4), unit="M cell-updates/s", cores=th_all, kind="oracle",
+                single_thread_value=round(v_one, 4), cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+                sample=f"{label}: {n_all} four-stage RK steps on {th_all} threads (OpenMP build over cells) "
+                       f"and {n_one} on one thread, FP64, {inst.n_cells} cells")
 
 
 def make_solver(F, inst, scheme, storage, reorder=None):
@@ -173,28 +201,82 @@ def served(args):
 
 
 def batched(F, W, stream, steps=1000, single_steps=100):
+    """The batched workload: 64 instances in shared, graph-replayed launches,
+    FP16-deviation storage, autotuned; each instance's error against its stored
+    FP64 oracle run after the same 1000 steps; then the batching gain at equal
+    storage (batched FP32 deviations, and FP16 and FP32 deviations one
+    instance at a time on the plain single-instance path)."""
     insts = W.batched()
     total = sum(i.n_cells for i in insts)
-    pairs = [make_solver(F, i, "rk4", "fp16dev") for i in insts]
-    b = F.Batch([s for _, s in pairs])
-    tune_ms = b.autotune(32)
-    el = events_time(stream, lambda: b.step(steps))
-    rec = dict(instances=len(insts), cells=total, steps=steps, storage="fp16dev", scheme="rk4",
-               M_cell_updates_per_s=round(total * steps / el / 1e6, 1), ms_per_step=round(el * 1e3 / steps, 4),
-               tuned_ms_per_step=round(tune_ms, 4))
-    b.close()
-    for _, s in pairs:
-        s.close()
-    # the plain single-instance FP32 path on the same instances, one after another
-    t = 0.0
-    for inst in insts:
-        mesh, s = make_solver(F, inst, "rk4", "fp32dev")
-        s.step(8)
-        t += events_time(stream, lambda: s.step(single_steps))
-        s.close(); mesh.close()
-    rec["single_fp32_M_cell_updates_per_s"] = round(total * single_steps / t / 1e6, 1)
-    rec["speedup_vs_single_fp32"] = round(rec["M_cell_updates_per_s"] / rec["single_fp32_M_cell_updates_per_s"], 2)
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_batched64_rk4_1000.npz")
+    ref = np.load(gold) if os.path.exists(gold) and steps == 1000 else None
+    rec = dict(instances=len(insts), cells=total, steps=steps, storage="fp16dev", scheme="rk4")
+    for storage in ("fp16dev", "fp32dev"):
+        pairs = [make_solver(F, i, "rk4", storage) for i in insts]
+        b = F.Batch([s for _, s in pairs])
+        tune_ms = b.autotune(32)
+        el = events_time(stream, lambda: b.step(steps))
+        if storage == "fp16dev":
+            rec.update(M_cell_updates_per_s=round(total * steps / el / 1e6, 1), ms_per_step=round(el * 1e3 / steps, 4),
+                       tuned_ms_per_step=round(tune_ms, 4), schedule=b.get_schedule())
+            if ref is not None:
+                errs = []
+                for k, (_, s) in enumerate(pairs):
+                    _, u, _ = s.macros()
+                    errs.append(float(np.abs(u[ref[f"idx_{k}"]] - ref[f"u_{k}"]).max() / 0.1))
+                rec["oracle_error"] = dict(metric="max |u - u_oracle| / U at 200 sampled cells, per instance",
+                                           max=float(f"{max(errs):.3g}"),
+                                           per_instance=[float(f"{e:.3g}") for e in errs])
+        else:
+            rec["batched_fp32dev_M_cell_updates_per_s"] = round(total * steps / el / 1e6, 1)
+        b.close()
+        for mesh, s in pairs:
+            s.close(); mesh.close()
+    # the plain single-instance path on the same instances, one after another
+    for storage in ("fp16dev", "fp32dev"):
+        t = 0.0
+        for inst in insts:
+            mesh, s = make_solver(F, inst, "rk4", storage)
+            s.step(8)
+            s.prepare(single_steps)
+            t += events_time(stream, lambda: s.step(single_steps))
+            s.close(); mesh.close()
+        rec[f"single_{storage}_M_cell_updates_per_s"] = round(total * single_steps / t / 1e6, 1)
+    rec["speedup_vs_single_fp32dev"] = round(rec["M_cell_updates_per_s"] / rec["single_fp32dev_M_cell_updates_per_s"], 2)
+    rec["batching_gain_fp16dev"] = round(rec["M_cell_updates_per_s"] / rec["single_fp16dev_M_cell_updates_per_s"], 2)
+    rec["batching_gain_fp32dev"] = round(rec["batched_fp32dev_M_cell_updates_per_s"] /
+                                         rec["single_fp32dev_M_cell_updates_per_s"], 2)
     return rec
+
+
+def single_workload(F, stream, inst, label, traffic_key, args, schedule):
+    """One solver stepped `args.steps` four-stage RK steps (graphs instantiated
+    beforehand), timed with HIP events on its stream."""
+    mesh, s = make_solver(F, inst, "rk4", args.storage)
+    nf = mesh.info()["nf"]
+    if schedule:
+        s.set_schedule(*schedule)
+    elif not args.no_autotune:
+        s.autotune(64)
+    s.step(args.warmup)
+    s.prepare(args.steps)
+    el = events_time(stream, lambda: s.step(args.steps))
+    n = inst.n_cells
+    t_launch = el / (4 * args.steps)
+    alg_launch = alg_bytes_per_update(nf, "rk4", args.storage) / 4 * n
+    rho, u, st = s.macros()
+    sched = s.get_schedule()
+    out = dict(value=round(n * args.steps / el / 1e6, 3), ms_per_step=round(el * 1e3 / args.steps, 5),
+               config={"workload": label, "cells": n, "scheme": "rk4", "storage": args.storage, "dt": s.dt,
+                       "schedule": sched},
+               roofline={"bound": "hbm", "achieved": round(alg_launch / t_launch / 1e9, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg_launch / t_launch / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic(traffic_key, sched) if args.storage == "fp32dev" else None,
+                         "kernel": f"k_tile<{nf},...> (one RK stage)",
+                         "alg_bytes_per_launch": alg_launch, "launch_us": round(t_launch * 1e6, 3)},
+               check={"max_u": float(np.abs(u).max()), "mass": st["mass"]})
+    s.close(); mesh.close()
+    return out
 
 
 def main():
@@ -203,8 +285,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="fp32dev")
-    ap.add_argument("--only", choices=["all", "headline", "streaming", "batched", "precision", "served", "copy"],
-                    default="all")
+    ap.add_argument("--only", choices=["all", "headline", "cavity20k", "streaming", "batched", "precision", "served",
+                                       "copy"], default="all")
     ap.add_argument("--schedule", default="", help="force a launch schedule 'block,xcd,persistent' instead of tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -226,46 +308,35 @@ def main():
         schedule = (b, bool(x), int(p))
     rec = {}
     if args.only in ("all", "headline"):
-        inst = W.cavity20k()
-        mesh, s = make_solver(F, inst, "rk4", args.storage)
-        nf = mesh.info()["nf"]
-        if args.schedule:
-            s.set_schedule(*schedule)
-        elif not args.no_autotune:
-            s.autotune(64)
-        s.step(args.warmup)
-        el = events_time(stream, lambda: s.step(args.steps))
-        n = inst.n_cells
-        t_launch = el / (4 * args.steps)
-        alg_launch = alg_bytes_per_update(nf, "rk4", args.storage) / 4 * n
-        rho, u, st = s.macros()
+        inst = W.cylinder98k()
+        label = ("flow past a circular cylinder Re=100 u_inf=0.1, O-grid 256x384 quads (98304 cells, "
+                 "first cell 0.005 D, far field 30 D), four-stage RK, CFL 0.5, deviations from the free stream")
+        h = single_workload(F, stream, inst, label, "cylinder98k", args, schedule)
         rec.update({
             "metric": "M cell-updates/s (D2Q9, FP32)",
-            "value": round(n * args.steps / el / 1e6, 3),
+            "value": h["value"],
             "unit": "M cell-updates/s",
             "n_gpus": 1,
             "steps": args.steps,
             "warmup": args.warmup,
-            "ms_per_step": round(el * 1e3 / args.steps, 5),
+            "ms_per_step": h["ms_per_step"],
             "higher_is_better": True,
             "scaling": "weak",
             "vs_baseline": None,
             "dtype": "f32" if args.storage in ("fp32", "fp32dev") else f"f32 compute, {args.storage} storage",
             "data": "synthetic",
-            "config": {"workload": "lid-driven cavity Re=1000 U=0.1, 20000 jittered triangles "
-                                   "(100x100 tanh growth 1.08, seed 0), four-stage RK, CFL 0.5",
-                       "cells": n, "scheme": "rk4", "storage": args.storage, "dt": s.dt,
-                       "schedule": s.get_schedule()},
-            "roofline": {"bound": "hbm", "achieved": round(alg_launch / t_launch / 1e9, 2), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(alg_launch / t_launch / 1e9 / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic(s.get_schedule()) if args.storage == "fp32dev" else None,
-                         "kernel": "k_tile<3> (one RK stage)",
-                         "alg_bytes_per_launch": alg_launch, "launch_us": round(t_launch * 1e6, 3)},
-            "check": {"max_u": float(np.abs(u).max()), "mass": st["mass"]},
+            "config": h["config"],
+            "roofline": h["roofline"],
+            "check": h["check"],
         })
-        s.close(); mesh.close()
         if not args.no_cpu_baseline:
-            rec["cpu_baseline"] = cpu_baseline(inst)
+            rec["cpu_baseline"] = cpu_baseline(inst, "the same 98,304-quad cylinder")
+    if args.only in ("all", "cavity20k"):
+        label = ("lid-driven cavity Re=1000 U=0.1, 20000 jittered triangles (100x100 tanh growth 1.08, seed 0), "
+                 "four-stage RK, CFL 0.5")
+        c = single_workload(F, stream, W.cavity20k(), label, "cavity20k", args, schedule)
+        c["M_cell_updates_per_s"] = c.pop("value")
+        rec["cavity20k"] = c
     if args.only == "copy":
         # calibration of the HBM byte counters: a plain device copy of a known size
         n = 1 << 28                       # 1 GiB of FP32 each way

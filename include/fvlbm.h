@@ -141,8 +141,17 @@ fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const doub
 double fvlbm_solver_dt(const fvlbm_solver *s);
 
 /* Steps 1-5 repeated n_steps times (Section 2.4.2), enqueued on the solver's stream;
- * does not sync.  Errors: FVLBM_E_ARG (n_steps < 0), FVLBM_E_STATE, FVLBM_E_DEVICE. */
+ * does not sync.  The launches replay HIP graphs of 32 steps and, for the rest of
+ * a call, of the largest power of two that fits, each instantiated on first use.
+ * Errors: FVLBM_E_ARG (n_steps < 0), FVLBM_E_STATE, FVLBM_E_DEVICE. */
 fvlbm_status fvlbm_step(fvlbm_solver *s, int64_t n_steps);
+
+/* Instantiates the graphs that fvlbm_step(s, n_steps) would replay from the
+ * solver's present position, without enqueueing anything or changing the
+ * state, so that a later call of that size spends no time building them (for
+ * callers that time or bound the latency of their step calls).  Optional.
+ * Errors: FVLBM_E_ARG, FVLBM_E_STATE, FVLBM_E_DEVICE. */
+fvlbm_status fvlbm_prepare(fvlbm_solver *s, int64_t n_steps);
 
 /*
  * Step 6: rho [n_cells], u [2*n_cells] (either may be NULL) and

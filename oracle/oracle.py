@@ -15,30 +15,52 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fvlbm_oracle.c")
 _LIB = os.path.join(_HERE, "libfvlbm_oracle.so")
+# the same source built with OpenMP over cells (bitwise the same results), for timing on many cores
+_LIB_OMP = os.path.join(_HERE, "libfvlbm_oracle_omp.so")
 MAXF = 8
 Q = 9
 SCHEMES = {"euler": 0, "rk4": 1, "ab2": 2}
 
 
+def _stale(path):
+    return not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle with gcc (FP64, no FMA contraction): the one-thread
+    library and the OpenMP timing build of the same source."""
+    for out, extra in ((_LIB, ["-Wno-unknown-pragmas"]), (_LIB_OMP, ["-fopenmp"])):
+        if force or _stale(out):
+            cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                   "-Wall", *extra, "-o", out + ".tmp", _SRC, "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(out + ".tmp", out)
     return _LIB
 
 
 _lib = None
+_lib_omp = None
 
 
-def lib():
-    global _lib
+def lib(threads: bool = False):
+    """The one-thread oracle library, or (threads=True) its OpenMP timing build."""
+    global _lib, _lib_omp
+    if threads:
+        if _lib_omp is None:
+            if _stale(_LIB_OMP):
+                build(force=True)
+            _lib_omp = _bind(C.CDLL(_LIB_OMP))
+        return _lib_omp
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale(_LIB):
             build(force=True)
-        L = C.CDLL(_LIB)
+        _lib = _bind(C.CDLL(_LIB))
+    return _lib
+
+
+def _bind(L):
+    """Argument and result types of every exported function."""
+    if L is not None:
         dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
         ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
         L.orc_create.restype = C.c_void_p
@@ -65,8 +87,8 @@ def lib():
         L.orc_macros.argtypes = [C.c_void_p, dp, dp]
         L.orc_mass.argtypes = [C.c_void_p]; L.orc_mass.restype = C.c_double
         L.orc_residual.argtypes = [C.c_int, dp, dp]; L.orc_residual.restype = C.c_double
-        _lib = L
-    return _lib
+        L.orc_set_threads.argtypes = [C.c_int]; L.orc_set_threads.restype = C.c_int
+    return L
 
 
 def feq(rho: float, ux: float, uy: float) -> np.ndarray:
@@ -97,8 +119,14 @@ class Oracle:
     """One FP64 solve on one raw mesh (see paper_1812_00390_amd.meshgen.RawMesh)."""
 
     def __init__(self, mesh, tau: float, dt: float = 0.0, cfl: float = 0.5, u_ref: float = 0.1,
-                 scheme: str = "euler"):
-        L = lib()
+                 scheme: str = "euler", threads: int = 1):
+        """threads > 1: the OpenMP timing build on that many threads (bitwise the same results)."""
+        L = lib(threads=threads > 1)
+        self._L = L
+        if threads > 1:
+            self.threads = L.orc_set_threads(int(threads))
+        else:
+            self.threads = 1
         g = mesh.groups
         kinds = np.asarray([x.kind for x in g] or [0], dtype=np.int32)
         internal = np.asarray([x.internal for x in g] or [0], dtype=np.int32)
@@ -131,43 +159,44 @@ class Oracle:
         self.scheme = scheme
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
+        L = getattr(self, "_L", None)
+        if getattr(self, "h", None) and L is not None:
+            L.orc_destroy(self.h)
             self.h = None
 
     @property
     def dt(self) -> float:
-        return lib().orc_dt(self.h)
+        return self._L.orc_dt(self.h)
 
     @property
     def steps(self) -> int:
-        return lib().orc_steps(self.h)
+        return self._L.orc_steps(self.h)
 
     def init(self, rho0=1.0, u0=(0.0, 0.0), rho=None, u=None):
         r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
         v = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
         self._init_keep = (r, v)
-        lib().orc_init(self.h, None if r is None else r.ctypes.data, None if v is None else v.ctypes.data,
+        self._L.orc_init(self.h, None if r is None else r.ctypes.data, None if v is None else v.ctypes.data,
                        float(rho0), float(u0[0]), float(u0[1]))
 
     @property
     def f(self) -> np.ndarray:
         out = np.zeros((self.n, Q))
-        lib().orc_get_f(self.h, out)
+        self._L.orc_get_f(self.h, out)
         return out
 
     @f.setter
     def f(self, value):
-        lib().orc_set_f(self.h, np.ascontiguousarray(value, dtype=np.float64).reshape(self.n, Q))
+        self._L.orc_set_f(self.h, np.ascontiguousarray(value, dtype=np.float64).reshape(self.n, Q))
 
     def rhs(self, f) -> np.ndarray:
         out = np.zeros((self.n, Q))
-        lib().orc_rhs(self.h, np.ascontiguousarray(f, dtype=np.float64).reshape(self.n, Q), out)
+        self._L.orc_rhs(self.h, np.ascontiguousarray(f, dtype=np.float64).reshape(self.n, Q), out)
         return out
 
     def face_values(self, f) -> np.ndarray:
         out = np.zeros((self.n, MAXF, Q))
-        lib().orc_face_values(self.h, np.ascontiguousarray(f, dtype=np.float64).reshape(self.n, Q), out)
+        self._L.orc_face_values(self.h, np.ascontiguousarray(f, dtype=np.float64).reshape(self.n, Q), out)
         return out
 
     def wall_force(self, f, group: int):
@@ -176,36 +205,36 @@ class Oracle:
         fr = np.ascontiguousarray(f, dtype=np.float64).reshape(self.n, Q)
         force = np.zeros(2)
         face_p = np.zeros(max(1, 4 * self.n))
-        k = lib().orc_wall_force(self.h, fr, int(group), force, face_p)
+        k = self._L.orc_wall_force(self.h, fr, int(group), force, face_p)
         return force, face_p[:k].copy()
 
     def step(self, n: int = 1):
-        lib().orc_step(self.h, int(n))
+        self._L.orc_step(self.h, int(n))
 
     def macros(self):
         rho = np.zeros(self.n); u = np.zeros((self.n, 2))
-        lib().orc_macros(self.h, rho, u)
+        self._L.orc_macros(self.h, rho, u)
         return rho, u
 
     def mass(self) -> float:
-        return lib().orc_mass(self.h)
+        return self._L.orc_mass(self.h)
 
     def geometry(self) -> dict:
         n = self.n
         a, cx, cy, lx, ly = (np.zeros(n) for _ in range(5))
         nf = np.zeros(n, np.int32)
-        lib().orc_geometry(self.h, a, cx, cy, lx, ly, nf)
+        self._L.orc_geometry(self.h, a, cx, cy, lx, ly, nf)
         return dict(area=a, cx=cx, cy=cy, lx=lx, ly=ly, nf=nf)
 
     def faces(self) -> dict:
         s = (self.n, MAXF)
         nbr, grp = np.zeros(s, np.int32), np.zeros(s, np.int32)
         fx, fy, nx, ny, ln, stx, sty = (np.zeros(s) for _ in range(7))
-        lib().orc_faces(self.h, nbr, grp, fx, fy, nx, ny, ln, stx, sty)
+        self._L.orc_faces(self.h, nbr, grp, fx, fy, nx, ny, ln, stx, sty)
         return dict(nbr=nbr, grp=grp, fx=fx, fy=fy, nx=nx, ny=ny, len=ln, stx=stx, sty=sty)
 
     def lsq_gradient(self, phi, phi_bnd) -> np.ndarray:
         out = np.zeros((self.n, 2))
-        lib().orc_lsq_gradient(self.h, np.ascontiguousarray(phi, dtype=np.float64),
+        self._L.orc_lsq_gradient(self.h, np.ascontiguousarray(phi, dtype=np.float64),
                                np.ascontiguousarray(phi_bnd, dtype=np.float64).reshape(self.n, MAXF), out)
         return out

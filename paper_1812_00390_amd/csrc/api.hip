@@ -266,21 +266,39 @@ hipGraphExec_t solver_graph(fvlbm_solver *s, int cur, int nsteps) {
 
 constexpr int GRAPH_CHUNK = 32;
 
-// Enqueue n steps without snapshots.
-fvlbm_status enqueue_steps(fvlbm_solver *s, int64_t n) {
+// Steps replayed by the next graph for `left` steps to go: 32 while at least
+// 32 remain, then the largest power of two (so any count uses at most six
+// graph sizes, each cached by start buffer and size).
+int graph_steps(int64_t left) {
+    if (left >= GRAPH_CHUNK) return GRAPH_CHUNK;
+    int c = 1;
+    while (2 * c <= left) c *= 2;
+    return c;
+}
+
+// Enqueue n steps without snapshots.  dry: only instantiate the graphs the
+// call would replay (the caller saves and restores the solver's position).
+fvlbm_status enqueue_steps(fvlbm_solver *s, int64_t n, bool dry = false) {
     std::vector<int> ks;
     int64_t done = 0;
     const int nf = s->mesh->dev.nf;
     while (done < n) {
         int64_t left = n - done;
-        bool graphable = left >= GRAPH_CHUNK && (s->p.scheme != FVLBM_SCHEME_AB2 || s->have_prev);
+        bool graphable = s->p.scheme != FVLBM_SCHEME_AB2 || s->have_prev;   // (the first AB2 step is an Euler step)
         if (graphable) {
-            hipGraphExec_t ex = solver_graph(s, s->cur, GRAPH_CHUNK);
+            const int g = graph_steps(left);
+            hipGraphExec_t ex = solver_graph(s, s->cur, g);
             if (!ex) return fail(FVLBM_E_DEVICE, "graph build failed");
-            if (hipGraphLaunch(ex, s->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "graph launch failed");
-            for (int k = 0; k < GRAPH_CHUNK; k++) advance_position(s->p.scheme, s->cur, s->have_prev);
-            done += GRAPH_CHUNK;
-            s->steps += GRAPH_CHUNK;
+            if (!dry && hipGraphLaunch(ex, s->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "graph launch failed");
+            for (int k = 0; k < g; k++) advance_position(s->p.scheme, s->cur, s->have_prev);
+            done += g;
+            s->steps += g;
+            continue;
+        }
+        if (dry) {
+            advance_position(s->p.scheme, s->cur, s->have_prev);
+            done++;
+            s->steps++;
             continue;
         }
         step_kinds(s->p.scheme, s->cur, s->have_prev, ks);
@@ -473,24 +491,46 @@ void fvlbm_solver_destroy(fvlbm_solver *s) {
     solver_free(s);
 }
 
-fvlbm_status fvlbm_step(fvlbm_solver *s, int64_t n_steps) {
-    if (!s || n_steps < 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_step");
-    if (s->failed || s->destroyed) return fail(FVLBM_E_STATE, "solver is in an error state or destroyed");
-    if (s->snap_cur < 0 && s->steps % s->lag == 0) {
+namespace {
+// fvlbm_step's sequence: steps split at residual-lag boundaries, where a
+// velocity snapshot is taken.  dry: graphs only (see fvlbm_prepare).
+fvlbm_status step_impl(fvlbm_solver *s, int64_t n_steps, bool dry) {
+    if (!dry && s->snap_cur < 0 && s->steps % s->lag == 0) {
         if (take_snapshot(s) != hipSuccess) { s->failed = true; return fail(FVLBM_E_DEVICE, "snapshot failed"); }
     }
     int64_t left = n_steps;
     while (left > 0) {
         int64_t to_snap = s->lag - (s->steps % s->lag);
         int64_t chunk = std::min(left, to_snap);
-        fvlbm_status st = enqueue_steps(s, chunk);
+        fvlbm_status st = enqueue_steps(s, chunk, dry);
         if (st != FVLBM_OK) { s->failed = true; return st; }
         left -= chunk;
-        if (s->steps % s->lag == 0) {
+        if (!dry && s->steps % s->lag == 0) {
             if (take_snapshot(s) != hipSuccess) { s->failed = true; return fail(FVLBM_E_DEVICE, "snapshot failed"); }
         }
     }
     return FVLBM_OK;
+}
+}  // namespace
+
+fvlbm_status fvlbm_step(fvlbm_solver *s, int64_t n_steps) {
+    if (!s || n_steps < 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_step");
+    if (s->failed || s->destroyed) return fail(FVLBM_E_STATE, "solver is in an error state or destroyed");
+    return step_impl(s, n_steps, false);
+}
+
+fvlbm_status fvlbm_prepare(fvlbm_solver *s, int64_t n_steps) {
+    if (!s || n_steps < 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_prepare");
+    if (s->failed || s->destroyed) return fail(FVLBM_E_STATE, "solver is in an error state or destroyed");
+    const int cur = s->cur;
+    const bool hp = s->have_prev;
+    const int64_t steps = s->steps;
+    fvlbm_status st = step_impl(s, n_steps, true);
+    s->cur = cur;
+    s->have_prev = hp;
+    s->steps = steps;
+    if (st != FVLBM_OK) s->failed = false;     // nothing ran: a failed graph build leaves the state intact
+    return st;
 }
 
 fvlbm_status fvlbm_macros(fvlbm_solver *s, double *rho, double *u, double *stats) {
@@ -815,37 +855,26 @@ hipGraphExec_t batch_graph(fvlbm_batch *b, int cur, int nsteps) {
 }  // extern "C"
 
 namespace {
-fvlbm_status batch_enqueue(fvlbm_batch *b, int64_t n_steps, bool snapshots) {
-    const int n = (int)b->members.size();
+// Advance every member n_steps with shared launches: graphs of 32 steps, then
+// of the largest power of two that fits (as a single solver).  dry: only
+// instantiate those graphs (no launch, no snapshot, positions untouched).
+fvlbm_status batch_enqueue(fvlbm_batch *b, int64_t n_steps, bool snapshots, bool dry = false) {
     int64_t left = n_steps;
-    std::vector<int> ks;
     // as fvlbm_step(): a member on a lag boundary without a snapshot takes one first
-    if (snapshots && n_steps > 0)
+    if (!dry && snapshots && n_steps > 0)
         for (fvlbm_solver *s : b->members)
             if (s->snap_cur < 0 && s->steps % s->lag == 0 && take_snapshot(s) != hipSuccess)
                 return fail(FVLBM_E_DEVICE, "snapshot failed");
+    int cur = b->members[0]->cur;
+    bool hp = true;
     while (left > 0) {
-        fvlbm_solver *s0 = b->members[0];
-        int64_t chunk = std::min<int64_t>(left, GRAPH_CHUNK);
-        if (chunk == GRAPH_CHUNK) {
-            hipGraphExec_t ex = batch_graph(b, s0->cur, GRAPH_CHUNK);
-            if (!ex) return fail(FVLBM_E_DEVICE, "batch graph build failed");
-            if (hipGraphLaunch(ex, b->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "batch graph launch failed");
-        } else {
-            int c = s0->cur;
-            bool hp = true;
-            for (int st = 0; st < chunk; st++) {
-                step_kinds(b->scheme, c, hp, ks);
-                for (int k : ks)
-                    for (int t = 0; t < 2; t++) {
-                        hipError_t e = launch_stage(b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
-                                                    b->sched.xcd_remap, b->sched.persistent, b->h2max[t], b->h1max[t], mode0(k),
-                                                    b->stream);
-                        if (e != hipSuccess) return fail(FVLBM_E_DEVICE, hipGetErrorString(e));
-                    }
-                advance_position(b->scheme, c, hp);
-            }
-        }
+        const int chunk = graph_steps(left);
+        hipGraphExec_t ex = batch_graph(b, cur, chunk);
+        if (!ex) return fail(FVLBM_E_DEVICE, "batch graph build failed");
+        for (int k = 0; k < chunk; k++) advance_position(b->scheme, cur, hp);
+        left -= chunk;
+        if (dry) continue;
+        if (hipGraphLaunch(ex, b->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "batch graph launch failed");
         for (fvlbm_solver *s : b->members) {
             int64_t before = s->steps;
             for (int64_t k = 0; k < chunk; k++) advance_position(s->p.scheme, s->cur, s->have_prev);
@@ -855,7 +884,6 @@ fvlbm_status batch_enqueue(fvlbm_batch *b, int64_t n_steps, bool snapshots) {
                 if (take_snapshot(s) != hipSuccess) return fail(FVLBM_E_DEVICE, "snapshot failed");
             }
         }
-        left -= chunk;
     }
     return FVLBM_OK;
 }
@@ -903,11 +931,12 @@ fvlbm_status restore_state(Saved &sv) {
     return FVLBM_OK;
 }
 
-// Times `steps` steps of `run` on `stream` with HIP events (after a warm-up
-// that also builds the step graphs); returns ms per step or -1.
-template <class Run>
-double time_steps(hipStream_t stream, int steps, Run run) {
-    if (run(GRAPH_CHUNK) != FVLBM_OK) return -1;
+// Times `steps` steps of `run` on `stream` with HIP events, after `prep`
+// (which instantiates the graphs of that call) and a warm-up of the same
+// number of steps; returns ms per step or -1.
+template <class Prep, class Run>
+double time_steps(hipStream_t stream, int steps, Prep prep, Run run) {
+    if (run(steps) != FVLBM_OK || prep(steps) != FVLBM_OK) return -1;
     hipEvent_t a, b;
     hipEventCreate(&a);
     hipEventCreate(&b);
@@ -957,7 +986,17 @@ fvlbm_status fvlbm_autotune(fvlbm_solver *s, int32_t trial_steps, double *best_m
         for (int x = 0; x < 2; x++)
             for (int ps = 0; ps < (T <= 128 ? 3 : 2); ps++) {
                 if (fvlbm_set_schedule(s, T, x, ps) != FVLBM_OK) continue;
-                double t = time_steps(s->stream, trial_steps, [&](int n) { return enqueue_steps(s, n); });
+                double t = time_steps(
+                    s->stream, trial_steps,
+                    [&](int n) {
+                        const int c = s->cur;
+                        const bool hp = s->have_prev;
+                        const int64_t st0 = s->steps;
+                        fvlbm_status r = enqueue_steps(s, n, true);
+                        s->cur = c; s->have_prev = hp; s->steps = st0;
+                        return r;
+                    },
+                    [&](int n) { return enqueue_steps(s, n); });
                 if (t > 0 && t < best_t) { best_t = t; best = s->sched; }
             }
     fvlbm_set_schedule(s, best.block, best.xcd_remap, best.persistent);
@@ -981,7 +1020,8 @@ fvlbm_status fvlbm_batch_autotune(fvlbm_batch *b, int32_t trial_steps, double *b
         for (int x = 0; x < 2; x++)
             for (int ps = 0; ps < 2; ps++) {
                 if (fvlbm_batch_set_schedule(b, T, x, ps) != FVLBM_OK) continue;
-                double t = time_steps(b->stream, trial_steps, [&](int n) { return batch_enqueue(b, n, false); });
+                double t = time_steps(b->stream, trial_steps, [&](int n) { return batch_enqueue(b, n, false, true); },
+                                      [&](int n) { return batch_enqueue(b, n, false); });
                 if (t > 0 && t < best_t) { best_t = t; best = b->sched; }
             }
     fvlbm_batch_set_schedule(b, best.block, best.xcd_remap, best.persistent);

@@ -60,6 +60,7 @@ SIGNATURES = {
     "fvlbm_init": (C.c_int, [_vp, C.POINTER(Params), _dp, _dp, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     "fvlbm_solver_dt": (C.c_double, [_vp]),
     "fvlbm_step": (C.c_int, [_vp, C.c_int64]),
+    "fvlbm_prepare": (C.c_int, [_vp, C.c_int64]),
     "fvlbm_macros": (C.c_int, [_vp, _dp, _dp, _dp]),
     "fvlbm_get_f": (C.c_int, [_vp, _dp]),
     "fvlbm_set_f": (C.c_int, [_vp, _dp]),
@@ -235,6 +236,10 @@ class Solver:
 
     def step(self, n: int = 1):
         _check(lib().fvlbm_step(self.h, int(n)))
+
+    def prepare(self, n: int):
+        """Instantiate the launch graphs a step(n) call from here would replay (runs nothing)."""
+        _check(lib().fvlbm_prepare(self.h, int(n)))
 
     def macros(self):
         rho = np.zeros(self.n); u = np.zeros((self.n, 2)); st = np.zeros(4)

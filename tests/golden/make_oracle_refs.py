@@ -13,8 +13,14 @@ velocity at seeded sample cells after a fixed number of steps:
                                   four-stage RK, CFL 0.5, u_ref 0.2, 100 steps
   oracle_cylinder256_rk4_20000.npz  the same cylinder after 20,000 steps (the
                                   full start-up run; about 20 minutes)
+  oracle_batched64_rk4_1000.npz   the 64 seeded instances of the batched
+                                  workload (2k-200k cells, cavities and
+                                  cylinders, Re 100-3000; seed 1), each after
+                                  1000 four-stage RK steps at CFL 0.5: 200
+                                  sample cells per instance
 
-Run: python tests/golden/make_oracle_refs.py   (a few minutes, one core)
+Run: python tests/golden/make_oracle_refs.py [file ...] [--threads N]
+(the OpenMP build of the oracle gives bitwise the one-thread results)
 """
 import os
 import sys
@@ -35,12 +41,38 @@ CASES = {
                                            cfl=0.5, u_ref=0.2, steps=100, u0=(0.1, 0.0)),
     "oracle_cylinder256_rk4_20000.npz": dict(mesh=lambda: mg.cylinder(nr=256, nt=384), tau=3 * 0.1 * 1.0 / 100,
                                              cfl=0.5, u_ref=0.2, steps=20000, u0=(0.1, 0.0)),
+    "oracle_batched64_rk4_1000.npz": {},
 }
 
 
+THREADS = 1
+
+
+def make_batched(name, steps=1000, per_instance=200):
+    from paper_1812_00390_amd import workloads as W
+    insts = W.batched()
+    out = dict(steps=steps, n=len(insts))
+    for k, inst in enumerate(insts):
+        o = O.Oracle(inst.mesh, tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme="rk4", threads=THREADS)
+        o.init(rho0=1.0, u0=inst.u0)
+        o.step(steps)
+        rho, u = o.macros()
+        rng = np.random.default_rng(1000 + k)
+        idx = np.sort(rng.choice(inst.n_cells, size=min(per_instance, inst.n_cells), replace=False))
+        out[f"idx_{k}"] = idx
+        out[f"u_{k}"] = u[idx]
+        out[f"rho_{k}"] = rho[idx]
+        out[f"dt_{k}"] = o.dt
+        out[f"cells_{k}"] = inst.n_cells
+        print(k, inst.kind, inst.n_cells, "dt", o.dt, "max|u|", np.abs(u).max(), flush=True)
+    np.savez_compressed(os.path.join(HERE, name), **out)
+
+
 def make(name, c):
+    if name.startswith("oracle_batched64"):
+        return make_batched(name)
     m = c["mesh"]()
-    o = O.Oracle(m, tau=c["tau"], cfl=c["cfl"], u_ref=c["u_ref"], scheme="rk4")
+    o = O.Oracle(m, tau=c["tau"], cfl=c["cfl"], u_ref=c["u_ref"], scheme="rk4", threads=THREADS)
     o.init(rho0=1.0, u0=c["u0"])
     o.step(c["steps"])
     rho, u = o.macros()
@@ -52,7 +84,12 @@ def make(name, c):
 
 
 if __name__ == "__main__":
+    args = sys.argv[1:]
+    if "--threads" in args:
+        i = args.index("--threads")
+        THREADS = int(args[i + 1])
+        del args[i:i + 2]
     for name, c in CASES.items():
-        if len(sys.argv) > 1 and name not in sys.argv[1:]:
+        if args and name not in args:
             continue
         make(name, c)
