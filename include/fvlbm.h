@@ -162,6 +162,20 @@ fvlbm_status fvlbm_prepare(fvlbm_solver *s, int64_t n_steps);
  */
 fvlbm_status fvlbm_macros(fvlbm_solver *s, double *rho, double *u, double *stats);
 
+/*
+ * For callers that cannot allocate device memory or sync (code under HIP graph
+ * capture, tight serving loops): Step 6 as fvlbm_macros computes it, written
+ * to the caller's device arrays and enqueued on the solver's stream, with no
+ * allocation, no copy to the host and no sync.
+ *   rho_dev   [n_cells] device array (may be NULL), u_dev [2*n_cells] (may be NULL)
+ *   stats_dev [2] device array: {mass = sum A_i rho_i, 1 if any rho or u is not finite else 0}
+ * The partial sums and the flag live in a static scratch of the library, one
+ * copy per GPU: meshes of at most 16,777,216 cells (FVLBM_E_ARG beyond), and
+ * calls that overlap on one GPU (several host threads or streams) race on it.
+ * Errors: FVLBM_E_ARG, FVLBM_E_STATE, FVLBM_E_DEVICE (launch failures only).
+ */
+fvlbm_status fvlbm_macros_noalloc(fvlbm_solver *s, double *rho_dev, double *u_dev, double *stats_dev);
+
 /* Copy the distributions out / in (FP64, [cell][alpha], input cell order).  Sync. */
 fvlbm_status fvlbm_get_f(fvlbm_solver *s, double *f);
 fvlbm_status fvlbm_set_f(fvlbm_solver *s, const double *f);

@@ -324,6 +324,41 @@ fvlbm_status upload_descs(fvlbm_solver *s) {
 
 }  // namespace
 
+// ------------------------------------------------------------ no allocation
+//
+// fvlbm_macros_noalloc keeps its partial sums and non-finite flag in this
+// file-scope array instead of the solver's workspace: one copy per GPU, held
+// until the process ends, shared by every call on that GPU.  Host code never
+// passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): its device address is taken once per device with
+// hipGetSymbolAddress, the device current, and kept in g_scratch.
+constexpr int NOALLOC_MAX_CELLS = 1 << 24;
+constexpr size_t NOALLOC_FLAG_BYTES = 256;   // the non-finite flag, then the block partial sums
+constexpr size_t SCRATCH_BYTES = NOALLOC_FLAG_BYTES + (size_t)2 * ((NOALLOC_MAX_CELLS + 255) / 256) * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch;   // device -> address of its copy of scratch
+
+// The current device's copy of scratch (looked up once per device).
+fvlbm_status scratch_ptr(char **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(FVLBM_E_DEVICE, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FVLBM_E_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        it = g_scratch.emplace(dev, static_cast<char *>(p)).first;
+    }
+    *out = it->second;
+    return FVLBM_OK;
+}
+}  // namespace
+
 fvlbm_solver::~fvlbm_solver() {
     hipStreamSynchronize(stream);
     free_graphs(graphs);
@@ -467,6 +502,11 @@ fvlbm_status fvlbm_init(fvlbm_mesh *mesh, const fvlbm_params *params, const doub
                            m.perm_dev, p.rho0, carry_ptr(s.get()), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("init failed: ") + hipGetErrorString(e));
+    {   // set-up of the no-allocation entry point's scratch on this device (once per device)
+        char *sp = nullptr;
+        fvlbm_status sst = scratch_ptr(&sp);
+        if (sst != FVLBM_OK) return sst;
+    }
     mesh->refs++;
     *out = s.release();
     return FVLBM_OK;
@@ -563,6 +603,28 @@ fvlbm_status fvlbm_macros(fvlbm_solver *s, double *rho, double *u, double *stats
         stats[3] = (double)s->steps;
     }
     if (fl) return fail(FVLBM_E_DIVERGED, "non-finite density or velocity");
+    return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_macros_noalloc(fvlbm_solver *s, double *rho_dev, double *u_dev, double *stats_dev) {
+    if (!s || !stats_dev) return fail(FVLBM_E_ARG, "null solver or stats");
+    if (s->failed || s->destroyed) return fail(FVLBM_E_STATE, "solver is in an error state or destroyed");
+    const MeshDev &m = s->mesh->dev;
+    if (m.n_cells > NOALLOC_MAX_CELLS)
+        return fail(FVLBM_E_ARG, "fvlbm_macros_noalloc handles meshes of at most 16777216 cells (its static scratch); "
+                                 "use fvlbm_macros");
+    char *sp = nullptr;
+    fvlbm_status st = scratch_ptr(&sp);
+    if (st != FVLBM_OK) return st;
+    int *flag = reinterpret_cast<int *>(sp);
+    double *partial = reinterpret_cast<double *>(sp + NOALLOC_FLAG_BYTES);
+    hipError_t e = launch_zero_int(flag, 1, s->stream);
+    if (e == hipSuccess)
+        e = launch_macros(fptr(s, s->cur), s->p.storage, m.n_cells, m.np, s->ref, carry_ptr(s), m.area, m.perm_dev,
+                          rho_dev, u_dev, partial, flag, s->stream);
+    if (e == hipSuccess) e = launch_finish_sums(partial, reduce_blocks(m.n_cells), stats_dev, 0, s->stream);
+    if (e == hipSuccess) e = launch_flag_out(flag, stats_dev + 1, s->stream);
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("macros (no allocation) failed: ") + hipGetErrorString(e));
     return FVLBM_OK;
 }
 

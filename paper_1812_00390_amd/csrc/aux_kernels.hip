@@ -243,6 +243,16 @@ __global__ void k_finish(const double *partial, int nblk, double *out, int mode)
     }
 }
 
+// one thread clears n ints (a fill kernel, so that the clear can sit in a captured graph)
+__global__ void k_zero_int(int *p, int n) {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0;
+}
+
+// out[0] = 1 if the flag is set, else 0
+__global__ void k_flag_out(const int *flag, double *out) {
+    if (threadIdx.x == 0) out[0] = flag[0] ? 1.0 : 0.0;
+}
+
 inline dim3 grid(int n) { return dim3((n + RB - 1) / RB); }
 
 }  // namespace
@@ -320,6 +330,16 @@ hipError_t launch_snapshot(const void *src, int storage, int n, int np, const Re
                            hipStream_t stream) {
     hipLaunchKernelGGL(k_snapshot, grid(n), dim3(RB), 0, stream, src, storage, n, np, ref, carry, snap_new, snap_old,
                        partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_int(int *p, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_out(const int *flag, double *out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_flag_out, dim3(1), dim3(64), 0, stream, flag, out);
     return hipGetLastError();
 }
 

@@ -236,6 +236,9 @@ hipError_t launch_snapshot(const void *src, int storage, int n, int np, const Re
                            hipStream_t stream);
 // partial: [nblk][2] -> out[0] = sum col0, out[1] = sum col1 (fixed order)
 hipError_t launch_finish_sums(const double *partial, int nblk, double *out, int mode, hipStream_t stream);
+// clear n ints with a kernel; out[0] = (flag[0] != 0) as a double
+hipError_t launch_zero_int(int *p, int n, hipStream_t stream);
+hipError_t launch_flag_out(const int *flag, double *out, hipStream_t stream);
 // Momentum flux through n wall faces (cell, slot) with wall velocity (uwx, uwy): partial sums of
 // (Fx, Fy) per block, and p = rho/3 of each face's border cell.
 hipError_t launch_wall_force(const void *src, int storage, int np, const RefDev &ref, const int2 *faces, int n,

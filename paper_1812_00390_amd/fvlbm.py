@@ -62,6 +62,7 @@ SIGNATURES = {
     "fvlbm_step": (C.c_int, [_vp, C.c_int64]),
     "fvlbm_prepare": (C.c_int, [_vp, C.c_int64]),
     "fvlbm_macros": (C.c_int, [_vp, _dp, _dp, _dp]),
+    "fvlbm_macros_noalloc": (C.c_int, [_vp, _vp, _vp, _vp]),
     "fvlbm_get_f": (C.c_int, [_vp, _dp]),
     "fvlbm_set_f": (C.c_int, [_vp, _dp]),
     "fvlbm_rhs": (C.c_int, [_vp, _dp]),
@@ -245,6 +246,12 @@ class Solver:
         rho = np.zeros(self.n); u = np.zeros((self.n, 2)); st = np.zeros(4)
         _check(lib().fvlbm_macros(self.h, _dptr(rho), _dptr(u), _dptr(st)))
         return rho, u, dict(mass=st[0], residual=st[1], t=st[2], steps=int(st[3]))
+
+    def macros_noalloc(self, rho=None, u=None, stats=None):
+        """Step 6 into device tensors (float64; rho [n], u [n, 2], stats [2] = mass, non-finite
+        flag), enqueued on the solver's stream without allocating or syncing."""
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())
+        _check(lib().fvlbm_macros_noalloc(self.h, ptr(rho), ptr(u), ptr(stats)))
 
     def stats(self) -> dict:
         st = np.zeros(4)
