@@ -190,14 +190,51 @@ def precision(F):
     return {"metric": "max |u - u_oracle| / U at sampled cells", "runs": out}
 
 
-def served(args):
-    """The served workload at a reduced size (its own module runs the full sweep)."""
-    import subprocess
-    cmd = [sys.executable, "-m", "paper_1812_00390_amd.serve", "--requests", "32", "--loads", "0.5,1.0"]
-    r = subprocess.run(cmd, capture_output=True, text=True, cwd=ROOT, timeout=600)
-    if r.returncode != 0:
-        return {"error": r.stderr[-500:]}
-    return json.loads(r.stdout.strip().splitlines()[-1])
+def served(F, W):
+    """The served workload at a reduced size: the 64 batched instances (2k-200k
+    cells, cavities and cylinders) as requests of 1000 four-stage RK steps
+    each, FP16-deviation storage, advanced in chunks of 250 steps by the
+    continuous-batching server (preparation on worker threads); first all at
+    once (saturated), then as a Poisson stream at 0.75 x that capacity.  Every
+    result's error against its stored FP64 oracle run.  The full served sweep
+    (5k-500k cells, 200 requests x 5 rates, residual 1e-6 or 20,000 steps) is
+    run by the serving module itself."""
+    from paper_1812_00390_amd.serve import GpuBackend, Request, Server, summarize
+    insts = W.batched()
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_batched64_rk4_1000.npz")
+    ref = np.load(gold) if os.path.exists(gold) else None
+    steps, chunk, budget = 1000, 250, 2 ** 31
+    out = {"config": dict(requests=len(insts), cells=sum(i.n_cells for i in insts), steps_per_request=steps,
+                          chunk=chunk, storage="fp16dev", scheme="rk4", slots=64, prep_workers=4, loads=[0.75],
+                          hbm_budget_gb=2.0, seed=2)}
+
+    def errors(res):
+        if ref is None:
+            return None
+        e = [float(np.abs(r.u[ref[f"idx_{r.rid}"]] - ref[f"u_{r.rid}"]).max() / 0.1) for r in sorted(res, key=lambda r: r.rid)]
+        return dict(max=float(f"{max(e):.3g}"), per_request=[float(f"{x:.3g}") for x in e])
+
+    schedule = None
+    rng = np.random.default_rng(2)
+    for label, rate in (("saturated", None), ("load_0.75", 0.75)):
+        if rate is None:
+            arrivals = np.zeros(len(insts))
+        else:
+            arrivals = np.cumsum(rng.exponential(1.0 / (rate * out["capacity_req_per_s"]), len(insts)))
+        reqs = [Request(k, inst, tol=0.0, budget=steps, arrival=float(a)) for k, (inst, a) in enumerate(zip(insts, arrivals))]
+        be = GpuBackend(chunk=chunk, storage="fp16dev", schedule=schedule)
+        srv = Server(be, int(2 * 2 ** 30), 64, chunk, keep_fields=ref is not None, prep_workers=4)
+        res = srv.run(reqs)
+        schedule = be.schedule
+        rec = summarize(res, srv.wall, srv.cell_updates)
+        rec.update(batch_builds=be.batch_builds, chunks=srv.chunks, host_s=round(srv.host_s, 2), oracle_error=errors(res))
+        if rate is None:
+            out["capacity_req_per_s"] = round(len(res) / srv.wall, 3)
+        else:
+            rec["rate_req_per_s"] = round(rate * out["capacity_req_per_s"], 3)
+        out[label] = rec
+    out["schedule"] = schedule
+    return out
 
 
 def batched(F, W, stream, steps=1000, single_steps=100):
@@ -351,7 +388,7 @@ def main():
     if args.only in ("all", "precision"):
         rec["precision"] = precision(F)
     if args.only in ("all", "served"):
-        rec["served"] = served(args)
+        rec["served"] = served(F, W)
     print(json.dumps(rec))
 
 

@@ -223,6 +223,14 @@ fvlbm_status fvlbm_wall_force(fvlbm_solver *s, int32_t group, double force[2], i
  */
 fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_batch **out);
 fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps);
+/* The velocity residual of Eq. 32 of every member (as fvlbm_macros reports it: against the
+ * snapshot residual_lag steps earlier, -1 until two snapshots exist) and its step count:
+ * out[2 i] = residual, out[2 i + 1] = steps of member i, in the order given to
+ * fvlbm_batch_create.  One sync of the batch's stream for all members (the residual is
+ * formed on the device in FP64 when a step count reaches a multiple of the lag).
+ * Errors: FVLBM_E_ARG, FVLBM_E_STATE, FVLBM_E_DEVICE. */
+fvlbm_status fvlbm_batch_residuals(fvlbm_batch *b, double *out);
+
 /* Destroys the batch (not its members, which stay usable alone) and frees members
  * that were destroyed while the batch held them. */
 void fvlbm_batch_destroy(fvlbm_batch *b);
@@ -242,6 +250,12 @@ void fvlbm_batch_destroy(fvlbm_batch *b);
  * Errors: FVLBM_E_ARG (unsupported tile size, or tile plus halo do not fit
  * the LDS a workgroup may use: 160 KiB on gfx950). */
 fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap, int32_t persistent);
+
+/* Moves a solver's later work to another stream (after syncing the one it was
+ * on), e.g. a solver prepared on a side stream and then handed to the stream
+ * its batch runs on.  Errors: FVLBM_E_ARG, FVLBM_E_STATE (a batch holds it:
+ * members keep the batch's stream), FVLBM_E_DEVICE. */
+fvlbm_status fvlbm_set_stream(fvlbm_solver *s, void *hip_stream);
 fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap, int32_t *persistent);
 fvlbm_status fvlbm_batch_set_schedule(fvlbm_batch *b, int32_t block, int32_t xcd_remap, int32_t persistent);
 /* The schedule a batch launches with (after fvlbm_batch_set_schedule, fvlbm_batch_autotune, or the

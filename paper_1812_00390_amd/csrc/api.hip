@@ -102,6 +102,7 @@ struct fvlbm_solver {
 struct fvlbm_batch {
     std::vector<fvlbm_solver *> members;
     InstDesc *desc_dev = nullptr;     // [N_KINDS][n]
+    double **res_src = nullptr;       // device: each member's residual scalar, then n gathered values
     UnitTable ut[2];                  // by face-slot count (3, 4)
     int h2max[2] = {0, 0};
     int h1max[2] = {0, 0};
@@ -769,6 +770,14 @@ fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_rema
     return upload_descs(s);
 }
 
+fvlbm_status fvlbm_set_stream(fvlbm_solver *s, void *hip_stream) {
+    if (!s) return fail(FVLBM_E_ARG, "null solver");
+    if (s->batch_refs > 0) return fail(FVLBM_E_STATE, "a batch holds the solver; its members keep the batch's stream");
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "stream synchronize failed");
+    s->stream = (hipStream_t)hip_stream;
+    return FVLBM_OK;
+}
+
 fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *xcd_remap, int32_t *persistent) {
     if (!s || !block || !xcd_remap || !persistent) return fail(FVLBM_E_ARG, "null argument");
     *block = s->sched.block;
@@ -807,6 +816,14 @@ fvlbm_status batch_build(fvlbm_batch *b) {
     if (hipMalloc(&b->desc_dev, all.size() * sizeof(InstDesc)) != hipSuccess) return fail(FVLBM_E_NOMEM, "batch descriptor allocation failed");
     if (hipMemcpy(b->desc_dev, all.data(), all.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess)
         return fail(FVLBM_E_DEVICE, "batch descriptor upload failed");
+    if (!b->res_src) {   // members' residual scalars (fvlbm_batch_residuals); membership is fixed
+        std::vector<double *> src(n);
+        for (int i = 0; i < n; i++) src[i] = reinterpret_cast<double *>(b->members[i]->buf + b->members[i]->L.scal) + 1;
+        if (hipMalloc(&b->res_src, (size_t)n * (sizeof(double *) + sizeof(double))) != hipSuccess)
+            return fail(FVLBM_E_NOMEM, "batch residual table allocation failed");
+        if (hipMemcpy(b->res_src, src.data(), (size_t)n * sizeof(double *), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(FVLBM_E_DEVICE, "batch residual table upload failed");
+    }
     for (int t = 0; t < 2; t++) {
         b->h2max[t] = h2max[t];
         b->h1max[t] = h1max[t];
@@ -1035,6 +1052,24 @@ fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps) {
     return batch_enqueue(b, n_steps, true);
 }
 
+fvlbm_status fvlbm_batch_residuals(fvlbm_batch *b, double *out) {
+    if (!b || !out) return fail(FVLBM_E_ARG, "null argument");
+    fvlbm_status st = batch_usable(b);
+    if (st != FVLBM_OK) return st;
+    const int n = (int)b->members.size();
+    double *gathered = reinterpret_cast<double *>(b->res_src + n);
+    std::vector<double> r(n);
+    hipError_t e = launch_gather(b->res_src, gathered, n, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(r.data(), gathered, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return fail(FVLBM_E_DEVICE, std::string("batch residuals failed: ") + hipGetErrorString(e));
+    for (int i = 0; i < n; i++) {
+        out[2 * i] = b->members[i]->res_valid ? r[i] : -1.0;
+        out[2 * i + 1] = (double)b->members[i]->steps;
+    }
+    return FVLBM_OK;
+}
+
 fvlbm_status fvlbm_autotune(fvlbm_solver *s, int32_t trial_steps, double *best_ms) {
     if (!s || trial_steps <= 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_autotune");
     if (s->failed) return fail(FVLBM_E_STATE, "solver is in an error state");
@@ -1101,6 +1136,7 @@ void fvlbm_batch_destroy(fvlbm_batch *b) {
     hipStreamSynchronize(b->stream);
     free_graphs(b->graphs);
     if (b->desc_dev) hipFree(b->desc_dev);
+    if (b->res_src) hipFree(b->res_src);
     for (auto &u : b->ut) if (u.units) hipFree(u.units);
     std::vector<fvlbm_solver *> members = std::move(b->members);
     delete b;

@@ -248,6 +248,11 @@ __global__ void k_zero_int(int *p, int n) {
     for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0;
 }
 
+// dst[i] = *src[i]: one scalar from each of n solvers' buffers
+__global__ void k_gather(const double *const *src, double *dst, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = *src[i];
+}
+
 // out[0] = 1 if the flag is set, else 0
 __global__ void k_flag_out(const int *flag, double *out) {
     if (threadIdx.x == 0) out[0] = flag[0] ? 1.0 : 0.0;
@@ -335,6 +340,11 @@ hipError_t launch_snapshot(const void *src, int storage, int n, int np, const Re
 
 hipError_t launch_zero_int(int *p, int n, hipStream_t stream) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const double *const *src, double *dst, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_gather, dim3(1), dim3(256), 0, stream, src, dst, n);
     return hipGetLastError();
 }
 

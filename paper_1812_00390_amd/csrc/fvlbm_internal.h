@@ -238,6 +238,8 @@ hipError_t launch_snapshot(const void *src, int storage, int n, int np, const Re
 hipError_t launch_finish_sums(const double *partial, int nblk, double *out, int mode, hipStream_t stream);
 // clear n ints with a kernel; out[0] = (flag[0] != 0) as a double
 hipError_t launch_zero_int(int *p, int n, hipStream_t stream);
+// dst[i] = *src[i] for n device pointers (src itself a device array)
+hipError_t launch_gather(const double *const *src, double *dst, int n, hipStream_t stream);
 hipError_t launch_flag_out(const int *flag, double *out, hipStream_t stream);
 // Momentum flux through n wall faces (cell, slot) with wall velocity (uwx, uwy): partial sums of
 // (Fx, Fy) per block, and p = rho/3 of each face's border cell.

@@ -79,6 +79,8 @@ SIGNATURES = {
     "fvlbm_get_schedule": (C.c_int, [_vp, _ip, _ip, _ip]),
     "fvlbm_batch_set_schedule": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
     "fvlbm_batch_get_schedule": (C.c_int, [_vp, _ip, _ip, _ip]),
+    "fvlbm_batch_residuals": (C.c_int, [_vp, _dp]),
+    "fvlbm_set_stream": (C.c_int, [_vp, _vp]),
     "fvlbm_autotune": (C.c_int, [_vp, C.c_int32, _dp]),
     "fvlbm_batch_autotune": (C.c_int, [_vp, C.c_int32, _dp]),
     "fvlbm_last_error": (C.c_char_p, []),
@@ -300,6 +302,11 @@ class Solver:
         slots (tiles of 64 or 128 cells; Euler and RK stages)."""
         _check(lib().fvlbm_set_schedule(self.h, int(block), int(bool(xcd_remap)), int(persistent)))
 
+    def set_stream(self, stream):
+        """Move the solver's later work to `stream` (a torch stream, or 0 for the null stream)."""
+        _check(lib().fvlbm_set_stream(self.h, _stream_handle(stream)))
+        self.stream = stream
+
     def get_schedule(self):
         b, x, p = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().fvlbm_get_schedule(self.h, C.byref(b), C.byref(x), C.byref(p)))
@@ -344,6 +351,12 @@ class Batch:
         b, x, p = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().fvlbm_batch_get_schedule(self.h, C.byref(b), C.byref(x), C.byref(p)))
         return dict(block=b.value, xcd_remap=bool(x.value), persistent=bool(p.value))
+
+    def residuals(self):
+        """(residual, steps) of every member, one sync: residual of Eq. 32 over the lag, -1 if none yet."""
+        out = np.zeros(2 * len(self.solvers))
+        _check(lib().fvlbm_batch_residuals(self.h, _dptr(out)))
+        return out[0::2].copy(), out[1::2].astype(np.int64)
 
     def autotune(self, trial_steps: int = 64) -> float:
         """Pick the fastest launch schedule for the whole batch (states restored); ms per step."""

@@ -12,6 +12,8 @@ the method runs in the HIP library.
               FP16-deviation storage
   streaming   the cavity20k tanh mapping refined to 2048 x 2048 quads, split:
               8.4M triangles, far larger than the on-chip caches
+  served      requests of Couette channels, cavities, cylinders and two-cylinder
+              meshes (see served_instance)
 """
 from __future__ import annotations
 
@@ -72,6 +74,30 @@ def cavity20k() -> Instance:
 
 def cylinder98k() -> Instance:
     return cylinder_instance(256, 384, 100.0)
+
+
+def couette_instance(n: int) -> Instance:
+    """Plate-driven Couette flow as the first configuration (Section 3.1): unit
+    channel periodic in x, lid U = 0.1, tau = 0.8, here on n x n cells split
+    into 2 n^2 triangles.  Steady and viscous (Re = U L / nu = 0.375), so it
+    reaches a residual of 1e-6 within a few thousand steps."""
+    m = mg.couette(n, n, U=U_REF, tri=True)
+    tau = 0.8
+    return Instance(m, tau, U_REF, (0.0, 0.0), "couette", U_REF * 1.0 / (tau / 3.0))
+
+
+def served_instance(rng: np.random.Generator, n_cells: float,
+                    kinds=("couette", "cavity", "cylinder", "two_cylinders")) -> Instance:
+    """One request of the served workload: the kind drawn uniformly from `kinds`;
+    Couette channels, cavities (Re uniform in [100, 3000]) and cylinders (Re
+    uniform in [100, 3000]) of about n_cells cells; two-cylinder meshes of two
+    128 x 256 O-blocks (65,536 cells, Re uniform in [100, 200])."""
+    kind = kinds[int(rng.integers(len(kinds)))]
+    if kind == "couette":
+        return couette_instance(max(4, int(round(math.sqrt(n_cells / 2.0)))))
+    if kind == "two_cylinders":
+        return two_cylinder_instance(128, 256, float(rng.uniform(100.0, 200.0)))
+    return random_instance(rng, n_cells, kinds=(kind,))
 
 
 def random_instance(rng: np.random.Generator, n_cells: float, kinds=("cavity", "cylinder")) -> Instance:

@@ -150,7 +150,7 @@ def test_served_request_matches_its_oracle_run(F, O, storage, utol):
     chunk, budget = 50, 150
     reqs = [Request(k, inst, tol=0.0, budget=budget, arrival=0.0) for k, inst in enumerate(insts)]
     backend = GpuBackend(chunk=chunk, storage=storage, autotune=False)
-    srv = Server(backend, hbm_budget=2 ** 31, max_slots=2, chunk=chunk, keep_fields=True)
+    srv = Server(backend, hbm_budget=2 ** 31, max_slots=2, chunk=chunk, keep_fields=True, prep_workers=2)
     res = {r.rid: r for r in srv.run(reqs)}
     assert sorted(res) == [0, 1, 2]
     for k, inst in enumerate(insts):

@@ -26,7 +26,7 @@ def test_served_equals_alone_bitwise(F):
     budgets = [128, 320, 192, 256, 128]
     reqs = [Request(k, inst, tol=0.0, budget=b, arrival=0.0) for k, (inst, b) in enumerate(zip(insts, budgets))]
     backend = GpuBackend(chunk=chunk, autotune=False)
-    srv = Server(backend, hbm_budget=2 ** 31, max_slots=3, chunk=chunk, keep_fields=True)
+    srv = Server(backend, hbm_budget=2 ** 31, max_slots=3, chunk=chunk, keep_fields=True, prep_workers=2)
     res = {r.rid: r for r in srv.run(reqs)}
     assert sorted(res) == list(range(5))
     # membership changed while requests ran: more requests than slots

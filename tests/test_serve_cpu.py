@@ -31,7 +31,7 @@ class FakeBackend:
     def footprint(self, inst):
         return inst.n_cells * 100
 
-    def create(self, inst):
+    def prepare(self, inst):
         h = len(self.created)
         self.created.append(inst.n_cells)
         self.live[h] = dict(res=1.0, steps=0)
@@ -43,8 +43,8 @@ class FakeBackend:
             self.live[h]["res"] *= self.decay
             self.live[h]["steps"] += steps
 
-    def stats(self, h):
-        return dict(residual=self.live[h]["res"], steps=self.live[h]["steps"])
+    def residuals(self, handles):
+        return [self.live[h]["res"] for h in handles]
 
     def fields(self, h):
         return np.zeros(1), np.zeros((1, 2))
@@ -123,3 +123,25 @@ def test_summary_percentiles():
     assert s["p50_latency_s"] == pytest.approx(50.5)
     assert s["p99_latency_s"] == pytest.approx(99.01)
     assert s["M_cell_updates_per_s"] == 10.0
+
+
+class SlowFakeBackend(FakeBackend):
+    """Preparation takes a while and runs on the server's worker threads."""
+
+    def prepare(self, inst):
+        import time
+        time.sleep(0.002)
+        return super().prepare(inst)
+
+
+def test_threaded_preparation_completes_every_request():
+    be = SlowFakeBackend(decay=0.1)
+    reqs = [Request(k, FakeInst(100 * (k + 1)), tol=1e-3, budget=10_000, arrival=0.0005 * k) for k in range(24)]
+    srv = Server(be, hbm_budget=1_000_000, max_slots=5, chunk=10, prep_workers=2)
+    res = srv.run(reqs)
+    assert sorted(r.rid for r in res) == list(range(24))
+    assert srv.used == 0 and not srv.active and not srv.preparing and not be.live
+    assert all(r.converged and r.steps == 40 for r in res)      # 0.1^4 < 1e-3 after four chunks
+    assert max(len(b) for b in be.batches) <= 5
+    assert all(r.admitted >= r.arrival for r in res)
+
