@@ -193,7 +193,7 @@ def precision(F):
 def served(F, W):
     """The served workload at a reduced size: the 64 batched instances (2k-200k
     cells, cavities and cylinders) as requests of 1000 four-stage RK steps
-    each, FP16-deviation storage, advanced in chunks of 250 steps by the
+    each, FP32-deviation storage, advanced in chunks of 250 steps by the
     continuous-batching server (preparation on worker threads); first all at
     once (saturated), then as a Poisson stream at 0.75 x that capacity.  Every
     result's error against its stored FP64 oracle run.  The full served sweep
@@ -205,7 +205,7 @@ def served(F, W):
     ref = np.load(gold) if os.path.exists(gold) else None
     steps, chunk, budget = 1000, 250, 2 ** 31
     out = {"config": dict(requests=len(insts), cells=sum(i.n_cells for i in insts), steps_per_request=steps,
-                          chunk=chunk, storage="fp16dev", scheme="rk4", slots=64, prep_workers=4, loads=[0.75],
+                          chunk=chunk, storage="fp32dev", scheme="rk4", slots=64, prep_workers=4, loads=[0.75],
                           hbm_budget_gb=2.0, seed=2)}
 
     def errors(res):
@@ -222,7 +222,7 @@ def served(F, W):
         else:
             arrivals = np.cumsum(rng.exponential(1.0 / (rate * out["capacity_req_per_s"]), len(insts)))
         reqs = [Request(k, inst, tol=0.0, budget=steps, arrival=float(a)) for k, (inst, a) in enumerate(zip(insts, arrivals))]
-        be = GpuBackend(chunk=chunk, storage="fp16dev", schedule=schedule)
+        be = GpuBackend(chunk=chunk, storage="fp32dev", schedule=schedule)
         srv = Server(be, int(2 * 2 ** 30), 64, chunk, keep_fields=ref is not None, prep_workers=4)
         res = srv.run(reqs)
         schedule = be.schedule

@@ -216,8 +216,9 @@ fvlbm_status fvlbm_wall_force(fvlbm_solver *s, int32_t group, double force[2], i
  * Batched solves: several solvers (each with its own mesh, parameters and
  * state) advanced by shared launches, one work unit per (solver, cell tile).
  * All solvers must use the same scheme and storage and the same stream.
- * fvlbm_batch_step() advances every member by n_steps; the launches of one
- * chunk of steps are captured once into a HIP graph and replayed.
+ * fvlbm_batch_step() advances every member by n_steps; the launches of 8 steps
+ * (and of the powers of two below for the rest of a call) are built once into
+ * HIP graphs and replayed.
  * The per-cell arithmetic is the same as fvlbm_step(): a member's result does
  * not depend on the other members.  Errors: FVLBM_E_ARG, FVLBM_E_PARAM, FVLBM_E_DEVICE.
  */
@@ -235,8 +236,8 @@ fvlbm_status fvlbm_batch_residuals(fvlbm_batch *b, double *out);
  * that were destroyed while the batch held them. */
 void fvlbm_batch_destroy(fvlbm_batch *b);
 
-/* Launch schedule: tile size in cells (one workgroup per tile: 64, 128, 256 or
- * 512), whether tiles are renumbered so that each XCD walks one contiguous
+/* Launch schedule: tile size in cells (one workgroup per tile: a multiple of 64
+ * from 64 to 512), whether tiles are renumbered so that each XCD walks one contiguous
  * range of tiles (neighbouring tiles then share that XCD's L2), and the launch
  * form `persistent`: 0 one workgroup per tile; 1 a persistent grid sized to
  * the resident capacity walks the tile list; 2 one workgroup per tile with one
@@ -262,7 +263,9 @@ fvlbm_status fvlbm_batch_set_schedule(fvlbm_batch *b, int32_t block, int32_t xcd
  * one fvlbm_batch_create chose).  Errors: FVLBM_E_ARG. */
 fvlbm_status fvlbm_batch_get_schedule(const fvlbm_batch *b, int32_t *block, int32_t *xcd_remap, int32_t *persistent);
 
-/* Autotuner: times every supported schedule for trial_steps steps (HIP
+/* Autotuner: times every supported schedule (tile sizes 64, 128, 256, 512 and
+ * the multiples of 64 that split the cells into about 1-4 tiles per compute
+ * unit, each with and without XCD remap, each launch form) for trial_steps steps (HIP
  * events on the solver's or batch's stream), keeps the fastest, and restores
  * the state, step counters and residual snapshots to what they were, so the
  * solve continues exactly as without tuning.  best_ms (may be NULL) receives

@@ -145,7 +145,7 @@ __half *carry_ptr(fvlbm_solver *s) {
 InstDesc base_desc(fvlbm_solver *s, const TileTables *tt) {
     const MeshDev &m = s->mesh->dev;
     InstDesc d{};
-    d.vxy = m.vxy; d.dxy = m.dxy; d.inva = m.inva; d.minv = m.minv;
+    d.vxy = m.vxy; d.dxy = m.dxy;
     d.lnbr = tt->lnbr; d.halo_idx = tt->halo_idx; d.halo_code = tt->halo_code;
     d.h1s = tt->h1max; d.h2s = tt->h2max;
     d.n_cells = m.n_cells; d.np = m.np;
@@ -267,15 +267,19 @@ hipGraphExec_t solver_graph(fvlbm_solver *s, int cur, int nsteps) {
 
 constexpr int GRAPH_CHUNK = 32;
 
-// Steps replayed by the next graph for `left` steps to go: 32 while at least
-// 32 remain, then the largest power of two (so any count uses at most six
-// graph sizes, each cached by start buffer and size).
-int graph_steps(int64_t left) {
-    if (left >= GRAPH_CHUNK) return GRAPH_CHUNK;
+// Steps replayed by the next graph for `left` steps to go: `chunk` (a power
+// of two) while at least that many remain, then the largest power of two (so
+// any count uses a handful of graph sizes, each cached by start buffer and size).
+int graph_steps(int64_t left, int chunk = GRAPH_CHUNK) {
+    if (left >= chunk) return chunk;
     int c = 1;
     while (2 * c <= left) c *= 2;
     return c;
 }
+// A batch replays graphs of 8 steps: its membership changes as requests come and
+// go (each change instantiates new graphs), and a graph's instantiation time grows
+// with its node count (steps x stages x cell kinds).
+constexpr int BATCH_GRAPH_CHUNK = 8;
 
 // Enqueue n steps without snapshots.  dry: only instantiate the graphs the
 // call would replay (the caller saves and restores the solver's position).
@@ -752,8 +756,12 @@ fvlbm_status fvlbm_restore(fvlbm_solver *s, const void *host_buf, size_t bytes) 
     return FVLBM_OK;
 }
 
+namespace {
+bool valid_block(int b) { return b >= 64 && b <= 512 && b % 64 == 0; }
+}  // namespace
+
 fvlbm_status fvlbm_set_schedule(fvlbm_solver *s, int32_t block, int32_t xcd_remap, int32_t persistent) {
-    if (!s || (block != 64 && block != 128 && block != 256 && block != 512)) return fail(FVLBM_E_ARG, "unsupported block size");
+    if (!s || !valid_block(block)) return fail(FVLBM_E_ARG, "unsupported block size (a multiple of 64 from 64 to 512)");
     const TileTables *tt = nullptr;
     std::string err;
     fvlbm_status st = get_tiles(s->mesh->dev, block, &tt, err);
@@ -877,7 +885,7 @@ fvlbm_status fvlbm_batch_get_schedule(const fvlbm_batch *b, int32_t *block, int3
 }
 
 fvlbm_status fvlbm_batch_set_schedule(fvlbm_batch *b, int32_t block, int32_t xcd_remap, int32_t persistent) {
-    if (!b || (block != 64 && block != 128 && block != 256 && block != 512)) return fail(FVLBM_E_ARG, "unsupported block size");
+    if (!b || !valid_block(block)) return fail(FVLBM_E_ARG, "unsupported block size (a multiple of 64 from 64 to 512)");
     Schedule old = b->sched;
     b->sched.block = block;
     b->sched.xcd_remap = xcd_remap ? 1 : 0;
@@ -947,7 +955,7 @@ fvlbm_status batch_enqueue(fvlbm_batch *b, int64_t n_steps, bool snapshots, bool
     int cur = b->members[0]->cur;
     bool hp = true;
     while (left > 0) {
-        const int chunk = graph_steps(left);
+        const int chunk = graph_steps(left, BATCH_GRAPH_CHUNK);
         hipGraphExec_t ex = batch_graph(b, cur, chunk);
         if (!ex) return fail(FVLBM_E_DEVICE, "batch graph build failed");
         for (int k = 0; k < chunk; k++) advance_position(b->scheme, cur, hp);
@@ -1030,7 +1038,20 @@ double time_steps(hipStream_t stream, int steps, Prep prep, Run run) {
     return st == FVLBM_OK ? ms / steps : -1;
 }
 
-const int TUNE_BLOCKS[] = {64, 128, 256, 512};
+// Tile sizes the autotuners try: the four powers of two, and the sizes that
+// split n cells into about 256 k tiles (one, two ... workgroups per CU of a
+// 256-CU GPU), rounded up to a multiple of 64.
+std::vector<int> tune_blocks(int64_t n) {
+    std::vector<int> out = {64, 128, 256, 512};
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    for (int k = 1; k <= 4; k++) {
+        const int64_t per = (n + (int64_t)cus * k - 1) / ((int64_t)cus * k);
+        const int t = (int)((per + 63) / 64 * 64);
+        if (t >= 64 && t <= 512 && std::find(out.begin(), out.end(), t) == out.end()) out.push_back(t);
+    }
+    return out;
+}
 }  // namespace
 
 extern "C" {
@@ -1079,7 +1100,7 @@ fvlbm_status fvlbm_autotune(fvlbm_solver *s, int32_t trial_steps, double *best_m
     if (st != FVLBM_OK) return st;
     Schedule best = s->sched;
     double best_t = 1e300;
-    for (int T : TUNE_BLOCKS)
+    for (int T : tune_blocks(s->mesh->dev.n_cells))
         for (int x = 0; x < 2; x++)
             for (int ps = 0; ps < (T <= 128 ? 3 : 2); ps++) {
                 if (fvlbm_set_schedule(s, T, x, ps) != FVLBM_OK) continue;
@@ -1113,7 +1134,9 @@ fvlbm_status fvlbm_batch_autotune(fvlbm_batch *b, int32_t trial_steps, double *b
     }
     Schedule best = b->sched;
     double best_t = 1e300;
-    for (int T : TUNE_BLOCKS)
+    int64_t cells = 0;
+    for (fvlbm_solver *m : b->members) cells += m->mesh->dev.n_cells;
+    for (int T : tune_blocks(cells))
         for (int x = 0; x < 2; x++)
             for (int ps = 0; ps < 2; ps++) {
                 if (fvlbm_batch_set_schedule(b, T, x, ps) != FVLBM_OK) continue;

@@ -83,8 +83,6 @@ struct MeshDev {
     // FP32 per-cell description, planes [slot][np] (see the geometry pass)
     float2 *vxy = nullptr;       // corner k - centroid
     float2 *dxy = nullptr;       // stencil offset of slot k
-    float *inva = nullptr;       // 1/A
-    float *minv = nullptr;       // [3][np] inverse least-squares matrix (m11, m12, m22)
     std::vector<int> nbr_host;   // [n][nf] slot codes (new order), for the tile tables
     std::map<int, struct TileTables> tiles;   // by tile size
     // FP64 per cell
@@ -134,7 +132,6 @@ void free_tiles(MeshDev &mesh);
 // One instance's view for a stage launch (device memory, read through scalar loads).
 struct InstDesc {
     const float2 *vxy, *dxy;
-    const float *inva, *minv;
     const uint2 *lnbr;
     const int *halo_idx;
     const uint2 *halo_code;

@@ -42,18 +42,20 @@ __global__ void k_cell_geometry(int n, int nf, const int *__restrict__ ncorner,
 
 // Compact FP32 per-cell description consumed by the step kernels:
 //   v[k]   corner k minus the centroid (corners padded with corner 0 up to nf)
-//   inva   1 / A
 //   d[k]   least-squares stencil offset x_n - x_i of slot k (0 on padded slots)
-//   minv   the 2x2 inverse of M = sum_k w_k d_k d_k^T, w_k = 1/|d_k|^2 (Eq. 12)
-// From these the kernels form the face midpoint offset (v_k + v_k+1)/2, the
-// scaled normal rot(v_k+1 - v_k)/A = n dl / A, the gradient coefficient
-// M^-1 w_k d_k, and the neighbour's offset to the face (midpoint - d_k).
+// From these the kernels form 1/A (shoelace over the v[k]), the face midpoint
+// offset (v_k + v_k+1)/2, the scaled normal rot(v_k+1 - v_k)/A = n dl / A, the
+// least-squares matrix M = sum_k w_k d_k d_k^T with w_k = 1/|d_k|^2 and its
+// inverse (Eq. 12; M is dimensionless and well scaled, so this is done in FP32
+// in registers, which reads 16 B per cell less than storing M^-1 and 1/A), the
+// gradient coefficient M^-1 w_k d_k, and the neighbour's offset to the face
+// (midpoint - d_k).  Here M is formed in FP64 only to reject a singular
+// stencil.
 __global__ void k_face_coefficients(int n, int nf, int np, const int *__restrict__ ncorner,
                                     const double *__restrict__ xy, const int *__restrict__ nbr_in,
                                     const double *__restrict__ shift, const double *__restrict__ cen,
                                     const double *__restrict__ area, const int *__restrict__ gkind,
-                                    float2 *__restrict__ vxy, float *__restrict__ inva,
-                                    float2 *__restrict__ dxy, float *__restrict__ minv,
+                                    float2 *__restrict__ vxy, float2 *__restrict__ dxy,
                                     int *__restrict__ bad) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -92,11 +94,7 @@ __global__ void k_face_coefficients(int n, int nf, int np, const int *__restrict
     }
     double det = m11 * m22 - m12 * m12;
     double tr = m11 + m22;
-    if (!(det > 1e-12 * tr * tr)) { atomicOr(bad, 1); det = 1.0; }
-    minv[i] = (float)(m22 / det);
-    minv[(size_t)np + i] = (float)(-m12 / det);
-    minv[2 * (size_t)np + i] = (float)(m11 / det);
-    inva[i] = (float)(1.0 / area[i]);
+    if (!(det > 1e-12 * tr * tr)) atomicOr(bad, 1);
 }
 
 __global__ void k_min_reduce(const double *__restrict__ v, int n, double *__restrict__ out) {
@@ -130,8 +128,6 @@ fvlbm_status build_device_mesh(const HostTopology &topo, const fvlbm_bc *groups,
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     size_t o_vxy = take((size_t)nf * np * sizeof(float2));
     size_t o_dxy = take((size_t)nf * np * sizeof(float2));
-    size_t o_inva = take((size_t)np * sizeof(float));
-    size_t o_minv = take((size_t)3 * np * sizeof(float));
     size_t o_area = take((size_t)n * sizeof(double));
     size_t o_perm = take((size_t)n * sizeof(int));
     // boundary faces by group, the caller's order within each group
@@ -149,8 +145,6 @@ fvlbm_status build_device_mesh(const HostTopology &topo, const fvlbm_bc *groups,
     mesh.block = blk; mesh.bytes = total;
     mesh.vxy = (float2 *)(blk + o_vxy);
     mesh.dxy = (float2 *)(blk + o_dxy);
-    mesh.inva = (float *)(blk + o_inva);
-    mesh.minv = (float *)(blk + o_minv);
     mesh.nbr_host = topo.nbr;
     mesh.area = (double *)(blk + o_area);
     mesh.perm_dev = (int *)(blk + o_perm);
@@ -192,7 +186,7 @@ fvlbm_status build_device_mesh(const HostTopology &topo, const fvlbm_bc *groups,
         hipLaunchKernelGGL(k_face_coefficients, dim3(nb), dim3(256), 0, stream, n, nf, np,
                            (const int *)(scr + s_nc), (const double *)(scr + s_xy), (const int *)(scr + s_nb),
                            (const double *)(scr + s_sh), (const double *)(scr + s_cen), mesh.area,
-                           (const int *)(scr + s_gk), mesh.vxy, mesh.inva, mesh.dxy, mesh.minv,
+                           (const int *)(scr + s_gk), mesh.vxy, mesh.dxy,
                            (int *)(scr + s_bad));
         chk(hipGetLastError());
         hipLaunchKernelGGL(k_min_reduce, dim3(1), dim3(1024), 0, stream, (const double *)(scr + s_cfl), n,

@@ -906,9 +906,11 @@ struct Hot {
 // half of phase 3).
 // Dynamic LDS: nA = T + (largest ring-1 slot count) region-A records, then
 // region-B records for the largest ring-2 slot count (sized by the launcher).
-template <int NF, int STORE, int T, bool DIRECT, bool M0, bool RING>
+template <int NF, int STORE, int TC, bool DIRECT, bool M0, bool RING>
 __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, int2 u, const Hot &hot, float4 *A,
                                           int sa, float4 *B) {
+    // TC: the tile size, or 0 for a tile size chosen at launch (the block size)
+    const int T = TC ? TC : (int)blockDim.x;
     const InstDesc &d = descs[u.x];
     // Two descriptor lines (reference state and update coefficients) are first
     // needed at the end of phase 1 (the split form's collision terms) or in
@@ -931,7 +933,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // RING: threads [0, T) own the tile's cells and one more wave, [T, T + 64),
     // owns the halo slots, so halo loads and ring-1 gradients run beside the
     // tile's own; otherwise thread t owns tile cell t and halo slot t.
-    constexpr int RS = RING ? 64 : T;                 // halo slots per pass
+    const int RS = RING ? 64 : T;                     // halo slots per pass
     // With 64-cell tiles (SPLIT3) two more waves form directions 5-8 of the
     // phase-2 gradients, one for the tile's cells (thread T + 64 + l: cell l), one
     // for the ring-1 slots (thread T + 128 + s: slot s), the tile and halo waves
@@ -939,22 +941,22 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // (0, 1, 3 | 2, 4 | 5, 7 | 6, 8), lane l of each taking tile cell l.
     // Opposite directions share a set, so every value is the one the whole pass
     // forms.
-    constexpr bool SPLIT3 = split_form(T, STORE, RING);
+    constexpr bool SPLIT3 = split_form(TC, STORE, RING);
     constexpr int GA = SPLIT3 ? 0 : -1;               // gradient half of the tile and halo waves
     // SPLIT3: phi_k - h of the tile cells' boundary slots, formed in phase 2 by
     // the tile's two waves (each its half of the directions), staged for the
     // phase-3 direction sets of every wave (the first slot of each also stays in
     // registers): float4 planes of T cells
-    __shared__ float4 lstash[SPLIT3 ? T * NF * 2 : 1];
+    __shared__ float4 lstash[SPLIT3 ? TC * NF * 2 : 1];
     // SPLIT3: the tile cells' phase-3 geometry (neighbour codes, h0, 1/A, stencil
     // offsets, corners), written by the tile's wave in phase 1 for the waves that
     // take the other direction sets: GP float4 planes of T cells
     constexpr int GP = 5;
-    __shared__ float4 lgeo[SPLIT3 ? T * GP : 1];
+    __shared__ float4 lgeo[SPLIT3 ? TC * GP : 1];
     // SPLIT3: the tile cells' collision term f_eq - f (a function of the cell's
     // own state), formed once in phase 1 by the wave for directions 5-8 of the
     // tile cells (which waits at the barrier longest): 3 float4 planes
-    __shared__ float4 lneq[SPLIT3 ? T * 3 : 1];
+    __shared__ float4 lneq[SPLIT3 ? TC * 3 : 1];
     const int wtid = RING ? __builtin_amdgcn_readfirstlane(tid) : 0;   // (wave-uniform)
     const bool ownw = !RING || wtid < T;                               // the tile's cells
     const bool ownb = SPLIT3 && wtid >= T + 64 && wtid < T + 128;      // their directions 5-8
@@ -1023,7 +1025,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // the instance's boundary groups, staged in LDS for the boundary slots (read
     // whole, without waiting for the group count)
     __shared__ GroupDev lg[MAX_GROUPS];
-    constexpr int BS = tile_threads(T, STORE, RING);  // threads per block
+    const int BS = TC ? tile_threads(TC, STORE, RING) : T;   // threads per block
     constexpr int GW = MAX_GROUPS * (int)(sizeof(GroupDev) / sizeof(int));
     const int *gsrc = reinterpret_cast<const int *>(d.groups);
     const int gv0 = ldg(gsrc, tid < GW ? tid : 0);
@@ -1220,7 +1222,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
 // (Arguments in the order the kernel needs them: the first sixteen dwords arrive in
 // scalar registers.)
 template <int NF, int STORE, int T, bool DIRECT, bool M0, bool RING>
-__global__ void __launch_bounds__(tile_threads(T, STORE, RING)) k_tile(const int *hot_halo_idx, const void *hot_src, const uint2 *hot_lnbr,
+__global__ void __launch_bounds__(T ? tile_threads(T, STORE, RING) : 512) k_tile(const int *hot_halo_idx, const void *hot_src, const uint2 *hot_lnbr,
                                             const float2 *hot_dxy, const float2 *hot_vxy, int hot_h12, int hot_np,
                                             int hot_n_cells, int units_x, const uint2 *hot_halo_code, const void *hot_base,
                                             const InstDesc *__restrict__ descs, int nA,
@@ -1231,7 +1233,7 @@ __global__ void __launch_bounds__(tile_threads(T, STORE, RING)) k_tile(const int
                   hot_np, hot_n_cells, hot_h12 & 0xffff, hot_h12 >> 16};
     // region-A records: T + h1s for a single instance (preloaded, so the first LDS
     // writes wait on no argument load), else the largest over the instances
-    const int sa = DIRECT ? T + (hot_h12 & 0xffff) : nA;
+    const int sa = DIRECT ? (T ? T : (int)blockDim.x) + (hot_h12 & 0xffff) : nA;
     tile_body<NF, STORE, T, DIRECT, M0, RING>(descs, (DIRECT || !units) ? make_int2(0, ub) : units[ub], hot, lds4,
                                              sa, lds4 + sa * RA);
 }
@@ -1240,7 +1242,7 @@ __global__ void __launch_bounds__(tile_threads(T, STORE, RING)) k_tile(const int
 // Persistent form: a grid sized to the resident capacity walks the unit list
 // (a multiple of 8 blocks, so each block stays on one XCD's range of tiles).
 template <int NF, int STORE, int T, bool M0>
-__global__ void __launch_bounds__(T) k_tile_persistent(const int *, const void *, const uint2 *, const float2 *,
+__global__ void __launch_bounds__(T ? T : 512) k_tile_persistent(const int *, const void *, const uint2 *, const float2 *,
                                                        const float2 *, int, int, int, int units_x, const uint2 *,
                                                        const void *, const InstDesc *__restrict__ descs, int nA,
                                                        const int2 *__restrict__ units) {
@@ -1261,7 +1263,7 @@ const void *fn(bool persistent, bool direct, bool m0, bool ring) {
         return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, false, false>)
                       : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false, false, false>);
     if (persistent) return reinterpret_cast<const void *>(&k_tile_persistent<NF, STORE, T, true>);
-    if constexpr (T <= 128)   // a ring wave: single instance, mode 0, tiles of 64 or 128 cells
+    if constexpr (T != 0 && T <= 128)   // a ring wave: single instance, mode 0, tiles of 64 or 128 cells
         if (ring && direct) return reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, true, true>);
     return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, true, false>)
                   : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false, true, false>);
@@ -1273,7 +1275,8 @@ const void *pick_t(int T, bool persistent, bool direct, bool m0, bool ring) {
     case 64: return fn<NF, STORE, 64>(persistent, direct, m0, ring);
     case 128: return fn<NF, STORE, 128>(persistent, direct, m0, ring);
     case 256: return fn<NF, STORE, 256>(persistent, direct, m0, ring);
-    default: return fn<NF, STORE, 512>(persistent, direct, m0, ring);
+    case 512: return fn<NF, STORE, 512>(persistent, direct, m0, ring);
+    default: return fn<NF, STORE, 0>(persistent, direct, m0, ring);   // other multiples of 64: set at launch
     }
 }
 

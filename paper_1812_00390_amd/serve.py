@@ -75,7 +75,7 @@ class GpuBackend:
     other streams do not wait for it); requests are prepared on a side stream
     and handed to the compute stream when they join."""
 
-    def __init__(self, scheme: str = "rk4", storage: str = "fp16dev", chunk: int = 1000, autotune: bool = True,
+    def __init__(self, scheme: str = "rk4", storage: str = "fp32dev", chunk: int = 1000, autotune: bool = True,
                  schedule: Optional[dict] = None, tune_members: int = 8):
         import torch
         from . import fvlbm as F
@@ -338,7 +338,10 @@ def main():
     ap.add_argument("--calib", type=int, default=48, help="requests of the saturated capacity run")
     ap.add_argument("--hbm-budget-gb", type=float, default=4.0, help="artificial admission budget")
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--storage", default="fp16dev", choices=["fp32dev", "fp16dev", "i16dev"])
+    # FP32 deviations: the 16-bit formats keep a rounding noise in the non-conserved moments that
+    # the collision relaxes at dt/tau per step; where tau >> dt (the viscous Couette requests) it
+    # holds the residual of Eq. 32 above 1e-6 (2e-4 block-scaled, 3e-3 FP16 on a 5k-cell channel)
+    ap.add_argument("--storage", default="fp32dev", choices=["fp32dev", "fp16dev", "i16dev"])
     ap.add_argument("--prep-workers", type=int, default=4)
     ap.add_argument("--capacity", type=float, default=0.0,
                     help="requests/s of a previous capacity run (skips the capacity run)")
