@@ -89,6 +89,12 @@ class GpuBackend:
         self._batch = None
         self._members = None
         self.batch_builds = 0
+        # host seconds of the main thread: batch (re)builds, enqueueing chunks (the first
+        # chunk of a new batch also instantiates its graphs), releasing finished requests
+        self.t_build = self.t_enqueue = self.t_free = 0.0
+
+    def timings(self) -> dict:
+        return dict(build_s=round(self.t_build, 2), enqueue_s=round(self.t_enqueue, 2), free_s=round(self.t_free, 2))
 
     def prepare(self, inst):
         """Device mesh and solver (Step 0) for a request, on the side stream; tile tables for
@@ -124,6 +130,7 @@ class GpuBackend:
         members = [h[1] for h in handles]
         if self._members is None or len(self._members) != len(members) or \
                 any(a is not b for a, b in zip(self._members, members)):
+            t0 = time.perf_counter()
             if self._batch is not None:
                 self._batch.close()
             self._batch = F.Batch(members)
@@ -138,11 +145,15 @@ class GpuBackend:
             elif self.autotune and len(members) >= self.tune_members:
                 self._batch.autotune(16)
                 self.schedule = self._batch.get_schedule()
+            self.t_build += time.perf_counter() - t0
         return self._batch
 
     def advance(self, handles: List, steps: int):
         """Enqueue `steps` steps of every running request (does not wait)."""
-        self._batch_for(handles).step(steps)
+        b = self._batch_for(handles)
+        t0 = time.perf_counter()
+        b.step(steps)
+        self.t_enqueue += time.perf_counter() - t0
 
     def residuals(self, handles: List) -> List[float]:
         """Residual of every running request (-1 while none), one sync."""
@@ -154,12 +165,14 @@ class GpuBackend:
         return rho, u
 
     def free(self, handle):
+        t0 = time.perf_counter()
         if self._members is not None and any(handle[1] is m for m in self._members):
             self._batch.close()
             self._batch = None
             self._members = None
         handle[1].close()
         handle[0].close()
+        self.t_free += time.perf_counter() - t0
 
 
 class Server:
@@ -335,7 +348,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--chunk", type=int, default=1000, help="steps per chunk, also the residual lag K")
     ap.add_argument("--slots", type=int, default=64)
-    ap.add_argument("--calib", type=int, default=48, help="requests of the saturated capacity run")
+    ap.add_argument("--calib", type=int, default=48, help="requests of the saturated run (all there at t = 0)")
     ap.add_argument("--hbm-budget-gb", type=float, default=4.0, help="artificial admission budget")
     ap.add_argument("--seed", type=int, default=2)
     # FP32 deviations: the 16-bit formats keep a rounding noise in the non-conserved moments that
@@ -361,6 +374,13 @@ def main():
                 f"latency {r.latency:.2f} s, {len(srv.active)} running, {len(srv.queue)} queued")
 
     budget = int(args.hbm_budget_gb * 2 ** 30)
+    # the load runs' requests (sizes and kinds do not depend on the rate: the arrival gaps
+    # are drawn from the same generator, only scaled); their mean work sets the capacity
+    probe = make_requests(args.requests, 1.0, args.seed, args.min_cells, args.max_cells, args.tol, args.budget)
+    mean_work = float(np.mean([q.inst.n_cells for q in probe])) * args.budget
+    out["load_requests"] = dict(mean_cells=round(mean_work / args.budget, 1),
+                                kinds=dict(collections.Counter(q.inst.kind for q in probe)))
+    del probe
     if args.capacity > 0:
         capacity = args.capacity
         b, x, p = (int(v) for v in args.schedule.split(","))
@@ -374,11 +394,14 @@ def main():
         srv = Server(backend, budget, args.slots, args.chunk, prep_workers=args.prep_workers, progress=progress)
         srv.run(calib)
         cap_cells = srv.cell_updates / srv.wall
-        capacity = len(srv.results) / srv.wall
+        # requests/s the saturated rate sustains for the load runs' mean request (its
+        # cell count times the step budget; the few that converge early take less)
+        capacity = cap_cells / mean_work
         schedule = backend.schedule
         out["capacity_req_per_s"] = round(capacity, 4)
         out["saturated"] = summarize(srv.results, srv.wall, srv.cell_updates)
-        out["saturated"].update(batch_builds=backend.batch_builds, chunks=srv.chunks, host_s=round(srv.host_s, 2))
+        out["saturated"].update(batch_builds=backend.batch_builds, chunks=srv.chunks, host_s=round(srv.host_s, 2),
+                                **backend.timings())
         out["saturated_M_cell_updates_per_s"] = round(cap_cells / 1e6, 1)
         if args.single > 0:
             # the plain single-instance FP32 path on the first calibration requests, one at a time
@@ -412,7 +435,7 @@ def main():
         res = srv.run(reqs)
         s = summarize(res, srv.wall, srv.cell_updates)
         s.update(rate_req_per_s=round(load * capacity, 4), rejected=len(srv.rejected), chunks=srv.chunks,
-                 batch_builds=be.batch_builds, host_s=round(srv.host_s, 2))
+                 batch_builds=be.batch_builds, host_s=round(srv.host_s, 2), **be.timings())
         out[f"load_{load}"] = s
         log(json.dumps(s))
     print(json.dumps(out))
