@@ -116,6 +116,9 @@ def _run_pair(F, O, m, tau, scheme, steps, storage="fp32dev", cfl=0.5, u_ref=0.1
 # 64-cell tiles, XCD remap, launch form 2 (the halo wave; with per-value storage
 # the four-wave split form).
 BENCH_SCHEDULE = (64, True, 2)
+# ... and on the 98,304-quad cylinder (the headline): 384-cell tiles (one per CU,
+# a tile size set at launch), XCD remap, one workgroup per tile.
+HEADLINE_SCHEDULE = (384, True, 0)
 
 # FP16 deviations (each cell's nine values rounded together so that its mass
 # and momentum keep their value, the rounding residual carried to the next
@@ -294,7 +297,8 @@ def test_schedules_do_not_change_results(F, scheme):
     m = mg.cavity(n=22, jitter=0.2, seed=13)
     outs = []
     for block, x, p in [(256, True, False), (64, False, True), (128, True, True), (256, False, False),
-                        (64, True, 2), (128, False, 2), (512, True, False), (512, False, True)]:
+                        (64, True, 2), (128, False, 2), (512, True, False), (512, False, True),
+                        (192, True, 0), (384, False, 1), (320, True, 0)]:
         mesh = F.Mesh(m)
         s = F.Solver(mesh, F.make_params(tau=3e-4, scheme=scheme))
         s.set_schedule(block, x, p)
@@ -404,7 +408,7 @@ def test_cavity_cfg2_full_run_vs_stored_oracle(F, schedule):
         assert np.abs(rho[idx] - ref["rho"]).max() <= utol * 0.1
 
 
-@pytest.mark.parametrize("schedule", [None, BENCH_SCHEDULE, (512, True, 0), (128, False, 1)])
+@pytest.mark.parametrize("schedule", [None, BENCH_SCHEDULE, HEADLINE_SCHEDULE, (512, True, 0), (128, False, 1)])
 def test_cylinder_cfg3_full_size_vs_stored_oracle(F, schedule):
     ref = np.load(os.path.join(GOLDEN, "oracle_cylinder256_rk4_100.npz"))
     m = mg.cylinder(nr=256, nt=384)
@@ -423,7 +427,8 @@ def test_cylinder_cfg3_full_size_vs_stored_oracle(F, schedule):
         assert err <= utol * 0.1
 
 
-def test_cylinder_cfg3_full_run_vs_stored_oracle(F):
+@pytest.mark.parametrize("schedule", [None, HEADLINE_SCHEDULE])
+def test_cylinder_cfg3_full_run_vs_stored_oracle(F, schedule):
     # the full start-up run of the cylinder case: 20,000 four-stage RK steps
     path = os.path.join(GOLDEN, "oracle_cylinder256_rk4_20000.npz")
     if not os.path.exists(path):
@@ -436,6 +441,8 @@ def test_cylinder_cfg3_full_run_vs_stored_oracle(F):
         s = F.Solver(mesh, F.make_params(tau=float(ref["tau"]), dt=float(ref["dt"]), scheme="rk4",
                                          storage=storage, u_ref=0.2, u_dev=(0.1, 0.0)),
                      u=np.tile([0.1, 0.0], (m.n_cells, 1)))
+        if schedule:
+            s.set_schedule(*schedule)
         s.step(int(ref["steps"]))
         rho, u, _ = s.macros()
         idx = ref["idx"]
