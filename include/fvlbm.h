@@ -78,7 +78,12 @@ typedef struct {
                               values per cell, 6 bytes) is carried to the next step's update: the state is
                               the stored values less that carry.  fvlbm_macros and the residual include
                               it; fvlbm_get_f, fvlbm_rhs and fvlbm_wall_force see the stored values;
-                              fvlbm_set_f and Step 0 set it from their own rounding */
+                              fvlbm_set_f and Step 0 set it from their own rounding.
+                              Accuracy of the 16-bit formats: the rounding noise left in the
+                              non-conserved moments is relaxed by the collision over about tau/dt
+                              steps, so it grows as sqrt(tau/dt) ulps: FP16 deviations keep
+                              1e-3 U where tau/dt is below about 10 (2e-3 U at tau/dt = 78),
+                              the block-scaled format about ten times better */
     double rho0;           /* reference density of the deviation storage (and of Step 0 when no field is given) */
     double fp16_scale;     /* S of the FP16 deviation storage; 0 = 3 |u_ref| (or 0.3 if u_ref = 0) */
     int32_t residual_lag;  /* steps between velocity snapshots for the residual (Eq. 32); 0 = 1000 */

@@ -154,6 +154,17 @@ def test_couette_cfg1_full_run(F, O):
     assert 0 <= st["residual"] < 1e-5
 
 
+def test_couette_cfg1_block_scaled_storage(F, O):
+    """The same run in the 16-bit block-scaled format: 1e-3 U.  (FP16 deviations reach
+    2e-3 U here: with tau / dt = 78 the collision relaxes the rounding noise of the
+    non-conserved moments only over about 78 steps, so it grows as sqrt(tau / dt) ulps;
+    the cavity and cylinder configurations have tau / dt near 4.)"""
+    m = mg.couette(16, 16, U=0.1)
+    (rg, ug, st), (ro, uo), o, s = _run_pair(F, O, m, 0.8, "euler", 6000, storage="i16dev")
+    assert np.abs(ug - uo).max() <= 1e-3 * 0.1
+    assert np.abs(rg - ro).max() <= 1e-4
+
+
 @pytest.mark.parametrize("name", ["channel_ext", "channel_int_sym", "cylinder", "two_cylinders", "hybrid"])
 def test_boundary_runs_match_oracle(F, O, name):
     make, tau = RHS_MESHES[name]
