@@ -227,7 +227,7 @@ def served(F, W):
         res = srv.run(reqs)
         schedule = be.schedule
         rec = summarize(res, srv.wall, srv.cell_updates)
-        rec.update(batch_builds=be.batch_builds, chunks=srv.chunks, host_s=round(srv.host_s, 2), oracle_error=errors(res))
+        rec.update(**be.graph_counts(), chunks=srv.chunks, host_s=round(srv.host_s, 2), oracle_error=errors(res))
         if rate is None:
             out["capacity_req_per_s"] = round(len(res) / srv.wall, 3)
         else:

@@ -237,6 +237,26 @@ fvlbm_status fvlbm_batch_step(fvlbm_batch *b, int64_t n_steps);
  * Errors: FVLBM_E_ARG, FVLBM_E_STATE, FVLBM_E_DEVICE. */
 fvlbm_status fvlbm_batch_residuals(fvlbm_batch *b, double *out);
 
+/* Replaces the batch's members (continuous batching: requests join and leave
+ * between calls), keeping its schedule and its instantiated graphs.  The graphs'
+ * kernel nodes are re-pointed in place at the new members' descriptors and work
+ * units (grid and LDS size follow); a graph built when the batch held another set
+ * of cell kinds (triangle, quadrilateral) is rebuilt at the next step instead.
+ * Each member advances exactly as alone (Section 2.4.2 per cell; the other
+ * members do not enter its arithmetic).
+ *   solvers, n   the new members, the same constraints as fvlbm_batch_create and
+ *                the batch's scheme, storage and stream; a member may stay, leave or
+ *                join.  Members that leave and were destroyed while the batch held
+ *                them are freed here.
+ * Synchronizes the batch's stream.  Errors: FVLBM_E_ARG (also: the new members'
+ * tiles do not fit the LDS at the batch's tile size), FVLBM_E_PARAM, FVLBM_E_NOMEM,
+ * FVLBM_E_DEVICE; on error the batch keeps its old members. */
+fvlbm_status fvlbm_batch_set_members(fvlbm_batch *b, fvlbm_solver *const *solvers, int32_t n);
+/* How many graphs the batch has instantiated, and how many times a membership
+ * change re-pointed an instantiated graph instead (fvlbm_batch_set_members).
+ * Errors: FVLBM_E_ARG. */
+fvlbm_status fvlbm_batch_graph_counts(const fvlbm_batch *b, int64_t *built, int64_t *repointed);
+
 /* Destroys the batch (not its members, which stay usable alone) and frees members
  * that were destroyed while the batch held them. */
 void fvlbm_batch_destroy(fvlbm_batch *b);

@@ -99,17 +99,36 @@ struct fvlbm_solver {
     ~fvlbm_solver();
 };
 
+// One instantiated batch graph, with what a membership change needs to re-point
+// its kernel nodes in place: the template it was instantiated from (whose node
+// handles name the exec's nodes), each node's descriptor kind and cell kind, and
+// each node's argument storage.
+struct BatchGraph {
+    struct Node {
+        hipGraphNode_t node;
+        int k, t;                     // descriptor kind (stage), cell kind (3 + t face slots)
+        std::unique_ptr<StageArgs> args;
+        void *argv[16];               // argv[0] = args, argv[1..14] = argument pointers
+    };
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t tmpl = nullptr;
+    std::vector<std::unique_ptr<Node>> nodes;
+    unsigned kinds = 0;               // cell kinds with units when built (bit t)
+};
+
 struct fvlbm_batch {
     std::vector<fvlbm_solver *> members;
     InstDesc *desc_dev = nullptr;     // [N_KINDS][n]
     double **res_src = nullptr;       // device: each member's residual scalar, then n gathered values
+    int res_cap = 0;                  // members res_src has room for
     UnitTable ut[2];                  // by face-slot count (3, 4)
     int h2max[2] = {0, 0};
     int h1max[2] = {0, 0};
     int scheme = 0, storage = 0;
     hipStream_t stream = nullptr;
-    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::map<std::pair<int, int>, BatchGraph> graphs;
     Schedule sched;
+    int64_t graph_builds = 0, graph_updates = 0;   // instantiated, and re-pointed on a membership change
 };
 
 namespace {
@@ -118,6 +137,13 @@ namespace {
 // unit table must not be destroyed while queued work may still use it.
 void free_graphs(std::map<std::pair<int, int>, hipGraphExec_t> &g) {
     for (auto &kv : g) hipGraphExecDestroy(kv.second);
+    g.clear();
+}
+void free_graphs(std::map<std::pair<int, int>, BatchGraph> &g) {
+    for (auto &kv : g) {
+        hipGraphExecDestroy(kv.second.exec);
+        hipGraphDestroy(kv.second.tmpl);
+    }
     g.clear();
 }
 
@@ -797,8 +823,15 @@ fvlbm_status fvlbm_get_schedule(const fvlbm_solver *s, int32_t *block, int32_t *
 // ------------------------------------------------------------------ batch
 
 namespace {
-// (Re)build a batch's descriptors and unit tables for its schedule.
-fvlbm_status batch_build(fvlbm_batch *b) {
+unsigned batch_kinds(const fvlbm_batch *b) {
+    return (b->ut[0].n_units ? 1u : 0u) | (b->ut[1].n_units ? 2u : 0u);
+}
+
+// (Re)build a batch's descriptors, unit tables and residual table for its
+// members and schedule.  Nothing changes when the members' tiles do not fit the
+// LDS at the schedule's tile size.  keep_graphs: leave the instantiated graphs
+// (the caller re-points or drops them); else they are dropped.
+fvlbm_status batch_build(fvlbm_batch *b, bool keep_graphs = false) {
     const int n = (int)b->members.size();
     std::vector<InstDesc> all((size_t)N_KINDS * n);
     int h2max[2] = {0, 0}, h1max[2] = {0, 0};
@@ -819,19 +852,23 @@ fvlbm_status batch_build(fvlbm_batch *b) {
         if (stage_lds_bytes(b->sched.block, h2max[t], h1max[t]) > stage_lds_limit())
             return fail(FVLBM_E_ARG, "batch tiles do not fit the LDS at this block size");
     if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(FVLBM_E_DEVICE, "stream synchronize failed");
-    free_graphs(b->graphs);
+    if (!keep_graphs) free_graphs(b->graphs);
     if (b->desc_dev) { hipFree(b->desc_dev); b->desc_dev = nullptr; }
     if (hipMalloc(&b->desc_dev, all.size() * sizeof(InstDesc)) != hipSuccess) return fail(FVLBM_E_NOMEM, "batch descriptor allocation failed");
     if (hipMemcpy(b->desc_dev, all.data(), all.size() * sizeof(InstDesc), hipMemcpyHostToDevice) != hipSuccess)
         return fail(FVLBM_E_DEVICE, "batch descriptor upload failed");
-    if (!b->res_src) {   // members' residual scalars (fvlbm_batch_residuals); membership is fixed
-        std::vector<double *> src(n);
-        for (int i = 0; i < n; i++) src[i] = reinterpret_cast<double *>(b->members[i]->buf + b->members[i]->L.scal) + 1;
+    // members' residual scalars (fvlbm_batch_residuals), then room for the gathered values
+    if (b->res_cap < n) {
+        if (b->res_src) { hipFree(b->res_src); b->res_src = nullptr; }
+        b->res_cap = 0;
         if (hipMalloc(&b->res_src, (size_t)n * (sizeof(double *) + sizeof(double))) != hipSuccess)
             return fail(FVLBM_E_NOMEM, "batch residual table allocation failed");
-        if (hipMemcpy(b->res_src, src.data(), (size_t)n * sizeof(double *), hipMemcpyHostToDevice) != hipSuccess)
-            return fail(FVLBM_E_DEVICE, "batch residual table upload failed");
+        b->res_cap = n;
     }
+    std::vector<double *> src(n);
+    for (int i = 0; i < n; i++) src[i] = reinterpret_cast<double *>(b->members[i]->buf + b->members[i]->L.scal) + 1;
+    if (hipMemcpy(b->res_src, src.data(), (size_t)n * sizeof(double *), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(FVLBM_E_DEVICE, "batch residual table upload failed");
     for (int t = 0; t < 2; t++) {
         b->h2max[t] = h2max[t];
         b->h1max[t] = h1max[t];
@@ -840,6 +877,22 @@ fvlbm_status batch_build(fvlbm_batch *b) {
             if (b->members[i]->mesh->dev.nf == 3 + t) inst.push_back({i, b->members[i]->mesh->dev.n_cells});
         fvlbm_status st = make_units(inst, b->sched.block, b->ut[t]);
         if (st != FVLBM_OK) return st;
+    }
+    return FVLBM_OK;
+}
+
+// Members for a batch of this scheme, storage and stream: usable, not repeated,
+// at one buffer parity (Euler, AB2), past their first AB2 step.
+fvlbm_status check_members(fvlbm_solver *const *solvers, int n, int scheme, int storage, hipStream_t stream) {
+    for (int i = 0; i < n; i++) {
+        fvlbm_solver *s = solvers[i];
+        if (!s || s->failed || s->destroyed) return fail(FVLBM_E_ARG, "null, failed or destroyed solver in batch");
+        if (s->p.scheme != scheme || s->p.storage != storage) return fail(FVLBM_E_PARAM, "batch members must share scheme and storage");
+        if (s->stream != stream) return fail(FVLBM_E_PARAM, "batch members must share a stream");
+        if (s->p.scheme != FVLBM_SCHEME_RK4 && s->cur != solvers[0]->cur) return fail(FVLBM_E_PARAM, "batch members must be at the same buffer parity");
+        if (s->p.scheme == FVLBM_SCHEME_AB2 && !s->have_prev) return fail(FVLBM_E_PARAM, "AB2 members must have taken their first step");
+        for (int j = 0; j < i; j++)
+            if (solvers[j] == s) return fail(FVLBM_E_PARAM, "a solver appears twice in the batch");
     }
     return FVLBM_OK;
 }
@@ -853,15 +906,9 @@ fvlbm_status fvlbm_batch_create(fvlbm_solver *const *solvers, int32_t n, fvlbm_b
     b->storage = solvers[0]->p.storage;
     b->stream = solvers[0]->stream;
     b->sched = solvers[0]->sched;
-    for (int i = 0; i < n; i++) {
-        fvlbm_solver *s = solvers[i];
-        if (!s || s->failed || s->destroyed) return fail(FVLBM_E_ARG, "null, failed or destroyed solver in batch");
-        if (s->p.scheme != b->scheme || s->p.storage != b->storage) return fail(FVLBM_E_PARAM, "batch members must share scheme and storage");
-        if (s->stream != b->stream) return fail(FVLBM_E_PARAM, "batch members must share a stream");
-        if (s->p.scheme != FVLBM_SCHEME_RK4 && s->cur != solvers[0]->cur) return fail(FVLBM_E_PARAM, "batch members must be at the same buffer parity");
-        if (s->p.scheme == FVLBM_SCHEME_AB2 && !s->have_prev) return fail(FVLBM_E_PARAM, "AB2 members must have taken their first step");
-        b->members.push_back(s);
-    }
+    fvlbm_status cst = check_members(solvers, n, b->scheme, b->storage, b->stream);
+    if (cst != FVLBM_OK) return cst;
+    b->members.assign(solvers, solvers + n);
     // the first member's tile size, or the largest smaller one whose tiles fit the LDS
     fvlbm_status st = FVLBM_E_ARG;
     for (int T : {b->sched.block, 256, 128, 64}) {
@@ -884,6 +931,38 @@ fvlbm_status fvlbm_batch_get_schedule(const fvlbm_batch *b, int32_t *block, int3
     return FVLBM_OK;
 }
 
+namespace {
+void repoint_graphs(fvlbm_batch *b);
+}  // namespace
+
+fvlbm_status fvlbm_batch_set_members(fvlbm_batch *b, fvlbm_solver *const *solvers, int32_t n) {
+    if (!b || !solvers || n <= 0) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_batch_set_members");
+    fvlbm_status st = check_members(solvers, n, b->scheme, b->storage, b->stream);
+    if (st != FVLBM_OK) return st;
+    std::vector<fvlbm_solver *> old = b->members;
+    b->members.assign(solvers, solvers + n);
+    st = batch_build(b, true);
+    if (st != FVLBM_OK) {
+        b->members = old;
+        if (batch_build(b, true) != FVLBM_OK) free_graphs(b->graphs);
+        else repoint_graphs(b);
+        return st;
+    }
+    repoint_graphs(b);
+    for (fvlbm_solver *s : b->members) s->batch_refs++;
+    // members that left and were destroyed while the batch held them are freed now
+    for (fvlbm_solver *s : old)
+        if (--s->batch_refs == 0 && s->destroyed) solver_free(s);
+    return FVLBM_OK;
+}
+
+fvlbm_status fvlbm_batch_graph_counts(const fvlbm_batch *b, int64_t *built, int64_t *repointed) {
+    if (!b || !built || !repointed) return fail(FVLBM_E_ARG, "null argument");
+    *built = b->graph_builds;
+    *repointed = b->graph_updates;
+    return FVLBM_OK;
+}
+
 fvlbm_status fvlbm_batch_set_schedule(fvlbm_batch *b, int32_t block, int32_t xcd_remap, int32_t persistent) {
     if (!b || !valid_block(block)) return fail(FVLBM_E_ARG, "unsupported block size (a multiple of 64 from 64 to 512)");
     Schedule old = b->sched;
@@ -902,11 +981,11 @@ namespace {
 hipGraphExec_t batch_graph(fvlbm_batch *b, int cur, int nsteps) {
     auto key = std::make_pair(cur, nsteps);
     auto it = b->graphs.find(key);
-    if (it != b->graphs.end()) return it->second;
-    hipGraph_t g;
-    if (hipGraphCreate(&g, 0) != hipSuccess) return nullptr;
+    if (it != b->graphs.end()) return it->second.exec;
+    BatchGraph bg;
+    if (hipGraphCreate(&bg.tmpl, 0) != hipSuccess) return nullptr;
+    bg.kinds = batch_kinds(b);
     std::vector<int> ks;
-    std::vector<std::unique_ptr<void *[]>> argstore;
     std::vector<hipGraphNode_t> prev;
     const int n = (int)b->members.size();
     int c = cur;
@@ -917,25 +996,58 @@ hipGraphExec_t batch_graph(fvlbm_batch *b, int cur, int nsteps) {
             std::vector<hipGraphNode_t> now;
             for (int t = 0; t < 2 && ok; t++) {
                 if (b->ut[t].n_units == 0) continue;
-                argstore.emplace_back(new void *[16]);
-                void **ab = argstore.back().get();
-                ab[0] = new char[sizeof(StageArgs)];
-                hipGraphNode_t node;
-                ok = add_stage_node(g, &node, prev.empty() ? nullptr : prev.data(), (int)prev.size(),
+                auto nd = std::make_unique<BatchGraph::Node>();
+                nd->k = k;
+                nd->t = t;
+                nd->args = std::make_unique<StageArgs>();
+                nd->argv[0] = nd->args.get();
+                ok = add_stage_node(bg.tmpl, &nd->node, prev.empty() ? nullptr : prev.data(), (int)prev.size(),
                                     b->desc_dev + (size_t)k * n, b->ut[t], 3 + t, b->storage,
-                                    b->sched.xcd_remap, b->sched.persistent, b->h2max[t], b->h1max[t], mode0(k), ab) == hipSuccess;
-                now.push_back(node);
+                                    b->sched.xcd_remap, b->sched.persistent, b->h2max[t], b->h1max[t], mode0(k),
+                                    nd->argv) == hipSuccess;
+                now.push_back(nd->node);
+                bg.nodes.push_back(std::move(nd));
             }
             prev = now;
         }
         advance_position(b->scheme, c, hp);
     }
-    hipGraphExec_t ex = nullptr;
-    if (ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) ex = nullptr;
-    for (auto &a : argstore) delete[] static_cast<char *>(a[0]);
-    hipGraphDestroy(g);
-    if (ex) b->graphs[key] = ex;
+    if (ok && hipGraphInstantiate(&bg.exec, bg.tmpl, nullptr, nullptr, 0) != hipSuccess) bg.exec = nullptr;
+    if (!bg.exec) {
+        hipGraphDestroy(bg.tmpl);
+        return nullptr;
+    }
+    b->graph_builds++;
+    hipGraphExec_t ex = bg.exec;
+    b->graphs.emplace(key, std::move(bg));
     return ex;
+}
+
+// After a membership change: re-point every instantiated graph's kernel nodes at
+// the new descriptors and unit tables (grid and LDS size follow).  A graph built
+// for another set of cell kinds, or whose update fails, is dropped and rebuilt
+// when next needed.  The stream has been synchronized (batch_build).
+void repoint_graphs(fvlbm_batch *b) {
+    const int n = (int)b->members.size();
+    const unsigned kinds = batch_kinds(b);
+    for (auto it = b->graphs.begin(); it != b->graphs.end();) {
+        BatchGraph &bg = it->second;
+        bool ok = bg.kinds == kinds;
+        for (size_t i = 0; ok && i < bg.nodes.size(); i++) {
+            BatchGraph::Node &nd = *bg.nodes[i];
+            ok = set_stage_node(bg.exec, nd.node, b->desc_dev + (size_t)nd.k * n, b->ut[nd.t], 3 + nd.t, b->storage,
+                                b->sched.xcd_remap, b->sched.persistent, b->h2max[nd.t], b->h1max[nd.t], mode0(nd.k),
+                                nd.argv) == hipSuccess;
+        }
+        if (ok) {
+            b->graph_updates++;
+            ++it;
+        } else {
+            hipGraphExecDestroy(bg.exec);
+            hipGraphDestroy(bg.tmpl);
+            it = b->graphs.erase(it);
+        }
+    }
 }
 }  // namespace
 

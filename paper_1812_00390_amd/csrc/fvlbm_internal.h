@@ -208,6 +208,12 @@ hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode
                           const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
                           int xcd_remap, int persistent, int h2max, int h1max, bool mode0, void **argbuf,
                           const InstDesc *host_desc = nullptr);
+// Re-point a kernel node of an instantiated graph, added by add_stage_node() with the
+// same nf, storage, tile size, XCD remap, persistent and mode0 (so the same kernel) and
+// no host descriptor, at other descriptors and units (grid and LDS size follow).
+hipError_t set_stage_node(hipGraphExec_t ex, hipGraphNode_t node, const InstDesc *descs_dev, const UnitTable &ut,
+                          int nf, int storage, int xcd_remap, int persistent, int h2max, int h1max, bool mode0,
+                          void **argbuf);
 
 // Step 0 and conversions (FP64 host data in input order <-> device storage).
 // carry: FP16 storage's moment carry (3 planes of np), written with the rounding residual of

@@ -1366,14 +1366,15 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
                            args, lds, stream);
 }
 
-hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
-                          const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
-                          int xcd_remap, int persistent, int h2max, int h1max, bool mode0, void **argbuf,
-                          const InstDesc *host_desc) {
+namespace {
+// Kernel-node parameters of one stage launch (as launch_stage() would launch it).
+// argbuf: caller-owned storage (a StageArgs block in argbuf[0], then one pointer per
+// argument), alive until the node is added or set.
+hipError_t stage_node_params(hipKernelNodeParams *p, const InstDesc *descs_dev, const UnitTable &ut, int nf,
+                             int storage, int xcd_remap, int persistent, int h2max, int h1max, bool mode0,
+                             void **argbuf, const InstDesc *host_desc) {
     const bool ring_form = persistent == 2;
     if (!mode0 || ring_form) persistent = 0;
-    // argbuf: caller-owned storage (a StageArgs block in argbuf[0], then one pointer per
-    // argument), alive until the graph is instantiated
     StageArgs *a = reinterpret_cast<StageArgs *>(argbuf[0]);
     *a = stage_args(descs_dev, ut, xcd_remap, persistent, h1max, host_desc);
     const bool ring = ring_form && mode0 && a->direct && ut.block <= 128;
@@ -1381,19 +1382,41 @@ hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode
     kp[0] = &a->hidx; kp[1] = &a->src; kp[2] = &a->lnbr; kp[3] = &a->dxy; kp[4] = &a->vxy; kp[5] = &a->h12;
     kp[6] = &a->np; kp[7] = &a->nc; kp[8] = &a->ux; kp[9] = &a->hcode; kp[10] = &a->base; kp[11] = &a->d;
     kp[12] = &a->nA; kp[13] = &a->u;
-    hipKernelNodeParams p{};
+    *p = hipKernelNodeParams{};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
-    p.func = const_cast<void *>(pick(nf, storage, ut.block, persistent, a->direct, mode0, ring));
+    p->func = const_cast<void *>(pick(nf, storage, ut.block, persistent, a->direct, mode0, ring));
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(p.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(p->func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    p.gridDim = dim3(grid_blocks(ut, persistent, nf, storage, lds));
-    p.blockDim = dim3(tile_threads(ut.block, storage, ring));
-    p.sharedMemBytes = (unsigned)lds;
-    p.kernelParams = kp;
-    p.extra = nullptr;
+    p->gridDim = dim3(grid_blocks(ut, persistent, nf, storage, lds));
+    p->blockDim = dim3(tile_threads(ut.block, storage, ring));
+    p->sharedMemBytes = (unsigned)lds;
+    p->kernelParams = kp;
+    p->extra = nullptr;
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t add_stage_node(hipGraph_t g, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps,
+                          const InstDesc *descs_dev, const UnitTable &ut, int nf, int storage,
+                          int xcd_remap, int persistent, int h2max, int h1max, bool mode0, void **argbuf,
+                          const InstDesc *host_desc) {
+    hipKernelNodeParams p;
+    hipError_t e = stage_node_params(&p, descs_dev, ut, nf, storage, xcd_remap, persistent, h2max, h1max, mode0,
+                                     argbuf, host_desc);
+    if (e != hipSuccess) return e;
     return hipGraphAddKernelNode(node, g, deps, ndeps, &p);
+}
+
+hipError_t set_stage_node(hipGraphExec_t ex, hipGraphNode_t node, const InstDesc *descs_dev, const UnitTable &ut,
+                          int nf, int storage, int xcd_remap, int persistent, int h2max, int h1max, bool mode0,
+                          void **argbuf) {
+    hipKernelNodeParams p;
+    hipError_t e = stage_node_params(&p, descs_dev, ut, nf, storage, xcd_remap, persistent, h2max, h1max, mode0,
+                                     argbuf, nullptr);
+    if (e != hipSuccess) return e;
+    return hipGraphExecKernelNodeSetParams(ex, node, &p);
 }
 
 }  // namespace fvlbm

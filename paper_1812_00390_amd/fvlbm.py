@@ -80,6 +80,8 @@ SIGNATURES = {
     "fvlbm_batch_set_schedule": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
     "fvlbm_batch_get_schedule": (C.c_int, [_vp, _ip, _ip, _ip]),
     "fvlbm_batch_residuals": (C.c_int, [_vp, _dp]),
+    "fvlbm_batch_set_members": (C.c_int, [_vp, C.POINTER(_vp), C.c_int32]),
+    "fvlbm_batch_graph_counts": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "fvlbm_set_stream": (C.c_int, [_vp, _vp]),
     "fvlbm_autotune": (C.c_int, [_vp, C.c_int32, _dp]),
     "fvlbm_batch_autotune": (C.c_int, [_vp, C.c_int32, _dp]),
@@ -342,6 +344,19 @@ class Batch:
 
     def step(self, n: int):
         _check(lib().fvlbm_batch_step(self.h, int(n)))
+
+    def set_members(self, solvers: Sequence[Solver]):
+        """Replace the members, keeping the schedule and re-pointing the instantiated graphs."""
+        solvers = list(solvers)
+        arr = (C.c_void_p * len(solvers))(*[s.h.value for s in solvers])
+        _check(lib().fvlbm_batch_set_members(self.h, arr, len(solvers)))
+        self.solvers = solvers
+
+    def graph_counts(self) -> dict:
+        """Graphs instantiated so far, and graphs re-pointed by membership changes."""
+        b, r = C.c_int64(), C.c_int64()
+        _check(lib().fvlbm_batch_graph_counts(self.h, C.byref(b), C.byref(r)))
+        return dict(built=b.value, repointed=r.value)
 
     def set_schedule(self, block: int, xcd_remap: bool = True, persistent: bool = False):
         _check(lib().fvlbm_batch_set_schedule(self.h, int(block), int(bool(xcd_remap)), int(bool(persistent))))

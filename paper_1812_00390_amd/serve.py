@@ -88,13 +88,25 @@ class GpuBackend:
         self.prep = torch.cuda.Stream()
         self._batch = None
         self._members = None
-        self.batch_builds = 0
+        self._freed = set()
+        self.batch_builds = 0           # batches created
+        self.member_changes = 0         # membership changes applied to the running batch in place
+        self.graphs_built = self.graphs_repointed = 0   # of closed batches (see graph_counts)
         # host seconds of the main thread: batch (re)builds, enqueueing chunks (the first
         # chunk of a new batch also instantiates its graphs), releasing finished requests
         self.t_build = self.t_enqueue = self.t_free = 0.0
 
     def timings(self) -> dict:
         return dict(build_s=round(self.t_build, 2), enqueue_s=round(self.t_enqueue, 2), free_s=round(self.t_free, 2))
+
+    def graph_counts(self) -> dict:
+        """Batch graphs instantiated, and re-pointed in place by membership changes."""
+        built, rep = self.graphs_built, self.graphs_repointed
+        if self._batch is not None:
+            c = self._batch.graph_counts()
+            built, rep = built + c["built"], rep + c["repointed"]
+        return dict(batch_builds=self.batch_builds, member_changes=self.member_changes, graphs_built=built,
+                    graphs_repointed=rep)
 
     def prepare(self, inst):
         """Device mesh and solver (Step 0) for a request, on the side stream; tile tables for
@@ -126,15 +138,24 @@ class GpuBackend:
         return int(mesh + state)
 
     def _batch_for(self, handles: List):
+        """The running batch with these members.  A membership change keeps the batch, its
+        schedule and its instantiated graphs (re-pointed in place); a new batch is made only
+        when there is none, or the new members' tiles do not fit the batch's tile size."""
         F = self.F
         members = [h[1] for h in handles]
-        if self._members is None or len(self._members) != len(members) or \
-                any(a is not b for a, b in zip(self._members, members)):
-            t0 = time.perf_counter()
-            if self._batch is not None:
+        if self._members is not None and len(self._members) == len(members) and \
+                all(a is b for a, b in zip(self._members, members)):
+            return self._batch
+        t0 = time.perf_counter()
+        if self._batch is not None:
+            try:
+                self._batch.set_members(members)
+                self.member_changes += 1
+            except F.FvlbmError:
                 self._batch.close()
+                self._batch = None
+        if self._batch is None:
             self._batch = F.Batch(members)
-            self._members = members
             self.batch_builds += 1
             if self.schedule is not None:
                 try:
@@ -142,10 +163,12 @@ class GpuBackend:
                                              self.schedule["persistent"])
                 except F.FvlbmError:
                     pass                 # this mix's tiles do not fit that schedule: keep the default
-            elif self.autotune and len(members) >= self.tune_members:
-                self._batch.autotune(16)
-                self.schedule = self._batch.get_schedule()
-            self.t_build += time.perf_counter() - t0
+        self._members = members
+        self._freed = set()
+        if self.schedule is None and self.autotune and len(members) >= self.tune_members:
+            self._batch.autotune(16)
+            self.schedule = self._batch.get_schedule()
+        self.t_build += time.perf_counter() - t0
         return self._batch
 
     def advance(self, handles: List, steps: int):
@@ -165,14 +188,26 @@ class GpuBackend:
         return rho, u
 
     def free(self, handle):
+        """Release a request's solver and mesh.  While the running batch still holds the
+        solver, the library frees it when the batch next changes members (or is closed,
+        once every member has been freed)."""
         t0 = time.perf_counter()
         if self._members is not None and any(handle[1] is m for m in self._members):
-            self._batch.close()
-            self._batch = None
-            self._members = None
+            self._freed.add(id(handle[1]))
+            if len(self._freed) == len(self._members):
+                self.close()
         handle[1].close()
         handle[0].close()
         self.t_free += time.perf_counter() - t0
+
+    def close(self):
+        if self._batch is not None:
+            counts = self._batch.graph_counts()
+            self.graphs_built += counts["built"]
+            self.graphs_repointed += counts["repointed"]
+            self._batch.close()
+        self._batch = None
+        self._members = None
 
 
 class Server:
@@ -400,7 +435,7 @@ def main():
         schedule = backend.schedule
         out["capacity_req_per_s"] = round(capacity, 4)
         out["saturated"] = summarize(srv.results, srv.wall, srv.cell_updates)
-        out["saturated"].update(batch_builds=backend.batch_builds, chunks=srv.chunks, host_s=round(srv.host_s, 2),
+        out["saturated"].update(**backend.graph_counts(), chunks=srv.chunks, host_s=round(srv.host_s, 2),
                                 **backend.timings())
         out["saturated_M_cell_updates_per_s"] = round(cap_cells / 1e6, 1)
         if args.single > 0:
@@ -435,7 +470,7 @@ def main():
         res = srv.run(reqs)
         s = summarize(res, srv.wall, srv.cell_updates)
         s.update(rate_req_per_s=round(load * capacity, 4), rejected=len(srv.rejected), chunks=srv.chunks,
-                 batch_builds=be.batch_builds, host_s=round(srv.host_s, 2), **be.timings())
+                 **be.graph_counts(), host_s=round(srv.host_s, 2), **be.timings())
         out[f"load_{load}"] = s
         log(json.dumps(s))
     print(json.dumps(out))
