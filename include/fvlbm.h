@@ -265,7 +265,13 @@ void fvlbm_batch_destroy(fvlbm_batch *b);
  * from 64 to 512), whether tiles are renumbered so that each XCD walks one contiguous
  * range of tiles (neighbouring tiles then share that XCD's L2), and the launch
  * form `persistent`: 0 one workgroup per tile; 1 a persistent grid sized to
- * the resident capacity walks the tile list; 2 one workgroup per tile with one
+ * the resident capacity takes tiles from a device work queue (one ticket
+ * counter per XCD, each over its own contiguous range of tiles, stealing from
+ * the others when its own is used up; Euler and RK stages, other stages as 0),
+ * so fast workgroups take more tiles and none waits for a new launch; the
+ * queue lives with the solver's or batch's tile tables and every launch leaves
+ * it cleared, so launches of one solver or batch must stay ordered on its
+ * stream (as the library issues them); 2 one workgroup per tile with one
  * more wave that loads the tile's halo and forms the ring-1 gradients beside
  * the tile's own (single solvers, tiles of 64 or 128 cells, Euler and RK
  * stages; elsewhere it acts as 0); with 64-cell tiles and per-value storage
@@ -291,7 +297,8 @@ fvlbm_status fvlbm_batch_get_schedule(const fvlbm_batch *b, int32_t *block, int3
 /* Autotuner: times every supported schedule (tile sizes 64, 128, 256, 512 and
  * the multiples of 64 that split the cells into about 1-4 tiles per compute
  * unit, each with and without XCD remap, each launch form) for trial_steps steps (HIP
- * events on the solver's or batch's stream), keeps the fastest, and restores
+ * events on the solver's or batch's stream; after one untimed run, the faster of
+ * two timed runs), keeps the fastest, and restores
  * the state, step counters and residual snapshots to what they were, so the
  * solve continues exactly as without tuning.  best_ms (may be NULL) receives
  * the chosen schedule's time per step.  Syncs the stream.

@@ -153,6 +153,11 @@ fvlbm_status make_units(const std::vector<std::pair<int, int>> &inst, int block,
     for (auto &pr : inst)
         for (int t = 0; t * block < pr.second; t++) units.push_back(make_int2(pr.first, t));
     if (ut.units) { hipFree(ut.units); ut.units = nullptr; }
+    if (!ut.queue) {   // the persistent form's work queue: zero, and left zero by every launch
+        const size_t qb = 9 * 128;   // eight per-XCD ticket counters and a leaving count, one line each
+        if (hipMalloc(&ut.queue, qb) != hipSuccess) return fail(FVLBM_E_NOMEM, "work queue allocation failed");
+        if (hipMemset(ut.queue, 0, qb) != hipSuccess) return fail(FVLBM_E_DEVICE, "work queue clear failed");
+    }
     ut.n_units = (int)units.size();
     ut.block = block;
     ut.direct = inst.size() == 1 && inst[0].first == 0;   // unit b is (instance 0, tile b): no table lookup
@@ -395,6 +400,7 @@ fvlbm_solver::~fvlbm_solver() {
     free_graphs(graphs);
     if (desc_dev) hipFree(desc_dev);
     if (ut.units) hipFree(ut.units);
+    if (ut.queue) hipFree(ut.queue);
 }
 
 extern "C" {
@@ -1139,15 +1145,20 @@ double time_steps(hipStream_t stream, int steps, Prep prep, Run run) {
     hipEvent_t a, b;
     hipEventCreate(&a);
     hipEventCreate(&b);
-    hipEventRecord(a, stream);
-    fvlbm_status st = run(steps);
-    hipEventRecord(b, stream);
-    hipEventSynchronize(b);
-    float ms = 0;
-    hipEventElapsedTime(&ms, a, b);
+    float best = -1;
+    fvlbm_status st = FVLBM_OK;
+    for (int rep = 0; rep < 2 && st == FVLBM_OK; rep++) {   // the faster of two runs
+        hipEventRecord(a, stream);
+        st = run(steps);
+        hipEventRecord(b, stream);
+        hipEventSynchronize(b);
+        float ms = 0;
+        hipEventElapsedTime(&ms, a, b);
+        if (best < 0 || ms < best) best = ms;
+    }
     hipEventDestroy(a);
     hipEventDestroy(b);
-    return st == FVLBM_OK ? ms / steps : -1;
+    return st == FVLBM_OK ? best / steps : -1;
 }
 
 // Tile sizes the autotuners try: the four powers of two, and the sizes that
@@ -1272,7 +1283,10 @@ void fvlbm_batch_destroy(fvlbm_batch *b) {
     free_graphs(b->graphs);
     if (b->desc_dev) hipFree(b->desc_dev);
     if (b->res_src) hipFree(b->res_src);
-    for (auto &u : b->ut) if (u.units) hipFree(u.units);
+    for (auto &u : b->ut) {
+        if (u.units) hipFree(u.units);
+        if (u.queue) hipFree(u.queue);
+    }
     std::vector<fvlbm_solver *> members = std::move(b->members);
     delete b;
     // members destroyed while the batch held them are freed now

@@ -161,6 +161,7 @@ struct Schedule {
 // Work units: (instance, tile index) per block; built for a schedule.
 struct UnitTable {
     int2 *units = nullptr;   // device; null when direct
+    unsigned *queue = nullptr;   // device, zeroed: the persistent form's work queue (ticket, workgroups done)
     int n_units = 0;
     int block = 0;
     bool direct = false;     // one instance: unit b is (0, b), the kernel needs no table
@@ -169,8 +170,8 @@ struct UnitTable {
 // Launch one RHS-evaluation stage over all units (one unit = one tile of
 // ut.block cells).  nf: 3 or 4; storage FVLBM_STORE_*; h2max, h1max: the
 // largest ring-2 and ring-1 slot counts over the launch's instances (LDS size).
-// persistent: 0 one workgroup per tile, 1 a resident-sized grid walking the
-// units, 2 one workgroup per tile with one more wave for the halo slots (used by
+// persistent: 0 one workgroup per tile, 1 a resident-sized grid taking the
+// units from a work queue, 2 one workgroup per tile with one more wave for the halo slots (used by
 // a single instance's mode-0 stages with tiles of 64 or 128 cells, else as 0).
 // mode0: the stage is a base + coef RHS update (descriptor mode 0: Euler, RK
 // stages), which runs a kernel compiled for it; other modes run one block per
@@ -187,7 +188,7 @@ size_t stage_lds_bytes(int T, int h2max, int h1max);
 // 64-cell halo-wave form).
 size_t stage_lds_limit();
 // Same as a kernel node for a graph.
-// argbuf: argbuf[0] holds a StageArgs, argbuf[1..14] receive the argument pointers.
+// argbuf: argbuf[0] holds a StageArgs, argbuf[1..15] receive the argument pointers.
 // (Kernel argument order: the first fourteen dwords, hidx .. ux, are preloaded.)
 struct StageArgs {
     const int *hidx;
@@ -200,6 +201,7 @@ struct StageArgs {
     const InstDesc *d;
     int nA;
     const int2 *u;
+    unsigned *queue;
     bool direct;
 };
 StageArgs stage_args(const InstDesc *descs_dev, const UnitTable &ut, int xcd_remap, int persistent, int h1max,

@@ -1226,7 +1226,7 @@ __global__ void __launch_bounds__(T ? tile_threads(T, STORE, RING) : 512) k_tile
                                             const float2 *hot_dxy, const float2 *hot_vxy, int hot_h12, int hot_np,
                                             int hot_n_cells, int units_x, const uint2 *hot_halo_code, const void *hot_base,
                                             const InstDesc *__restrict__ descs, int nA,
-                                            const int2 *__restrict__ units) {
+                                            const int2 *__restrict__ units, unsigned *) {
     extern __shared__ float4 lds4[];
     const int ub = remap_block(blockIdx.x, units_x >> 1, units_x & 1);
     const Hot hot{hot_src, hot_base, hot_halo_idx, hot_halo_code, hot_lnbr, hot_dxy, hot_vxy,
@@ -1238,22 +1238,81 @@ __global__ void __launch_bounds__(T ? tile_threads(T, STORE, RING) : 512) k_tile
                                              sa, lds4 + sa * RA);
 }
 
-// (units null: a single instance whose unit b is tile b.)
-// Persistent form: a grid sized to the resident capacity walks the unit list
-// (a multiple of 8 blocks, so each block stays on one XCD's range of tiles).
-template <int NF, int STORE, int T, bool M0>
-__global__ void __launch_bounds__(T ? T : 512) k_tile_persistent(const int *, const void *, const uint2 *, const float2 *,
-                                                       const float2 *, int, int, int, int units_x, const uint2 *,
-                                                       const void *, const InstDesc *__restrict__ descs, int nA,
-                                                       const int2 *__restrict__ units) {
+// Work queue of the persistent form: XCD x owns units [x n / 8, (x + 1) n / 8)
+// and a ticket counter of its own (one 128-byte line each, so the eight
+// counters' atomics proceed in parallel and an XCD's units, contiguous in the
+// cell order, share its L2), then a count of the workgroups that have left.
+constexpr int QUEUE_STRIDE = 32;                 // uints between counters
+constexpr int QUEUE_DONE = 8 * QUEUE_STRIDE;
+__device__ inline int queue_lo(int n, int x) { return (int)((long long)n * x / 8); }
+
+// The unit a ticket of XCD x's counter names, or -1 past the end of x's range.
+__device__ inline int queue_unit(int n, int x, unsigned t) {
+    const int lo = queue_lo(n, x), hi = queue_lo(n, x + 1);
+    return t < (unsigned)(hi - lo) ? lo + (int)t : -1;
+}
+
+// A unit from any XCD's range once x's own is used up, or n when every range is:
+// counters only grow, so one whose value is past its range is skipped without an
+// atomic.
+__device__ inline int queue_steal(unsigned *queue, int n, int x) {
+    for (int k = 1; k < 8; k++) {
+        const int y = (x + k) & 7;
+        const unsigned seen = __hip_atomic_load(queue + y * QUEUE_STRIDE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (queue_unit(n, y, seen) < 0) continue;
+        const int u = queue_unit(n, y, atomicAdd(queue + y * QUEUE_STRIDE, 1u));
+        if (u >= 0) return u;
+    }
+    return n;
+}
+
+// Persistent form: a grid sized to the resident capacity takes units from the
+// work queue above, so a workgroup starts its next unit as soon as it is done
+// with one, and fast workgroups take more units than slow ones.  The ticket for
+// the next unit is taken at the start of each unit and read at its end, so its
+// round trip overlaps the unit.  A ticket is handed out once, so every unit is
+// processed exactly once; every workgroup leaves once all ranges are used up,
+// and the last to leave clears the queue for the next launch (launches on one
+// queue never overlap: they are ordered on the solver's or batch's stream).
+// Mode-0 stages only.
+// DIRECT: a single instance (unit b is tile b) with its first-load values as
+// arguments; else units from the table (null: a single instance).
+template <int NF, int STORE, int T, bool DIRECT>
+__global__ void __launch_bounds__(T ? T : 512) __attribute__((amdgpu_waves_per_eu(NF == 3 ? 4 : 1)))
+k_tile_persistent(const int *hot_halo_idx, const void *hot_src, const uint2 *hot_lnbr, const float2 *hot_dxy,
+                  const float2 *hot_vxy, int hot_h12, int hot_np, int hot_n_cells, int units_x,
+                  const uint2 *hot_halo_code, const void *hot_base, const InstDesc *__restrict__ descs, int nA,
+                  const int2 *__restrict__ units, unsigned *queue) {
     extern __shared__ float4 lds4[];
-    const Hot hot{};
-    const int n_units = units_x >> 1, xcd_remap = units_x & 1;
-    for (int b = blockIdx.x; b < n_units; b += gridDim.x) {
-        const int ub = remap_block(b, n_units, xcd_remap);
-        tile_body<NF, STORE, T, false, M0, false>(descs, units ? units[ub] : make_int2(0, ub), hot, lds4, nA,
-                                                  lds4 + nA * RA);
+    __shared__ int next_unit;
+    const Hot hot{hot_src, hot_base, hot_halo_idx, hot_halo_code, hot_lnbr, hot_dxy, hot_vxy,
+                  hot_np, hot_n_cells, hot_h12 & 0xffff, hot_h12 >> 16};
+    const int n_units = units_x >> 1;
+    const int sa = DIRECT ? (T ? T : (int)blockDim.x) + (hot_h12 & 0xffff) : nA;
+    // the XCD this workgroup runs on (hardware register XCC_ID)
+    const int xcd = (int)(__builtin_amdgcn_s_getreg((15 << 11) | 20) & 7u);
+    unsigned *own = queue + xcd * QUEUE_STRIDE;
+    if (threadIdx.x == 0) {
+        const int u = queue_unit(n_units, xcd, atomicAdd(own, 1u));
+        next_unit = u >= 0 ? u : queue_steal(queue, n_units, xcd);
+    }
+    __syncthreads();
+    int b = next_unit;
+    while (b < n_units) {
+        unsigned ticket = 0;
+        if (threadIdx.x == 0) ticket = atomicAdd(own, 1u);
+        tile_body<NF, STORE, T, DIRECT, true, false>(descs, (DIRECT || !units) ? make_int2(0, b) : units[b], hot,
+                                                     lds4, sa, lds4 + sa * RA);
+        if (threadIdx.x == 0) {      // (every wave read the last value before this unit's barriers)
+            const int u = queue_unit(n_units, xcd, ticket);
+            next_unit = u >= 0 ? u : queue_steal(queue, n_units, xcd);
+        }
         __syncthreads();             // the next unit reuses the LDS records
+        b = next_unit;
+    }
+    if (threadIdx.x == 0 && atomicAdd(queue + QUEUE_DONE, 1u) == gridDim.x - 1) {
+        for (int x = 0; x < 8; x++) atomicExch(queue + x * QUEUE_STRIDE, 0u);
+        atomicExch(queue + QUEUE_DONE, 0u);
     }
 }
 
@@ -1262,7 +1321,9 @@ const void *fn(bool persistent, bool direct, bool m0, bool ring) {
     if (!m0)    // runtime mode: one block per unit (the launchers never ask for persistence here)
         return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, false, false>)
                       : reinterpret_cast<const void *>(&k_tile<NF, STORE, T, false, false, false>);
-    if (persistent) return reinterpret_cast<const void *>(&k_tile_persistent<NF, STORE, T, true>);
+    if (persistent)
+        return direct ? reinterpret_cast<const void *>(&k_tile_persistent<NF, STORE, T, true>)
+                      : reinterpret_cast<const void *>(&k_tile_persistent<NF, STORE, T, false>);
     if constexpr (T != 0 && T <= 128)   // a ring wave: single instance, mode 0, tiles of 64 or 128 cells
         if (ring && direct) return reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, true, true>);
     return direct ? reinterpret_cast<const void *>(&k_tile<NF, STORE, T, true, true, false>)
@@ -1295,10 +1356,10 @@ const void *pick(int nf, int storage, int T, bool persistent, bool direct, bool 
 
 // Grid of a launch: one block per unit, or (persistent) the number of blocks
 // the device holds at once, rounded down to a multiple of 8 (one per XCD).
-int grid_blocks(const UnitTable &ut, int persistent, int nf, int storage, size_t lds) {
+int grid_blocks(const UnitTable &ut, int persistent, int nf, int storage, size_t lds, bool direct) {
     if (!persistent) return ut.n_units;
     int per_cu = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick(nf, storage, ut.block, true, false, true, false), ut.block, lds);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick(nf, storage, ut.block, true, direct, true, false), ut.block, lds);
     int dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1316,7 +1377,8 @@ StageArgs stage_args(const InstDesc *descs_dev, const UnitTable &ut, int xcd_rem
     a.ux = 2 * ut.n_units + (xcd_remap ? 1 : 0);
     a.nA = ut.block + h1max;
     // (a single-instance launch sizes region A from its own ring-1 slot count)
-    a.direct = ut.direct && host_desc && !persistent && a.nA == ut.block + host_desc->h1s;
+    a.queue = ut.queue;
+    a.direct = ut.direct && host_desc && a.nA == ut.block + host_desc->h1s;
     if (a.direct) {
         a.src = host_desc->src;
         a.base = host_desc->base;
@@ -1355,21 +1417,21 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
     StageArgs a = stage_args(descs_dev, ut, xcd_remap, persistent, h1max, host_desc);
     const bool ring = ring_form && mode0 && a.direct && ut.block <= 128;
     void *args[] = {&a.hidx, &a.src, &a.lnbr, &a.dxy, &a.vxy, &a.h12, &a.np, &a.nc, &a.ux, &a.hcode, &a.base,
-                    &a.d, &a.nA, &a.u};
+                    &a.d, &a.nA, &a.u, &a.queue};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
     const void *fn_ptr = pick(nf, storage, ut.block, persistent, a.direct, mode0, ring);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn_ptr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    return hipLaunchKernel(fn_ptr, dim3(grid_blocks(ut, persistent, nf, storage, lds)), dim3(tile_threads(ut.block, storage, ring)),
+    return hipLaunchKernel(fn_ptr, dim3(grid_blocks(ut, persistent, nf, storage, lds, a.direct)), dim3(tile_threads(ut.block, storage, ring)),
                            args, lds, stream);
 }
 
 namespace {
 // Kernel-node parameters of one stage launch (as launch_stage() would launch it).
 // argbuf: caller-owned storage (a StageArgs block in argbuf[0], then one pointer per
-// argument), alive until the node is added or set.
+// argument: argbuf[1..15]), alive until the node is added or set.
 hipError_t stage_node_params(hipKernelNodeParams *p, const InstDesc *descs_dev, const UnitTable &ut, int nf,
                              int storage, int xcd_remap, int persistent, int h2max, int h1max, bool mode0,
                              void **argbuf, const InstDesc *host_desc) {
@@ -1381,7 +1443,7 @@ hipError_t stage_node_params(hipKernelNodeParams *p, const InstDesc *descs_dev, 
     void **kp = argbuf + 1;
     kp[0] = &a->hidx; kp[1] = &a->src; kp[2] = &a->lnbr; kp[3] = &a->dxy; kp[4] = &a->vxy; kp[5] = &a->h12;
     kp[6] = &a->np; kp[7] = &a->nc; kp[8] = &a->ux; kp[9] = &a->hcode; kp[10] = &a->base; kp[11] = &a->d;
-    kp[12] = &a->nA; kp[13] = &a->u;
+    kp[12] = &a->nA; kp[13] = &a->u; kp[14] = &a->queue;
     *p = hipKernelNodeParams{};
     const size_t lds = stage_lds_bytes(ut.block, h2max, h1max);
     p->func = const_cast<void *>(pick(nf, storage, ut.block, persistent, a->direct, mode0, ring));
@@ -1389,7 +1451,7 @@ hipError_t stage_node_params(hipKernelNodeParams *p, const InstDesc *descs_dev, 
         hipError_t e = hipFuncSetAttribute(p->func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    p->gridDim = dim3(grid_blocks(ut, persistent, nf, storage, lds));
+    p->gridDim = dim3(grid_blocks(ut, persistent, nf, storage, lds, a->direct));
     p->blockDim = dim3(tile_threads(ut.block, storage, ring));
     p->sharedMemBytes = (unsigned)lds;
     p->kernelParams = kp;

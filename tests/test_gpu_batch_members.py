@@ -41,8 +41,8 @@ def _pairs(F, storage, lag=None):
     return alone, mixed
 
 
-@pytest.mark.parametrize("storage", ["fp32dev", "fp16dev"])
-def test_members_change_in_place_bitwise(F, storage):
+@pytest.mark.parametrize("storage,persistent", [("fp32dev", False), ("fp16dev", False), ("fp32dev", True)])
+def test_members_change_in_place_bitwise(F, storage, persistent):
     alone, mixed = _pairs(F, storage)
     S = [s for _, s in mixed]
     steps = [0] * len(S)
@@ -56,6 +56,7 @@ def test_members_change_in_place_bitwise(F, storage):
     for members, n in plan:
         if b is None:
             b = F.Batch([S[i] for i in members])
+            b.set_schedule(128, True, persistent)      # (work-queue form: one queue per cell kind)
         else:
             b.set_members([S[i] for i in members])
         repointed.append(b.graph_counts()["repointed"])

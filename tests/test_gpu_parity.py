@@ -319,6 +319,32 @@ def test_schedules_do_not_change_results(F, scheme):
         assert np.array_equal(outs[0], o)
 
 
+@pytest.mark.parametrize("storage", ["fp32dev", "fp16dev"])
+def test_work_queue_form_is_bitwise_the_plain_form(F, storage):
+    # launch form 1 takes tiles from per-XCD work queues.  Every launch must leave
+    # its queue cleared (hundreds of launches here), and a mesh with fewer tiles
+    # than XCDs leaves some XCD ranges empty, whose workgroups take tiles from the
+    # other ranges.
+    meshes = [mg.cavity(n=10, jitter=0.2, seed=40),          # 200 cells: 4 tiles of 64, 1 of 512
+              mg.cavity(n=40, jitter=0.2, seed=41),
+              mg.cylinder(nr=24, nt=36, R=8.0, h0=0.02),     # quadrilaterals
+              mg.hybrid(12)]
+    for m in meshes:
+        mesh = F.Mesh(m)
+        for scheme in ("euler", "rk4"):
+            outs = []
+            for block, p in [(64, 0), (64, 1), (128, 1), (256, 1), (512, 1), (192, 1)]:
+                s = F.Solver(mesh, F.make_params(tau=3e-3, scheme=scheme, storage=storage, u_ref=0.2))
+                s.set_schedule(block, True, p)
+                assert s.get_schedule()["persistent"] == p
+                s.step(70)
+                outs.append(s.f)
+                s.close()
+            assert np.all(np.isfinite(outs[0]))
+            for o in outs[1:]:
+                assert np.array_equal(outs[0], o), (m.n_cells, scheme)
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp32dev", "fp16dev", "i16dev"])
 @pytest.mark.parametrize("scheme", ["euler", "rk4"])
 def test_ring_wave_form_is_bitwise_the_plain_form(F, scheme, storage):
