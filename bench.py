@@ -60,11 +60,12 @@ def alg_bytes_per_update(nf: int, scheme: str, storage: str) -> float:
     return STATE_VALUES[scheme] * STORE_BYTES[storage] + CARRY_BYTES.get(storage, 0.0) + n_rhs * MESH_BYTES[nf]
 
 
-def measured_traffic(workload, schedule):
+def measured_traffic(workload, schedule, leg=None):
     """HBM bytes per launch of the stage kernel from the committed counter runs
     (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain copy of
     known size), or None when the kernel sources changed since they were taken
-    or the timed schedule is not one they were taken with."""
+    or the timed schedule is not one they were taken with.  leg: the scheme and
+    storage, where one workload's record covers several."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_tile_traffic_{workload}.json")
     if not os.path.exists(path):
@@ -76,6 +77,8 @@ def measured_traffic(workload, schedule):
     if h.hexdigest() != rec["source_sha256"]:
         return None
     key = "%d,%d,%d" % (schedule["block"], int(schedule["xcd_remap"]), int(schedule["persistent"]))
+    if leg:
+        key = leg + ":" + key
     ent = rec["per_schedule"].get(key)
     return ent["bytes_per_launch"] if ent else None
 
@@ -132,27 +135,34 @@ def make_solver(F, inst, scheme, storage, reorder=None):
     return mesh, s
 
 
-def streaming(F, W, stream, schedule=None):
+STREAMING_LEGS = (("euler", "fp32dev", 20), ("rk4", "fp32dev", 5), ("rk4", "i16dev", 5))
+
+
+def streaming(F, W, stream, schedule=None, legs=None):
     out = {}
     m = W.streaming()
     mesh = F.Mesh(m, reorder=F.REORDER_BISECT)
     nf = mesh.info()["nf"]
-    for scheme, storage, k in (("euler", "fp32dev", 20), ("rk4", "fp32dev", 5), ("rk4", "i16dev", 5)):
+    for scheme, storage, k in STREAMING_LEGS:
+        leg = f"{scheme}_{storage}"
+        if legs and leg not in legs:
+            continue
         s = F.Solver(mesh, F.make_params(tau=3e-5, scheme=scheme, storage=storage))
         if schedule:
             s.set_schedule(*schedule)
             s.step(2)
         else:
-            s.autotune(4)
+            s.autotune(k)
         s.step(k)                                      # warm (graphs built, caches in steady state)
         el = sorted(events_time(stream, lambda: s.step(k)) for _ in range(3))[1]   # median of three runs
         n_launch = k * (4 if scheme == "rk4" else 1)
         t_launch = el / n_launch
         alg = alg_bytes_per_update(nf, scheme, storage) / (4 if scheme == "rk4" else 1) * m.n_cells
-        out[f"{scheme}_{storage}"] = dict(cells=m.n_cells, steps=k,
-                                          M_cell_updates_per_s=round(m.n_cells * k / el / 1e6, 1),
-                                          launch_ms=round(t_launch * 1e3, 4), achieved_GBs=round(alg / t_launch / 1e9, 1),
-                                          frac=round(alg / t_launch / 1e9 / HBM_PEAK_GBS, 4), schedule=s.get_schedule())
+        sched = s.get_schedule()
+        out[leg] = dict(cells=m.n_cells, steps=k, M_cell_updates_per_s=round(m.n_cells * k / el / 1e6, 1),
+                        launch_ms=round(t_launch * 1e3, 4), achieved_GBs=round(alg / t_launch / 1e9, 1),
+                        frac=round(alg / t_launch / 1e9 / HBM_PEAK_GBS, 4), alg_bytes_per_launch=alg,
+                        traffic=measured_traffic("streaming8m", sched, leg), schedule=sched)
         s.close()
     mesh.close()
     return out
@@ -328,6 +338,7 @@ def main():
     ap.add_argument("--schedule", default="", help="force a launch schedule 'block,xcd,persistent' instead of tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--legs", default="", help="streaming legs to run, e.g. 'rk4_fp32dev' (default: all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
@@ -383,7 +394,7 @@ def main():
         el = events_time(stream, lambda: [dst.copy_(src) for _ in range(5)])
         rec["copy"] = dict(bytes_each_way=4 * n, launches=5, GBs=round(2 * 4 * n * 5 / el / 1e9, 1))
     if args.only in ("all", "streaming"):
-        rec["streaming"] = streaming(F, W, stream, schedule)
+        rec["streaming"] = streaming(F, W, stream, schedule, [x for x in args.legs.split(",") if x])
     if args.only in ("all", "batched"):
         rec["batched"] = batched(F, W, stream)
     if args.only in ("all", "precision"):
