@@ -88,7 +88,6 @@ class GpuBackend:
         self.prep = torch.cuda.Stream()
         self._batch = None
         self._members = None
-        self._freed = set()
         self.batch_builds = 0           # batches created
         self.member_changes = 0         # membership changes applied to the running batch in place
         self.graphs_built = self.graphs_repointed = 0   # of closed batches (see graph_counts)
@@ -164,7 +163,6 @@ class GpuBackend:
                 except F.FvlbmError:
                     pass                 # this mix's tiles do not fit that schedule: keep the default
         self._members = members
-        self._freed = set()
         if self.schedule is None and self.autotune and len(members) >= self.tune_members:
             self._batch.autotune(16)
             self.schedule = self._batch.get_schedule()
@@ -189,18 +187,16 @@ class GpuBackend:
 
     def free(self, handle):
         """Release a request's solver and mesh.  While the running batch still holds the
-        solver, the library frees it when the batch next changes members (or is closed,
-        once every member has been freed)."""
+        solver, the library frees it when the batch next changes members or is closed.
+        A batch whose members have all finished is kept, graphs and all, for the next
+        requests (it is not stepped until then)."""
         t0 = time.perf_counter()
-        if self._members is not None and any(handle[1] is m for m in self._members):
-            self._freed.add(id(handle[1]))
-            if len(self._freed) == len(self._members):
-                self.close()
         handle[1].close()
         handle[0].close()
         self.t_free += time.perf_counter() - t0
 
     def close(self):
+        """Destroy the running batch (and with it the solvers of finished requests it holds)."""
         if self._batch is not None:
             counts = self._batch.graph_counts()
             self.graphs_built += counts["built"]
@@ -339,6 +335,8 @@ class Server:
         finally:
             if self._pool is not None:
                 self._pool.shutdown(wait=True)
+            if hasattr(self.backend, "close"):
+                self.backend.close()
         self.wall = clock() - t0
         return self.results
 
