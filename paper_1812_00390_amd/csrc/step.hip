@@ -1359,10 +1359,13 @@ const void *pick(int nf, int storage, int T, bool persistent, bool direct, bool 
 int grid_blocks(const UnitTable &ut, int persistent, int nf, int storage, size_t lds, bool direct) {
     if (!persistent) return ut.n_units;
     int per_cu = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick(nf, storage, ut.block, true, direct, true, false), ut.block, lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick(nf, storage, ut.block, true, direct, true, false),
+                                                     ut.block, lds) != hipSuccess)
+        per_cu = 1;
     int dev = 0, cus = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
     int g = std::max(8, (per_cu > 0 ? per_cu : 1) * cus / 8 * 8);
     return std::min(g, (ut.n_units + 7) / 8 * 8);
 }
