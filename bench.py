@@ -297,10 +297,14 @@ def batched(F, W, stream, steps=1000, single_steps=100):
     return rec
 
 
-def single_workload(F, stream, inst, label, traffic_key, args, schedule):
+ORDERS = {"bisect": 3, "hilbert": 2}
+
+
+def single_workload(F, stream, inst, label, traffic_key, args, schedule, order="bisect"):
     """One solver stepped `args.steps` four-stage RK steps (graphs instantiated
-    beforehand), timed with HIP events on its stream."""
-    mesh, s = make_solver(F, inst, "rk4", args.storage)
+    beforehand), timed with HIP events on its stream.  order: the mesh's cell
+    order (tiles are runs of consecutive cells)."""
+    mesh, s = make_solver(F, inst, "rk4", args.storage, reorder=ORDERS[order])
     nf = mesh.info()["nf"]
     if schedule:
         s.set_schedule(*schedule)
@@ -316,10 +320,10 @@ def single_workload(F, stream, inst, label, traffic_key, args, schedule):
     sched = s.get_schedule()
     out = dict(value=round(n * args.steps / el / 1e6, 3), ms_per_step=round(el * 1e3 / args.steps, 5),
                config={"workload": label, "cells": n, "scheme": "rk4", "storage": args.storage, "dt": s.dt,
-                       "schedule": sched},
+                       "cell_order": order, "schedule": sched},
                roofline={"bound": "hbm", "achieved": round(alg_launch / t_launch / 1e9, 2), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(alg_launch / t_launch / 1e9 / HBM_PEAK_GBS, 4),
-                         "traffic": measured_traffic(traffic_key, sched) if args.storage == "fp32dev" else None,
+                         "traffic": measured_traffic(traffic_key, sched, order) if args.storage == "fp32dev" else None,
                          "kernel": f"k_tile<{nf},...> (one RK stage)",
                          "alg_bytes_per_launch": alg_launch, "launch_us": round(t_launch * 1e6, 3)},
                check={"max_u": float(np.abs(u).max()), "mass": st["mass"]})
@@ -339,6 +343,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--legs", default="", help="streaming legs to run, e.g. 'rk4_fp32dev' (default: all)")
+    ap.add_argument("--reorder", choices=sorted(ORDERS), default="hilbert",
+                    help="cell order of the headline mesh (Hilbert: the faster on the cylinder O-grid)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
@@ -360,7 +366,7 @@ def main():
         inst = W.cylinder98k()
         label = ("flow past a circular cylinder Re=100 u_inf=0.1, O-grid 256x384 quads (98304 cells, "
                  "first cell 0.005 D, far field 30 D), four-stage RK, CFL 0.5, deviations from the free stream")
-        h = single_workload(F, stream, inst, label, "cylinder98k", args, schedule)
+        h = single_workload(F, stream, inst, label, "cylinder98k", args, schedule, args.reorder)
         rec.update({
             "metric": "M cell-updates/s (D2Q9, FP32)",
             "value": h["value"],

@@ -118,7 +118,8 @@ def _run_pair(F, O, m, tau, scheme, steps, storage="fp32dev", cfl=0.5, u_ref=0.1
 BENCH_SCHEDULE = (64, True, 2)
 # ... and on the 98,304-quad cylinder (the headline): 384-cell tiles (one per CU,
 # a tile size set at launch), XCD remap, one workgroup per tile.
-HEADLINE_SCHEDULE = (384, True, 0)
+HEADLINE_SCHEDULE = (128, True, 2)
+HEADLINE_ORDER = 2           # Hilbert: the benchmark's cell order for the cylinder
 
 # FP16 deviations (each cell's nine values rounded together so that its mass
 # and momentum keep their value, the rounding residual carried to the next
@@ -445,11 +446,12 @@ def test_cavity_cfg2_full_run_vs_stored_oracle(F, schedule):
         assert np.abs(rho[idx] - ref["rho"]).max() <= utol * 0.1
 
 
-@pytest.mark.parametrize("schedule", [None, BENCH_SCHEDULE, HEADLINE_SCHEDULE, (512, True, 0), (128, False, 1)])
-def test_cylinder_cfg3_full_size_vs_stored_oracle(F, schedule):
+@pytest.mark.parametrize("schedule,order", [(None, 3), (BENCH_SCHEDULE, 3), ((384, True, 0), 3), ((512, True, 0), 3),
+                                            ((128, False, 1), 3), (HEADLINE_SCHEDULE, HEADLINE_ORDER), (None, 2)])
+def test_cylinder_cfg3_full_size_vs_stored_oracle(F, schedule, order):
     ref = np.load(os.path.join(GOLDEN, "oracle_cylinder256_rk4_100.npz"))
     m = mg.cylinder(nr=256, nt=384)
-    mesh = F.Mesh(m)
+    mesh = F.Mesh(m, reorder=order)
     for storage, utol in (("fp32", 1e-5), ("fp32dev", 1e-5), ("fp16dev", FP16_UTOL), ("i16dev", I16_UTOL)):
         s = F.Solver(mesh, F.make_params(tau=float(ref["tau"]), dt=float(ref["dt"]), scheme="rk4",
                                          storage=storage, u_ref=0.2, u_dev=(0.1, 0.0)),
@@ -464,15 +466,15 @@ def test_cylinder_cfg3_full_size_vs_stored_oracle(F, schedule):
         assert err <= utol * 0.1
 
 
-@pytest.mark.parametrize("schedule", [None, HEADLINE_SCHEDULE])
-def test_cylinder_cfg3_full_run_vs_stored_oracle(F, schedule):
+@pytest.mark.parametrize("schedule,order", [(None, 3), ((384, True, 0), 3), (HEADLINE_SCHEDULE, HEADLINE_ORDER)])
+def test_cylinder_cfg3_full_run_vs_stored_oracle(F, schedule, order):
     # the full start-up run of the cylinder case: 20,000 four-stage RK steps
     path = os.path.join(GOLDEN, "oracle_cylinder256_rk4_20000.npz")
     if not os.path.exists(path):
         pytest.skip("stored oracle run not generated (tests/golden/make_oracle_refs.py)")
     ref = np.load(path)
     m = mg.cylinder(nr=256, nt=384)
-    mesh = F.Mesh(m)
+    mesh = F.Mesh(m, reorder=order)
     errs = {}
     for storage, utol in (("fp32", 1e-5), ("fp32dev", 1e-5), ("fp16dev", FP16_UTOL), ("i16dev", I16_UTOL)):
         s = F.Solver(mesh, F.make_params(tau=float(ref["tau"]), dt=float(ref["dt"]), scheme="rk4",
