@@ -128,7 +128,7 @@ def cpu_baseline(inst, label, scheme="rk4", target_s=10.0):
 
 
 def make_solver(F, inst, scheme, storage, reorder=None):
-    mesh = F.Mesh(inst.mesh, reorder=F.REORDER_BISECT if reorder is None else reorder)
+    mesh = F.Mesh(inst.mesh, reorder=inst.order if reorder is None else reorder)
     s = F.Solver(mesh, F.make_params(tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme=scheme,
                                      storage=storage, u_dev=inst.u0),
                  u=np.tile(np.asarray(inst.u0, float), (inst.n_cells, 1)))
@@ -298,12 +298,14 @@ def batched(F, W, stream, steps=1000, single_steps=100):
 
 
 ORDERS = {"bisect": 3, "hilbert": 2}
+ORDER_NAMES = {v: k for k, v in ORDERS.items()}
 
 
-def single_workload(F, stream, inst, label, traffic_key, args, schedule, order="bisect"):
+def single_workload(F, stream, inst, label, traffic_key, args, schedule, order=None):
     """One solver stepped `args.steps` four-stage RK steps (graphs instantiated
     beforehand), timed with HIP events on its stream.  order: the mesh's cell
-    order (tiles are runs of consecutive cells)."""
+    order (tiles are runs of consecutive cells; default: the instance's)."""
+    order = order or ORDER_NAMES[inst.order]
     mesh, s = make_solver(F, inst, "rk4", args.storage, reorder=ORDERS[order])
     nf = mesh.info()["nf"]
     if schedule:
@@ -343,8 +345,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--legs", default="", help="streaming legs to run, e.g. 'rk4_fp32dev' (default: all)")
-    ap.add_argument("--reorder", choices=sorted(ORDERS), default="hilbert",
-                    help="cell order of the headline mesh (Hilbert: the faster on the cylinder O-grid)")
+    ap.add_argument("--reorder", choices=sorted(ORDERS), default=None,
+                    help="cell order of the headline mesh (default: the workload's, Hilbert for the cylinder O-grid)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "

@@ -112,7 +112,7 @@ class GpuBackend:
         the serving schedule are built here too.  Runs on a worker thread."""
         F, torch = self.F, self.torch
         torch.cuda.set_device(0)
-        mesh = F.Mesh(inst.mesh, reorder=F.REORDER_BISECT, stream=self.prep)
+        mesh = F.Mesh(inst.mesh, reorder=inst.order, stream=self.prep)
         p = F.make_params(tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme=self.scheme, storage=self.storage,
                           u_dev=inst.u0, residual_lag=self.chunk)
         s = F.Solver(mesh, p, u=np.tile(np.asarray(inst.u0, float), (inst.n_cells, 1)), stream=self.prep)
@@ -444,7 +444,7 @@ def main():
             t = 0.0
             for q in calib[:args.single]:
                 inst = q.inst
-                mesh = F.Mesh(inst.mesh, reorder=F.REORDER_BISECT)
+                mesh = F.Mesh(inst.mesh, reorder=inst.order)
                 s = F.Solver(mesh, F.make_params(tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme="rk4", storage="fp32dev",
                                                  u_dev=inst.u0), u=np.tile(np.asarray(inst.u0, float), (inst.n_cells, 1)))
                 s.step(8)

@@ -32,7 +32,7 @@ def test_served_equals_alone_bitwise(F):
     # membership changed while requests ran: more requests than slots
     assert srv.used == 0
     for k, inst in enumerate(insts):
-        mesh = F.Mesh(inst.mesh, reorder=F.REORDER_BISECT)
+        mesh = F.Mesh(inst.mesh, reorder=inst.order)
         p = F.make_params(tau=inst.tau, cfl=0.5, u_ref=inst.u_ref, scheme="rk4", storage=backend.storage,
                           u_dev=inst.u0, residual_lag=chunk)
         s = F.Solver(mesh, p, u=np.tile(np.asarray(inst.u0, float), (inst.n_cells, 1)))
