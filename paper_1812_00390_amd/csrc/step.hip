@@ -513,10 +513,20 @@ __device__ inline int unpack16(uint32_t w, int hi) { return (int)(int16_t)(hi ? 
 constexpr bool split_form(int T, int STORE, bool RING) {
     return RING && T == 64 && STORE != FVLBM_STORE_I16_DEV && STORE != FVLBM_STORE_FP16_DEV;
 }
-// Threads per workgroup of a stage kernel: the tile's cells, a wave for the halo
-// slots (RING), two waves for directions 5-8 of the gradients (split form).
-constexpr int tile_threads(int T, int STORE, bool RING) {
-    return T + (RING ? 64 : 0) + (split_form(T, STORE, RING) ? 128 : 0);
+// Threads per workgroup of a stage kernel: the tile's cells, one or two waves for
+// the halo slots (RING; two when the larger ring holds more than 64 slots, one in
+// the split form), two waves for directions 5-8 of the gradients (split form).
+constexpr int tile_threads(int T, int STORE, bool RING, int waves = 1) {
+    return T + (RING ? 64 * (split_form(T, STORE, RING) ? 1 : waves) : 0) + (split_form(T, STORE, RING) ? 128 : 0);
+}
+// (A third and fourth wave for rings above 128 slots measured slower: the rare
+// tiles with such rings set the block size of the whole launch.)
+constexpr int MAX_HALO_WAVES = 2;
+// Halo waves of a RING launch whose larger ring holds hmax slots.
+inline int halo_waves(int hmax) { return std::min(MAX_HALO_WAVES, std::max(1, (hmax + 63) / 64)); }
+// The largest block a stage kernel is launched with.
+constexpr int max_tile_threads(int T, int STORE, bool RING) {
+    return T ? tile_threads(T, STORE, RING, MAX_HALO_WAVES) : 512;
 }
 
 // v[k] from registers by selects (no dynamic register indexing; k may differ
@@ -931,9 +941,9 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     const int tile = u.y;
     const int tid = threadIdx.x;
     // RING: threads [0, T) own the tile's cells and one more wave, [T, T + 64),
-    // owns the halo slots, so halo loads and ring-1 gradients run beside the
-    // tile's own; otherwise thread t owns tile cell t and halo slot t.
-    const int RS = RING ? 64 : T;                     // halo slots per pass
+    // owns the halo slots (outside the split form two waves when the larger ring
+    // holds more than 64 slots), so halo loads and ring-1 gradients run
+    // beside the tile's own; otherwise thread t owns tile cell t and halo slot t.
     // With 64-cell tiles (SPLIT3) two more waves form directions 5-8 of the
     // phase-2 gradients, one for the tile's cells (thread T + 64 + l: cell l), one
     // for the ring-1 slots (thread T + 128 + s: slot s), the tile and halo waves
@@ -942,6 +952,8 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // Opposite directions share a set, so every value is the one the whole pass
     // forms.
     constexpr bool SPLIT3 = split_form(TC, STORE, RING);
+    // halo slots per pass: the halo waves' lanes (RING), else the tile's threads
+    const int RS = RING ? (SPLIT3 ? 64 : (int)blockDim.x - T) : T;
     constexpr int GA = SPLIT3 ? 0 : -1;               // gradient half of the tile and halo waves
     // SPLIT3: phi_k - h of the tile cells' boundary slots, formed in phase 2 by
     // the tile's two waves (each its half of the directions), staged for the
@@ -1025,7 +1037,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     // the instance's boundary groups, staged in LDS for the boundary slots (read
     // whole, without waiting for the group count)
     __shared__ GroupDev lg[MAX_GROUPS];
-    const int BS = TC ? tile_threads(TC, STORE, RING) : T;   // threads per block
+    const int BS = (int)blockDim.x;                   // threads per block
     constexpr int GW = MAX_GROUPS * (int)(sizeof(GroupDev) / sizeof(int));
     const int *gsrc = reinterpret_cast<const int *>(d.groups);
     const int gv0 = ldg(gsrc, tid < GW ? tid : 0);
@@ -1222,7 +1234,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
 // (Arguments in the order the kernel needs them: the first sixteen dwords arrive in
 // scalar registers.)
 template <int NF, int STORE, int T, bool DIRECT, bool M0, bool RING>
-__global__ void __launch_bounds__(T ? tile_threads(T, STORE, RING) : 512) k_tile(const int *hot_halo_idx, const void *hot_src, const uint2 *hot_lnbr,
+__global__ void __launch_bounds__(max_tile_threads(T, STORE, RING)) k_tile(const int *hot_halo_idx, const void *hot_src, const uint2 *hot_lnbr,
                                             const float2 *hot_dxy, const float2 *hot_vxy, int hot_h12, int hot_np,
                                             int hot_n_cells, int units_x, const uint2 *hot_halo_code, const void *hot_base,
                                             const InstDesc *__restrict__ descs, int nA,
@@ -1427,7 +1439,8 @@ hipError_t launch_stage(const InstDesc *descs_dev, const UnitTable &ut, int nf, 
         hipError_t e = hipFuncSetAttribute(fn_ptr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    return hipLaunchKernel(fn_ptr, dim3(grid_blocks(ut, persistent, nf, storage, lds, a.direct)), dim3(tile_threads(ut.block, storage, ring)),
+    return hipLaunchKernel(fn_ptr, dim3(grid_blocks(ut, persistent, nf, storage, lds, a.direct)),
+                           dim3(tile_threads(ut.block, storage, ring, halo_waves(std::max(h1max, h2max)))),
                            args, lds, stream);
 }
 
@@ -1455,7 +1468,7 @@ hipError_t stage_node_params(hipKernelNodeParams *p, const InstDesc *descs_dev, 
         if (e != hipSuccess) return e;
     }
     p->gridDim = dim3(grid_blocks(ut, persistent, nf, storage, lds, a->direct));
-    p->blockDim = dim3(tile_threads(ut.block, storage, ring));
+    p->blockDim = dim3(tile_threads(ut.block, storage, ring, halo_waves(std::max(h1max, h2max))));
     p->sharedMemBytes = (unsigned)lds;
     p->kernelParams = kp;
     p->extra = nullptr;

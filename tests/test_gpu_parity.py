@@ -352,9 +352,13 @@ def test_ring_wave_form_is_bitwise_the_plain_form(F, scheme, storage):
     # launch form 2 (a wave for the halo slots) against one workgroup per tile:
     # a natural-order mesh (halo rings wider than one 64-slot pass), a channel
     # with inlet, outlet and symmetry groups, and quads
+    # (rings above 64 slots take two halo waves: the natural order and the O-grid
+    # in both orders)
     meshes = [(mg.cavity(n=30, jitter=0.2, seed=21), F.REORDER_NONE),
               (mg.channel(26, 10, jitter=0.2, seed=22, tri=True, top="symmetry"), F.REORDER_BISECT),
-              (mg.cavity(n=12, jitter=0.1, seed=23, tri=False), F.REORDER_BISECT)]
+              (mg.cavity(n=12, jitter=0.1, seed=23, tri=False), F.REORDER_BISECT),
+              (mg.cylinder(nr=96, nt=128, R=10.0, h0=0.01), F.REORDER_HILBERT),
+              (mg.cylinder(nr=96, nt=128, R=10.0, h0=0.01), F.REORDER_BISECT)]
     for m, reorder in meshes:
         mesh = F.Mesh(m, reorder=reorder)
         outs = []
