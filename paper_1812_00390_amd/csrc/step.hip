@@ -25,6 +25,8 @@
 // go through one rolled loop per phase, which keeps the kernel small.
 #include "fvlbm_internal.h"
 
+#include <type_traits>
+
 // No implicit contraction: every fused multiply-add below is written as fmaf,
 // so every kernel variant (tile size, persistent or not, batched or not)
 // performs the same roundings and results are bitwise independent of the
@@ -61,9 +63,25 @@ template <class T>
 __device__ inline T ldo(const void *base, uint32_t off) {
     return *(const FVLBM_GLOBAL_AS T *)((const FVLBM_GLOBAL_AS char *)base + off);
 }
+// Stores of the new state (and of the other per-cell outputs) are non-temporal:
+// nothing reads them again in the same launch, so their lines should not
+// displace from L2 the halo values that neighbouring tiles read again.
 template <class T>
 __device__ inline void sto(void *base, uint32_t off, T v) {
-    *(FVLBM_GLOBAL_AS T *)((FVLBM_GLOBAL_AS char *)base + off) = v;
+    FVLBM_GLOBAL_AS char *p = (FVLBM_GLOBAL_AS char *)base + off;
+    if constexpr (std::is_same<T, __half>::value)
+        __builtin_nontemporal_store(__half_as_ushort(v), (FVLBM_GLOBAL_AS unsigned short *)p);
+    else
+        __builtin_nontemporal_store(v, (FVLBM_GLOBAL_AS T *)p);
+}
+// A non-temporal load of two dwords, for the mesh data a launch reads once (a
+// cell's corner offsets and neighbour codes; the stencil offsets are read again
+// as ring-1 geometry of the neighbouring tiles and stay ordinary loads).
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef unsigned uint2v __attribute__((ext_vector_type(2)));
+template <class V>
+__device__ inline V ldn(const void *base, uint32_t off) {
+    return __builtin_nontemporal_load((const FVLBM_GLOBAL_AS V *)((const FVLBM_GLOBAL_AS char *)base + off));
 }
 __device__ inline const void *plane(const void *p, size_t plane_bytes, int a) {
     return static_cast<const char *>(p) + plane_bytes * (size_t)a;
@@ -581,7 +599,10 @@ struct CellFaces {
     __device__ void load(const float2 *vxy, size_t np, int c) {
         const uint32_t o8 = (uint32_t)c * 8u;
 #pragma unroll
-        for (int k = 0; k < (NF == 3 ? 2 : NF); k++) v[k] = ldo<float2>(plane(vxy, np * 8, k), o8);
+        for (int k = 0; k < (NF == 3 ? 2 : NF); k++) {
+            const float2v t = ldn<float2v>(plane(vxy, np * 8, k), o8);
+            v[k] = make_float2(t.x, t.y);
+        }
     }
     __device__ void finish() {
         if (NF == 3) v[2] = make_float2(-(v[0].x + v[1].x), -(v[0].y + v[1].y));
@@ -1001,7 +1022,8 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     const int ic = valid ? i : 0;
     if (ownw) {
         load_cell<STORE>(src, np, ic, f, d.ref);
-        ln = ldo<uint2>(lnbr, (uint32_t)ic * 8u);
+        const uint2v t = ldn<uint2v>(lnbr, (uint32_t)ic * 8u);
+        ln = make_uint2(t.x, t.y);
         geo.load(dxy, np, ic);
         cf.load(vxy, np, ic);
     }
