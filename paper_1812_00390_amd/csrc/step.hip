@@ -74,15 +74,17 @@ __device__ inline void sto(void *base, uint32_t off, T v) {
     else
         __builtin_nontemporal_store(v, (FVLBM_GLOBAL_AS T *)p);
 }
-// A non-temporal load of two dwords, for the mesh data a launch reads once (a
-// cell's corner offsets and neighbour codes; the stencil offsets are read again
-// as ring-1 geometry of the neighbouring tiles and stay ordinary loads).
+// Non-temporal loads, for the data a launch reads once: a cell's corner offsets
+// and neighbour codes, a tile's halo tables, the update base (the stencil offsets
+// and the state are read again as halo values of the neighbouring tiles and stay
+// ordinary loads).
 typedef float float2v __attribute__((ext_vector_type(2)));
 typedef unsigned uint2v __attribute__((ext_vector_type(2)));
 template <class V>
 __device__ inline V ldn(const void *base, uint32_t off) {
     return __builtin_nontemporal_load((const FVLBM_GLOBAL_AS V *)((const FVLBM_GLOBAL_AS char *)base + off));
 }
+__device__ inline int ldn1(const int *p, int i) { return __builtin_nontemporal_load((const FVLBM_GLOBAL_AS int *)p + i); }
 __device__ inline const void *plane(const void *p, size_t plane_bytes, int a) {
     return static_cast<const char *>(p) + plane_bytes * (size_t)a;
 }
@@ -294,11 +296,20 @@ struct BlockI16 {
 };
 
 // Per-cell access for every storage mode.  load_cell fills f[a0..8] with the
-// deviations of cell c; store_cell writes b + inc.
-template <int STORE>
+// deviations of cell c; store_cell writes b + inc.  NT: a non-temporal load (the
+// update base, which only the cell's own tile reads), for the FP32 storages.
+template <int STORE, bool NT = false>
 __device__ inline void load_cell(const void *buf, size_t np, int c, float f[Q], const RefDev &r, int a0 = 0,
                                  int a1 = Q) {
-    if constexpr (STORE == FVLBM_STORE_I16_DEV) {
+    if constexpr (NT && (STORE == FVLBM_STORE_FP32 || STORE == FVLBM_STORE_FP32_DEV)) {
+        const uint32_t off = (uint32_t)c * 4u;
+#pragma unroll
+        for (int a = a0; a < a1; a++) {
+            const float x = __builtin_nontemporal_load(
+                (const FVLBM_GLOBAL_AS float *)((const FVLBM_GLOBAL_AS char *)plane(buf, np * 4, a) + off));
+            f[a] = STORE == FVLBM_STORE_FP32 ? x - r.fref[a] : x;
+        }
+    } else if constexpr (STORE == FVLBM_STORE_I16_DEV) {
         const float sc = BlockI16::scale(buf, np, c);
 #pragma unroll
         for (int a = a0; a < Q; a++) f[a] = BlockI16::load(buf, np, c, a, sc);
@@ -1017,8 +1028,10 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     CellFaces<NF> cf;
     uint2 ln = make_uint2(0u, 0u);
     int hraw1 = -1, hraw2 = -1;
+    // (the tile's halo tables are read once here, non-temporally; the later
+    // passes that read them again find them in L2 or the Infinity Cache)
     if (!RING)
-        hraw1 = ldg(hidx, tid < hs ? tid : 0), hraw2 = ldg(hidx, h1s + tid < hs ? h1s + tid : 0);
+        hraw1 = ldn1(hidx, tid < hs ? tid : 0), hraw2 = ldn1(hidx, h1s + tid < hs ? h1s + tid : 0);
     const int ic = valid ? i : 0;
     if (ownw) {
         load_cell<STORE>(src, np, ic, f, d.ref);
@@ -1034,7 +1047,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         geo.load(dxy, np, icb);
     }
     if (halow)
-        hraw1 = ldg(hidx, rj < hs ? rj : 0), hraw2 = ldg(hidx, h1s + rj < hs ? h1s + rj : 0);
+        hraw1 = ldn1(hidx, rj < hs ? rj : 0), hraw2 = ldn1(hidx, h1s + rj < hs ? h1s + rj : 0);
     if (SPLIT3 && halob) hraw1 = ldg(hidx, rj < hs ? rj : 0);
     const int i3 = tile * T + rj;                     // SPLIT3: this halo lane's tile cell
     const bool valid3 = SPLIT3 && (halow || halob) && i3 < n_cells;
@@ -1049,7 +1062,8 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         load_cell<STORE>(src, np, c1 >= 0 ? c1 : 0, f1, d.ref);
         hgeo.load(dxy, np, c1 >= 0 ? c1 : 0);
         load_cell<STORE>(src, np, c2 >= 0 ? c2 : 0, f2, d.ref, 1);
-        hl = ldg(halo_code, (size_t)tile * h1s + (rin && rj < h1s ? rj : 0));
+        const uint2v t = ldn<uint2v>(halo_code + (size_t)tile * h1s + (rin && rj < h1s ? rj : 0), 0u);
+        hl = make_uint2(t.x, t.y);
     }
     if (SPLIT3 && halob) {                            // the ring-1 cell's h0 and stencil
         load_cell<STORE>(src, np, c1 >= 0 ? c1 : 0, f1, d.ref, 0, 1);
@@ -1074,7 +1088,7 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
     if (ownw) {
         if (sep_base) {
             if constexpr (SPLIT3) load_set<STORE, 2>(basep, np, ic, base, d.ref);
-            else load_cell<STORE>(basep, np, ic, base, d.ref);
+            else load_cell<STORE, true>(basep, np, ic, base, d.ref);
         }
         h0 = f[0];
 #pragma unroll
