@@ -57,7 +57,12 @@ CARRY_BYTES = {"fp16dev": 12.0}
 
 def alg_bytes_per_update(nf: int, scheme: str, storage: str) -> float:
     n_rhs = 4 if scheme == "rk4" else 1
-    return STATE_VALUES[scheme] * STORE_BYTES[storage] + CARRY_BYTES.get(storage, 0.0) + n_rhs * MESH_BYTES[nf]
+    return state_bytes_per_update(scheme, storage) + n_rhs * MESH_BYTES[nf]
+
+
+def state_bytes_per_update(scheme: str, storage: str) -> float:
+    """The state part of the algorithmic bytes alone (18 s or 99 s B per cell-update)."""
+    return STATE_VALUES[scheme] * STORE_BYTES[storage] + CARRY_BYTES.get(storage, 0.0)
 
 
 def measured_traffic(workload, schedule, leg=None):
@@ -135,7 +140,8 @@ def make_solver(F, inst, scheme, storage, reorder=None):
     return mesh, s
 
 
-STREAMING_LEGS = (("euler", "fp32dev", 20), ("rk4", "fp32dev", 5), ("rk4", "i16dev", 5))
+STREAMING_LEGS = (("euler", "fp32dev", 20), ("rk4", "fp32dev", 5), ("euler", "fp16dev", 20), ("rk4", "fp16dev", 5),
+                  ("rk4", "i16dev", 5))
 
 
 def streaming(F, W, stream, schedule=None, legs=None):
@@ -158,8 +164,11 @@ def streaming(F, W, stream, schedule=None, legs=None):
         n_launch = k * (4 if scheme == "rk4" else 1)
         t_launch = el / n_launch
         alg = alg_bytes_per_update(nf, scheme, storage) / (4 if scheme == "rk4" else 1) * m.n_cells
+        state = state_bytes_per_update(scheme, storage) / (4 if scheme == "rk4" else 1) * m.n_cells
         sched = s.get_schedule()
         out[leg] = dict(cells=m.n_cells, steps=k, M_cell_updates_per_s=round(m.n_cells * k / el / 1e6, 1),
+                        M_rhs_evals_per_s=round(m.n_cells * k * (4 if scheme == "rk4" else 1) / el / 1e6, 1),
+                        state_only_frac=round(state / t_launch / 1e9 / HBM_PEAK_GBS, 4),
                         launch_ms=round(t_launch * 1e3, 4), achieved_GBs=round(alg / t_launch / 1e9, 1),
                         frac=round(alg / t_launch / 1e9 / HBM_PEAK_GBS, 4), alg_bytes_per_launch=alg,
                         traffic=measured_traffic("streaming8m", sched, leg), schedule=sched)
@@ -320,14 +329,17 @@ def single_workload(F, stream, inst, label, traffic_key, args, schedule, order=N
     alg_launch = alg_bytes_per_update(nf, "rk4", args.storage) / 4 * n
     rho, u, st = s.macros()
     sched = s.get_schedule()
+    state_launch = state_bytes_per_update("rk4", args.storage) / 4 * n
     out = dict(value=round(n * args.steps / el / 1e6, 3), ms_per_step=round(el * 1e3 / args.steps, 5),
+               M_rhs_evals_per_s=round(4 * n * args.steps / el / 1e6, 3),
                config={"workload": label, "cells": n, "scheme": "rk4", "storage": args.storage, "dt": s.dt,
                        "cell_order": order, "schedule": sched},
                roofline={"bound": "hbm", "achieved": round(alg_launch / t_launch / 1e9, 2), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(alg_launch / t_launch / 1e9 / HBM_PEAK_GBS, 4),
                          "traffic": measured_traffic(traffic_key, sched, order) if args.storage == "fp32dev" else None,
                          "kernel": f"k_tile<{nf},...> (one RK stage)",
-                         "alg_bytes_per_launch": alg_launch, "launch_us": round(t_launch * 1e6, 3)},
+                         "alg_bytes_per_launch": alg_launch, "launch_us": round(t_launch * 1e6, 3),
+                         "state_only_frac": round(state_launch / t_launch / 1e9 / HBM_PEAK_GBS, 4)},
                check={"max_u": float(np.abs(u).max()), "mass": st["mass"]})
     s.close(); mesh.close()
     return out
@@ -377,6 +389,7 @@ def main():
             "steps": args.steps,
             "warmup": args.warmup,
             "ms_per_step": h["ms_per_step"],
+            "M_rhs_evals_per_s": h["M_rhs_evals_per_s"],
             "higher_is_better": True,
             "scaling": "weak",
             "vs_baseline": None,
