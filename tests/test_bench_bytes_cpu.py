@@ -1,4 +1,5 @@
-"""The algorithmic bytes per cell-update that the benchmark's roofline divides by.
+"""The algorithmic bytes per cell-update that the benchmark's roofline divides by,
+and the gating of its measured-traffic field.
 
 They count the state a step must read and write plus one read of a compact mesh
 description per RHS evaluation (60 B per triangle: three neighbour indices, 1/A,
@@ -8,7 +9,9 @@ state part is 18 values per Euler step (read f, write f) and 99 per four-stage
 RK step (the first stage reads f and writes a stage, the other three also read
 the step's base f): 18 + 3 x 27.
 """
+import hashlib
 import importlib.util
+import json
 import os
 
 import pytest
@@ -54,3 +57,25 @@ def test_state_only_bytes(bench):
     assert bench.state_bytes_per_update("euler", "fp32dev") == 72
     assert bench.state_bytes_per_update("rk4", "fp32dev") == 396
     assert bench.state_bytes_per_update("rk4", "fp16dev") == 198 + 12
+
+
+def test_traffic_is_reported_only_for_profiled_sources_and_schedules(bench, tmp_path, monkeypatch):
+    """`roofline.traffic` comes from committed counter runs; a record whose sources
+    no longer hash to the profiled ones, or a schedule it does not hold, gives None."""
+    src = tmp_path / "kernel.hip"
+    src.write_text("// a kernel\n")
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rec = {"sources": ["kernel.hip"], "source_sha256": sha,
+           "per_schedule": {"hilbert:128,1,2": {"bytes_per_launch": 123},
+                            "rk4_fp32dev:256,1,0": {"bytes_per_launch": 456}}}
+    (prof / "k_tile_traffic_w.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    sched = {"block": 128, "xcd_remap": True, "persistent": 2}
+    assert bench.measured_traffic("w", sched, "hilbert") == 123
+    assert bench.measured_traffic("w", {"block": 256, "xcd_remap": True, "persistent": 0}, "rk4_fp32dev") == 456
+    assert bench.measured_traffic("w", dict(sched, xcd_remap=False), "hilbert") is None      # not profiled
+    assert bench.measured_traffic("absent", sched, "hilbert") is None
+    src.write_text("// a changed kernel\n")
+    assert bench.measured_traffic("w", sched, "hilbert") is None                              # stale record
