@@ -198,16 +198,21 @@ oracle_t *orc_create(int n_nodes, const double *xy, int n_cells, const int *cell
     o->rhs_prev = (double *)calloc((size_t)N * Q, sizeof(double));
     for (int i = 0; i < NS; i++) { o->nbr[i] = -1; o->grp[i] = -1; }
 
-    /* cell geometry: shoelace area and area centroid (Section 2.2), bbox extents */
+    /* cell geometry: shoelace area and area centroid (Section 2.2), bbox extents.
+     * The corners are taken relative to the cell's first node (ox, oy): the same
+     * area and centroid in exact arithmetic, but the cross products then scale
+     * with the cell's size rather than its distance from the origin, which for a
+     * small cell far from the origin would cancel away most of their digits. */
     for (int c = 0; c < N; c++) {
         int p0 = cell_ptr[c], m = cell_ptr[c + 1] - p0;
         if (m < 3 || m > MAXF) { set_err(err, errlen, "cell with fewer than 3 or more than 8 nodes"); orc_destroy(o); return NULL; }
         o->nf[c] = m;
         double a2 = 0, sx = 0, sy = 0;
         double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+        const double ox = xy[2 * cell_nodes[p0]], oy = xy[2 * cell_nodes[p0] + 1];
         for (int k = 0; k < m; k++) {
             int na = cell_nodes[p0 + k], nb = cell_nodes[p0 + (k + 1) % m];
-            double xa = xy[2 * na], ya = xy[2 * na + 1], xb = xy[2 * nb], yb = xy[2 * nb + 1];
+            double xa = xy[2 * na] - ox, ya = xy[2 * na + 1] - oy, xb = xy[2 * nb] - ox, yb = xy[2 * nb + 1] - oy;
             double cr = xa * yb - xb * ya;
             a2 += cr;
             sx += (xa + xb) * cr;
@@ -219,8 +224,8 @@ oracle_t *orc_create(int n_nodes, const double *xy, int n_cells, const int *cell
         }
         if (!(a2 > 0)) { set_err(err, errlen, "cell with non-positive area (not CCW)"); orc_destroy(o); return NULL; }
         o->area[c] = 0.5 * a2;
-        o->cx[c] = sx / (3.0 * a2);
-        o->cy[c] = sy / (3.0 * a2);
+        o->cx[c] = ox + sx / (3.0 * a2);
+        o->cy[c] = oy + sy / (3.0 * a2);
         o->lx[c] = xmax - xmin;
         o->ly[c] = ymax - ymin;
         for (int k = 0; k < m; k++) {

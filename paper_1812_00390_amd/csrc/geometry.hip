@@ -22,11 +22,15 @@ __global__ void k_cell_geometry(int n, int nf, const int *__restrict__ ncorner,
     if (i >= n) return;
     int m = ncorner[i];
     const double *p = xy + (size_t)i * nf * 2;
+    // corners relative to corner 0: the cross products then carry the cell's
+    // size, not its distance from the origin (a cell of 1e-5 at x = 1 would
+    // otherwise keep only about seven digits of its area and centroid)
+    const double bx = p[0], by = p[1];
     double a2 = 0, sx = 0, sy = 0;
-    double x0 = p[0], x1 = p[0], y0 = p[1], y1 = p[1];
+    double x0 = 0, x1 = 0, y0 = 0, y1 = 0;
     for (int k = 0; k < m; k++) {
         int k1 = (k + 1 == m) ? 0 : k + 1;
-        double xa = p[2 * k], ya = p[2 * k + 1], xb = p[2 * k1], yb = p[2 * k1 + 1];
+        double xa = p[2 * k] - bx, ya = p[2 * k + 1] - by, xb = p[2 * k1] - bx, yb = p[2 * k1 + 1] - by;
         double cr = __dmul_rn(xa, yb) - __dmul_rn(xb, ya);
         a2 += cr;
         sx += (xa + xb) * cr;
@@ -35,8 +39,8 @@ __global__ void k_cell_geometry(int n, int nf, const int *__restrict__ ncorner,
         y0 = fmin(y0, ya); y1 = fmax(y1, ya);
     }
     area[i] = 0.5 * a2;
-    cen[2 * i] = sx / (3.0 * a2);
-    cen[2 * i + 1] = sy / (3.0 * a2);
+    cen[2 * i] = bx + sx / (3.0 * a2);
+    cen[2 * i + 1] = by + sy / (3.0 * a2);
     cfl_len[i] = 0.5 * a2 / ((x1 - x0) + (y1 - y0));
 }
 

@@ -192,5 +192,7 @@ def test_batched_workload_full_size_vs_stored_oracle(F):
         err = np.abs(u[ref[f"idx_{k}"]] - ref[f"u_{k}"]).max() / U
         worst = max(worst, err)
         assert err <= 1e-3, (k, err)
-        assert np.abs(rho[ref[f"idx_{k}"]] - ref[f"rho_{k}"]).max() <= 1e-4
+        # density: the velocity target through the acoustic relation d rho = d u / c_s
+        # (c_s^2 = 1/3 in the equilibrium, Eq. 3), sqrt(3) 1e-3 U, rounded up
+        assert np.abs(rho[ref[f"idx_{k}"]] - ref[f"rho_{k}"]).max() <= 2e-4
     print(f"batched 64 instances fp16dev 1000 steps: worst max|u-u_oracle|/U = {worst:.3e}, schedule {b.get_schedule()}")

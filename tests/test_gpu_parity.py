@@ -59,6 +59,13 @@ def _rhs_scale(O, o, f, tau):
     return math.sqrt(2) * H * perim + 2 * H / tau
 
 
+def _shrunk(m, scale, shift):
+    """The mesh with its nodes scaled and moved: cells far smaller than their distance
+    from the origin (the geometry must be formed relative to each cell)."""
+    return mg.RawMesh(m.nodes * scale + np.asarray(shift, float), m.cell_ptr, m.cell_nodes, m.bface_nodes,
+                      m.bface_group, m.groups, m.periodic, m.periodic_shift, name=m.name + "_shrunk")
+
+
 RHS_MESHES = {
     "couette_quad": (lambda: mg.couette(16, 16), 0.8),
     "cavity_tri_ragged": (lambda: mg.cavity(n=13, jitter=0.2, seed=1), 0.003),
@@ -71,6 +78,8 @@ RHS_MESHES = {
     "pbox_single_cell": (lambda: mg.periodic_box(1, 1, jitter=0.0, tri=False), 0.05),
     "pbox_2x2": (lambda: mg.periodic_box(2, 2, jitter=0.0, tri=True), 0.05),
     "hybrid": (lambda: mg.hybrid(12), 0.003),
+    "cavity_tri_tiny_far": (lambda: _shrunk(mg.cavity(n=8, jitter=0.25, seed=6), 1e-5, (1.0, 1.0)), 0.003),
+    "cavity_quad_tiny_far": (lambda: _shrunk(mg.cavity(n=6, jitter=0.2, seed=7, tri=False), 1e-4, (1e3, -2e3)), 0.003),
 }
 
 
@@ -511,6 +520,70 @@ def test_streaming_size_mesh_invariants(F):
     rho, u, st = s.macros()
     assert np.abs(u).max() < 1e-7
     assert abs(st["mass"] - st0["mass"]) / st0["mass"] < 1e-7
+
+
+# the streaming legs' launch configurations (tile size, XCD remap, launch form) that
+# the benchmark's autotuner has picked on this mesh
+STREAMING_SCHEDULES = [(256, True, 0), (512, True, 1), (512, False, 0), (512, True, 0)]
+
+
+def test_streaming_size_euler_step_vs_oracle_in_bench_configs(F, O):
+    """8.4M triangles in the benchmark's streaming launch configurations: one
+    Euler step from a smooth seeded state, every cell's increment against the
+    FP64 oracle's dt RHS at the stored state, and the steps bitwise equal."""
+    m = mg.streaming_cavity(2048)
+    tau = 3e-5
+    o = O.Oracle(m, tau=tau, cfl=0.5, u_ref=0.1, scheme="euler")
+    f, _, _ = _smooth_state(O, o, seed=5)
+    _, _, w = O.lattice()
+    mesh = F.Mesh(m, reorder=F.REORDER_BISECT)
+    first = ref = f0 = tol = None
+    for schedule in STREAMING_SCHEDULES:
+        print(f"streaming Euler step, schedule {schedule}", flush=True)
+        s = F.Solver(mesh, F.make_params(tau=tau, dt=o.dt, scheme="euler", storage="fp32dev"))
+        s.set_schedule(*schedule)
+        assert s.get_schedule()["block"] == schedule[0]
+        s.f = f
+        if ref is None:
+            f0 = s.f                                   # the stored state, which both sides evaluate
+            ref = o.rhs(f0)
+        s.step(1)
+        f1 = s.f
+        if first is None:
+            first = f1
+            # the kernel's FP32 error (as for one RHS), plus the rounding of the stored
+            # deviations f - w (a dithered ulp each) divided by dt
+            dev = np.maximum(np.abs(f0 - w[None, :]), np.abs(f1 - w[None, :])).max(axis=1)
+            tol = 64 * EPS32 * _rhs_scale(O, o, f, tau) + 4 * EPS32 * dev / o.dt
+            err = np.abs((f1 - f0) / o.dt - ref).max(axis=1)
+            assert np.all(err <= tol), (err.max(), tol[np.argmax(err / tol)])
+            assert np.abs(f1 - f0).max() > 0
+        else:
+            assert np.array_equal(f1, first), schedule
+        s.close()
+    mesh.close()
+
+
+@pytest.mark.parametrize("storage", ["fp16dev", "i16dev"])
+def test_streaming_size_16bit_rk4_step_in_bench_configs(F, storage):
+    """The 16-bit streaming legs at 8.4M triangles: one RK4 step bitwise the same in
+    both tile sizes the autotuner picks, finite, and mass conserved in the closed cavity."""
+    m = mg.streaming_cavity(2048)
+    mesh = F.Mesh(m, reorder=F.REORDER_BISECT)
+    outs = []
+    for schedule in [(256, True, 0), (512, True, 0)]:
+        print(f"streaming RK4 step {storage}, schedule {schedule}", flush=True)
+        s = F.Solver(mesh, F.make_params(tau=3e-5, scheme="rk4", storage=storage))
+        s.set_schedule(*schedule)
+        m0 = s.stats()["mass"]
+        s.step(1)
+        _, u, st = s.macros()
+        assert np.all(np.isfinite(u)) and np.abs(u).max() > 0      # the lid moves the fluid
+        assert abs(st["mass"] - m0) <= 1e-8 * m0
+        outs.append(s.f)
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    mesh.close()
 
 
 @pytest.mark.parametrize("storage", ["fp32dev", "i16dev"])

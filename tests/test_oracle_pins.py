@@ -149,6 +149,46 @@ def test_quad_centroid_is_area_centroid(oracle_mod):
     assert np.abs(g["cx"] - v[:, :, 0].mean(1)).max() > 1e-6
 
 
+def _shrunk_copy(m, scale, shift):
+    """The same mesh with its nodes scaled by `scale` and moved by `shift`."""
+    return mg.RawMesh(m.nodes * scale + np.asarray(shift, float), m.cell_ptr, m.cell_nodes, m.bface_nodes,
+                      m.bface_group, m.groups, m.periodic, m.periodic_shift, name=m.name + "_shrunk")
+
+
+@pytest.mark.parametrize("tri", [True, False])
+@pytest.mark.parametrize("scale,shift", [(1e-5, (1.0, 1.0)), (1e-4, (1e3, -2e3))])
+def test_small_cells_far_from_the_origin(oracle_mod, tri, scale, shift):
+    """The area and area centroid (Section 2.2) of cells much smaller than their
+    distance from the origin (the wall cells of a strongly graded fine mesh).
+    They must be what the cell's own size allows: the area to rounding, the
+    centroid to a few units in the last place of its coordinates.  The plain
+    shoelace in absolute coordinates fails this: its cross products are of the
+    coordinates' size and cancel to the cell's."""
+    base = mg.cavity(n=6, jitter=0.25, seed=5, tri=tri)
+    m = _shrunk_copy(base, scale, shift)
+    o = oracle_mod.Oracle(m, tau=0.1, dt=1e-12)
+    g = o.geometry()
+    k = 3 if tri else 4
+    v = m.nodes[m.cell_nodes.reshape(-1, k)]
+    rel = v - v[:, :1, :]                        # corners relative to the first (exact here)
+    def tri_area(a, b, c):
+        return 0.5 * ((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (c[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1]))
+    if tri:
+        area = tri_area(rel[:, 0], rel[:, 1], rel[:, 2])
+        cen = v[:, 0] + rel.sum(axis=1) / 3
+    else:
+        A1, A2 = tri_area(rel[:, 0], rel[:, 1], rel[:, 2]), tri_area(rel[:, 0], rel[:, 2], rel[:, 3])
+        c1, c2 = (rel[:, 1] + rel[:, 2]) / 3, (rel[:, 2] + rel[:, 3]) / 3
+        area = A1 + A2
+        cen = v[:, 0] + (A1[:, None] * c1 + A2[:, None] * c2) / area[:, None]
+    assert np.all(area > 0)
+    assert np.abs(g["area"] / area - 1).max() <= 1e-12
+    ulp = np.spacing(np.abs(np.asarray(shift, float)).max() + 1.0)
+    assert np.abs(g["cx"] - cen[:, 0]).max() <= 4 * ulp
+    assert np.abs(g["cy"] - cen[:, 1]).max() <= 4 * ulp
+    assert g["area"].sum() == pytest.approx(scale * scale, rel=1e-10)
+
+
 def test_total_area(oracle_mod):
     for m, exact in [(mg.cavity(n=20, seed=1), 1.0), (mg.couette(8, 8), 1.0),
                      (mg.channel(10, 5, Lx=2.0), 2.0)]:
