@@ -564,6 +564,42 @@ def test_streaming_size_euler_step_vs_oracle_in_bench_configs(F, O):
     mesh.close()
 
 
+def test_streaming_size_rk4_step_vs_oracle(F, O):
+    """8.4M triangles: one four-stage RK step (stages 2-4 read the step's base as well
+    as the stage state) in two of the benchmark's launch configurations, bitwise the
+    same, and every cell against the oracle's FP64 RK step from the same stored state."""
+    m = mg.streaming_cavity(2048)
+    tau = 3e-5
+    o = O.Oracle(m, tau=tau, cfl=0.5, u_ref=0.1, scheme="rk4")
+    f, _, _ = _smooth_state(O, o, seed=6)
+    _, _, w = O.lattice()
+    mesh = F.Mesh(m, reorder=F.REORDER_BISECT)
+    outs = []
+    for schedule in [(256, True, 0), (512, True, 1)]:
+        print(f"streaming RK4 step, schedule {schedule}", flush=True)
+        s = F.Solver(mesh, F.make_params(tau=tau, dt=o.dt, scheme="rk4", storage="fp32dev"))
+        s.set_schedule(*schedule)
+        s.f = f
+        if not outs:
+            f0 = s.f
+        s.step(1)
+        outs.append(s.f)
+        s.close()
+    mesh.close()
+    assert np.array_equal(outs[0], outs[1])
+    o.f = f0
+    o.step(1)
+    ref = o.f
+    f1 = outs[0]
+    # four stages of the one-RHS bound, each scaled by its coefficient (at most dt),
+    # and the rounding of four stored stage values
+    dev = np.maximum(np.abs(f0 - w[None, :]), np.abs(f1 - w[None, :])).max(axis=1)
+    tol = 4 * o.dt * 64 * EPS32 * _rhs_scale(O, o, f, tau) + 16 * EPS32 * dev
+    err = np.abs(f1 - ref).max(axis=1)
+    assert np.all(err <= tol), (err.max(), tol[np.argmax(err / tol)])
+    assert np.abs(f1 - f0).max() > 10 * err.max()
+
+
 @pytest.mark.parametrize("storage", ["fp16dev", "i16dev"])
 def test_streaming_size_16bit_rk4_step_in_bench_configs(F, storage):
     """The 16-bit streaming legs at 8.4M triangles: one RK4 step bitwise the same in
