@@ -361,7 +361,7 @@ def main():
                     help="cell order of the headline mesh (default: the workload's, Hilbert for the cylinder O-grid)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no multi-GPU path; "
               "the design notes describe how the step would shard.", file=sys.stderr)
         sys.exit(2)
 

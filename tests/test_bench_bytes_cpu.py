@@ -79,3 +79,14 @@ def test_traffic_is_reported_only_for_profiled_sources_and_schedules(bench, tmp_
     assert bench.measured_traffic("absent", sched, "hilbert") is None
     src.write_text("// a changed kernel\n")
     assert bench.measured_traffic("w", sched, "hilbert") is None                              # stale record
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; asked for more it says so and exits non-zero
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
