@@ -556,6 +556,7 @@ def test_streaming_size_euler_step_vs_oracle_in_bench_configs(F, O):
             dev = np.maximum(np.abs(f0 - w[None, :]), np.abs(f1 - w[None, :])).max(axis=1)
             tol = 64 * EPS32 * _rhs_scale(O, o, f, tau) + 4 * EPS32 * dev / o.dt
             err = np.abs((f1 - f0) / o.dt - ref).max(axis=1)
+            print(f"  worst cell at {(err / tol).max():.3f} of its bound", flush=True)
             assert np.all(err <= tol), (err.max(), tol[np.argmax(err / tol)])
             assert np.abs(f1 - f0).max() > 0
         else:
@@ -596,6 +597,7 @@ def test_streaming_size_rk4_step_vs_oracle(F, O):
     dev = np.maximum(np.abs(f0 - w[None, :]), np.abs(f1 - w[None, :])).max(axis=1)
     tol = 4 * o.dt * 64 * EPS32 * _rhs_scale(O, o, f, tau) + 16 * EPS32 * dev
     err = np.abs(f1 - ref).max(axis=1)
+    print(f"  worst cell at {(err / tol).max():.3f} of its bound", flush=True)
     assert np.all(err <= tol), (err.max(), tol[np.argmax(err / tol)])
     assert np.abs(f1 - f0).max() > 10 * err.max()
 
