@@ -85,3 +85,33 @@ def test_null_arguments():
     assert L.fvlbm_batch_create(None, 0, None) == -1
     L.fvlbm_solver_destroy(None); L.fvlbm_mesh_destroy(None); L.fvlbm_batch_destroy(None)
     assert b"bad arguments" in L.fvlbm_last_error()
+
+
+def test_rejects_empty_and_degenerate_meshes():
+    """No cells, no nodes, a cell of two corners or of more corners than a cell may
+    have, a corner index out of range, a zero-area (collinear) triangle: each is an
+    argument or mesh error, raised before any device call."""
+    m = mg.cavity(n=2, jitter=0.0)
+    empty = mg.RawMesh(m.nodes, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros((0, 2), np.int32),
+                       np.zeros(0, np.int32), m.groups, np.zeros((0, 2), np.int32), np.zeros((0, 2)), name="empty")
+    _raises_status(lambda: F.Mesh(empty, stream=0), -1)
+    no_nodes = mg.RawMesh(np.zeros((0, 2)), m.cell_ptr, m.cell_nodes, m.bface_nodes, m.bface_group, m.groups,
+                          m.periodic, m.periodic_shift, name="no_nodes")
+    _raises_status(lambda: F.Mesh(no_nodes, stream=0), -1)
+    for ptr, nodes_of in ((np.array([0, 2], np.int32), np.array([0, 1], np.int32)),
+                          (np.array([0, 5], np.int32), np.array([0, 1, 4, 3, 2], np.int32))):
+        bad = mg.RawMesh(m.nodes, ptr, nodes_of, m.bface_nodes, m.bface_group, m.groups, m.periodic,
+                         m.periodic_shift, name="bad_polygon")
+        with pytest.raises(F.FvlbmError):
+            F.Mesh(bad, stream=0)
+    out_of_range = mg.cavity(n=2, jitter=0.0)
+    out_of_range.cell_nodes = out_of_range.cell_nodes.copy()
+    out_of_range.cell_nodes[0] = out_of_range.n_nodes + 3
+    with pytest.raises(F.FvlbmError):
+        F.Mesh(out_of_range, stream=0)
+    flat = mg.cavity(n=2, jitter=0.0)
+    nodes = flat.nodes.copy()
+    a, b, c = flat.cell_nodes[:3]
+    nodes[c] = 0.5 * (nodes[a] + nodes[b])          # the first triangle's third corner on its first edge
+    flat.nodes = nodes
+    _raises_status(lambda: F.Mesh(flat, stream=0), -2)
