@@ -272,11 +272,12 @@ void fvlbm_batch_destroy(fvlbm_batch *b);
  * queue lives with the solver's or batch's tile tables and every launch leaves
  * it cleared, so launches of one solver or batch must stay ordered on its
  * stream (as the library issues them); 2 one workgroup per tile with one
- * more wave that loads the tile's halo and forms the ring-1 gradients beside
+ * more wave (two when the larger halo ring of any tile holds more than 64
+ * cells) that loads the tile's halo and forms the ring-1 gradients beside
  * the tile's own (single solvers, tiles of 64 or 128 cells, Euler and RK
  * stages; elsewhere it acts as 0); with 64-cell tiles and per-value storage
  * two more waves take half of each cell's directions, so a workgroup runs four
- * waves of 64.  A batch takes 0 or 1.  A schedule never
+ * waves of 64 (one halo wave).  A batch takes 0 or 1.  A schedule never
  * changes the per-cell arithmetic: results are bitwise identical under every
  * schedule.
  * Errors: FVLBM_E_ARG (unsupported tile size, or tile plus halo do not fit
