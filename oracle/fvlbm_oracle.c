@@ -25,7 +25,8 @@
  *
  * Readings where the paper is silent or garbled (each also listed in the
  * design notes):
- *  - f lives at the polygon's area centroid (Section 2.2).
+ *  - f lives at the polygon's area centroid (Section 2.2); area and centroid
+ *    are formed on the corners relative to the cell's first corner.
  *  - The least-squares stencil is the face neighbours; a wall face contributes
  *    its midpoint P with value f_P; inlet/outlet/symmetry faces contribute a
  *    ghost at the mirror image of the cell centre across the face line;
