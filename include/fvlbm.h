@@ -41,7 +41,8 @@ typedef enum {
     FVLBM_E_NOMEM = -4,    /* device allocation failed */
     FVLBM_E_DEVICE = -5,   /* a HIP runtime call or kernel failed */
     FVLBM_E_DIVERGED = -6, /* a non-finite density or velocity was found (fvlbm_macros) */
-    FVLBM_E_STATE = -7     /* the solver is in an error state; destroy it */
+    FVLBM_E_STATE = -7     /* the call does not fit the object's state (a solver in an error state:
+                              destroy it; the last member of a batch) */
 } fvlbm_status;
 
 /* Boundary-condition kinds, Section 2.4 (Eqs. 18-26). */
@@ -252,6 +253,15 @@ fvlbm_status fvlbm_batch_residuals(fvlbm_batch *b, double *out);
  * tiles do not fit the LDS at the batch's tile size), FVLBM_E_PARAM, FVLBM_E_NOMEM,
  * FVLBM_E_DEVICE; on error the batch keeps its old members. */
 fvlbm_status fvlbm_batch_set_members(fvlbm_batch *b, fvlbm_solver *const *solvers, int32_t n);
+/* Remove one member from a batch (a request that has finished): the batch keeps its
+ * other members in their order and its graphs, re-pointed as by
+ * fvlbm_batch_set_members, which this call is a shorthand for.  The solver itself
+ * is not destroyed; it can be stepped alone or joined to a batch again.
+ * Synchronizes the batch's stream.  Errors: FVLBM_E_ARG (null arguments, or the
+ * solver is not a member), FVLBM_E_STATE (it is the last member: destroy the
+ * batch instead), and those of fvlbm_batch_set_members; on error the batch keeps
+ * its members. */
+fvlbm_status fvlbm_batch_remove(fvlbm_batch *b, fvlbm_solver *s);
 /* How many graphs the batch has instantiated, and how many times a membership
  * change re-pointed an instantiated graph instead (fvlbm_batch_set_members).
  * Errors: FVLBM_E_ARG. */

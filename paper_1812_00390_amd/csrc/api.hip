@@ -962,6 +962,17 @@ fvlbm_status fvlbm_batch_set_members(fvlbm_batch *b, fvlbm_solver *const *solver
     return FVLBM_OK;
 }
 
+fvlbm_status fvlbm_batch_remove(fvlbm_batch *b, fvlbm_solver *s) {
+    if (!b || !s) return fail(FVLBM_E_ARG, "bad arguments to fvlbm_batch_remove");
+    std::vector<fvlbm_solver *> keep;
+    keep.reserve(b->members.size());
+    for (fvlbm_solver *m : b->members)
+        if (m != s) keep.push_back(m);
+    if (keep.size() == b->members.size()) return fail(FVLBM_E_ARG, "the solver is not a member of the batch");
+    if (keep.empty()) return fail(FVLBM_E_STATE, "cannot remove the last member of a batch (destroy the batch)");
+    return fvlbm_batch_set_members(b, keep.data(), (int32_t)keep.size());
+}
+
 fvlbm_status fvlbm_batch_graph_counts(const fvlbm_batch *b, int64_t *built, int64_t *repointed) {
     if (!b || !built || !repointed) return fail(FVLBM_E_ARG, "null argument");
     *built = b->graph_builds;

@@ -81,6 +81,7 @@ SIGNATURES = {
     "fvlbm_batch_get_schedule": (C.c_int, [_vp, _ip, _ip, _ip]),
     "fvlbm_batch_residuals": (C.c_int, [_vp, _dp]),
     "fvlbm_batch_set_members": (C.c_int, [_vp, C.POINTER(_vp), C.c_int32]),
+    "fvlbm_batch_remove": (C.c_int, [_vp, _vp]),
     "fvlbm_batch_graph_counts": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "fvlbm_set_stream": (C.c_int, [_vp, _vp]),
     "fvlbm_autotune": (C.c_int, [_vp, C.c_int32, _dp]),
@@ -351,6 +352,11 @@ class Batch:
         arr = (C.c_void_p * len(solvers))(*[s.h.value for s in solvers])
         _check(lib().fvlbm_batch_set_members(self.h, arr, len(solvers)))
         self.solvers = solvers
+
+    def remove(self, solver: Solver):
+        """Remove one member (fvlbm_batch_remove); the others keep their order and the graphs."""
+        _check(lib().fvlbm_batch_remove(self.h, solver.h))
+        self.solvers = [s for s in self.solvers if s is not solver]
 
     def graph_counts(self) -> dict:
         """Graphs instantiated so far, and graphs re-pointed by membership changes."""

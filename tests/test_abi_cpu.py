@@ -83,6 +83,7 @@ def test_null_arguments():
     assert L.fvlbm_mesh_cfl_length(None) == -1.0
     assert L.fvlbm_solver_dt(None) == -1.0
     assert L.fvlbm_batch_create(None, 0, None) == -1
+    assert L.fvlbm_batch_remove(None, None) == -1
     L.fvlbm_solver_destroy(None); L.fvlbm_mesh_destroy(None); L.fvlbm_batch_destroy(None)
     assert b"bad arguments" in L.fvlbm_last_error()
 

@@ -126,3 +126,32 @@ def test_member_destroyed_in_the_batch_is_freed_when_it_leaves(F):
     b.step(8)
     assert S[0].stats()["steps"] == 16 and S[2].stats()["steps"] == 16
     b.close()
+
+
+def test_remove_one_member(F):
+    """fvlbm_batch_remove: the others go on bitwise as alone, with the graphs re-pointed
+    while the batch keeps its cell kinds; the removed solver steps on alone; a
+    non-member or the last member is refused and leaves the batch as it was."""
+    alone, mixed = _pairs(F, "fp32dev")
+    S = [s for _, s in mixed]                           # 0, 2, 5 triangles; 1 quadrilaterals
+    b = F.Batch([S[0], S[1], S[2], S[5]])
+    b.step(16)
+    before = b.graph_counts()["repointed"]
+    b.remove(S[2])                                      # both cell kinds stay: graphs re-pointed
+    assert b.graph_counts()["repointed"] > before
+    assert [s.h.value for s in b.solvers] == [S[0].h.value, S[1].h.value, S[5].h.value]
+    b.step(8)
+    S[2].step(8)                                        # on its own again
+    with pytest.raises(F.FvlbmError) as e:
+        b.remove(S[3])                                  # never a member
+    assert e.value.status == -1
+    b.remove(S[0]); b.remove(S[5])
+    with pytest.raises(F.FvlbmError) as e:
+        b.remove(S[1])                                  # the last member
+    assert e.value.status == -7
+    b.step(8)                                           # S[1] alone in the batch
+    for k, n in ((0, 24), (1, 32), (2, 24), (5, 24)):
+        alone[k][1].step(n)
+        assert S[k].stats()["steps"] == n
+        assert np.array_equal(alone[k][1].f, S[k].f), k
+    b.close()
