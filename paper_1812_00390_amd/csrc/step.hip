@@ -1152,6 +1152,24 @@ __device__ __forceinline__ void tile_body(const InstDesc *__restrict__ descs, in
         wr_f(B + k * RB, 1, g);
     }
     asm volatile("" ::"s"(warm0), "s"(warm1));    // (keeps the two reads above)
+    if constexpr (RING && !SPLIT3) {
+        // Waves with a boundary face among their cells (own or ring-1) carry the
+        // longest phase-2 and phase-3 chains, and their tiles end the launch: they
+        // issue first on their SIMD.  (Measured: 1.4 % off the 128-cell ring form's
+        // launch on a cylinder O-grid; the same test cost the split form and the
+        // one-workgroup-per-tile forms about 1 %, so they do without it.)
+        bool bnd = false;
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < NF; k++) bnd = bnd || (code[k] < 0 && code[k] >= PAD_BELOW);
+        }
+        if (c1 >= 0) {
+#pragma unroll
+            for (int k = 0; k < NF; k++) bnd = bnd || (hcode[k] < 0 && hcode[k] >= PAD_BELOW);
+        }
+        if (__builtin_amdgcn_ballot_w64(bnd) != 0) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(0);
+    }
     __syncthreads();
     if constexpr (SPLIT3) {
         // the other waves' phase-3 cells: their geometry from the tile's wave,
